@@ -1,0 +1,1073 @@
+/*
+ * twk_ref.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * Slow, single-threaded, written to be checked by eye against the paper:
+ *   Wang, Wang & Dong, "Twinkle: A GPU-based binary-lens microlensing code
+ *   with contour integration method", arXiv 2501.03322.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  It shares no code with the HIP path.
+ *
+ * Every floating-point quantity is IEEE binary64.  Build with
+ * -ffp-contract=off so that no operation is fused behind the reader's back.
+ *
+ * Readings of passages that the paper leaves ambiguous or garbled are marked
+ * "READING" below; each one is listed with its justification in the design
+ * notes of the repository.
+ *
+ * Parity pins (what fixes each part independently of this code) live in the
+ * test suite: symbolic re-derivation of the quintic, LAPACK companion roots,
+ * the zero residual-sum identity, the Paczynski and Witt-Mao closed forms,
+ * finite differences of the limb derivatives, and inverse ray shooting.
+ */
+#include "twk_ref.h"
+
+#include <complex.h>
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define PI_D 3.14159265358979323846
+
+/* ------------------------------------------------------------------ */
+/* Lens set-up: Sec. 2.1 (lens equation and binary positions).          */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  double s, q;
+  double m1, m2; /* masses normalised by the total mass            */
+  double z1, z2; /* lens positions on the real axis, CM frame       */
+} lens_t;
+
+static lens_t lens_make(double s, double q) {
+  lens_t L;
+  L.s = s;
+  L.q = q;
+  L.m1 = 1.0 / (1.0 + q);
+  L.m2 = q / (1.0 + q);
+  L.z1 = -q * s / (1.0 + q);
+  L.z2 = s / (1.0 + q);
+  return L;
+}
+
+static int lens_ok(double s, double q) {
+  return isfinite(s) && isfinite(q) && s > 0.0 && q > 0.0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Coefficients: Sec. 2.2, Eq. method-transformed (refined form).       */
+/* y = zeta - z2 is the source in the lens-2 frame; lens 1 is at -s.    */
+/* "Im(y) i" is the purely imaginary number i*Im(y); Re(.) of v_p, v_c  */
+/* and 1 - s y are real parts.                                           */
+/* ------------------------------------------------------------------ */
+static void coeffs_refined(const lens_t *L, cplx y, cplx c[6]) {
+  const double s = L->s, m2 = L->m2;
+  const cplx yb = conj(y);
+  const double yr = creal(y), yi = cimag(y);
+  const cplx iy = CMPLX(0.0, yi);   /* Im(y) i           */
+  const cplx vc = yb + s;           /* v_c = conj(y) + s */
+  const cplx vp = 1.0 + s * yb;     /* v_p = 1 + s conj(y) */
+  const double re_vp = 1.0 + s * yr;
+  const double re_vc = yr + s;
+  const double re_1sy = 1.0 - s * yr;
+
+  c[5] = -yb * vc;
+  c[4] = (yb * y - 1.0 - 2.0 * s * yb) * vc + m2 * s;
+  c[3] = (2.0 * y - s) * (vp * vc + 2.0 * iy - m2 * s) + 4.0 * (m2 * s - y) * iy;
+  c[2] = re_vp * re_vp * re_vc + CMPLX(0.0, yi * re_vp * re_1sy) +
+         s * yi * yi * (2.0 + s * vc) +
+         m2 * s * (2.0 * yb * (y - s) - (1.0 - s * y));
+  c[1] = m2 * s * ((s + 2.0 * y) * vp + s * (2.0 * s * iy - m2));
+  c[0] = s * s * m2 * m2 * y;
+}
+
+/* Conventional form, Sec. 2.2 Eq. lens-poly-orig.  READING: the symbol `a`
+ * printed in c3 stands for -s (symbolic re-derivation of the quintic). */
+static void coeffs_conventional(const lens_t *L, cplx y, cplx c[6]) {
+  const double s = L->s, m1 = L->m1, m2 = L->m2;
+  const cplx yb = conj(y);
+  const double a = -s;
+  c[5] = -yb * (yb + s);
+  c[4] = yb * (yb * (-2.0 * s + y) - 1.0) + s * (yb * (-2.0 * s + y) - m1);
+  c[3] = 2.0 * yb * y - s * s * s * yb + s * s * (yb * (2.0 * y - yb) - m1) -
+         a * (y + 2.0 * yb * (yb * y - m2));
+  c[2] = y * (1.0 + s * s * s * yb) + s * (m1 + 2.0 * y * yb * (1.0 + m2)) +
+         s * s * (yb * (m1 - m2) + y * (1.0 + m2 + yb * yb));
+  c[1] = m2 * s * (s * (m1 + y * (2.0 * yb + s)) + 2.0 * y);
+  c[0] = s * s * m2 * m2 * y;
+}
+
+/* ------------------------------------------------------------------ */
+/* Roots: the paper uses Skowron & Gould (2012); any method that finds   */
+/* all five roots to working precision serves.  The oracle uses the      */
+/* Aberth-Ehrlich simultaneous iteration from a cold start on a circle,  */
+/* followed by Newton steps on the undeflated polynomial.                */
+/* ------------------------------------------------------------------ */
+static void horner2(const cplx c[6], cplx x, cplx *p, cplx *dp) {
+  cplx b = c[5], d = 0.0;
+  for (int k = 4; k >= 0; --k) {
+    d = d * x + b;
+    b = b * x + c[k];
+  }
+  *p = b;
+  *dp = d;
+}
+
+static int roots5(const cplx c[6], cplx r[5]) {
+  /* Fujiwara's bound on the root moduli, and the geometric mean of the
+   * moduli |c0/c5|^(1/5): start on a circle of the latter radius (clamped
+   * into the bound), which keeps the cold start near the roots. */
+  if (c[5] == 0.0) {
+    for (int k = 0; k < 5; ++k) r[k] = CMPLX(NAN, NAN);
+    return 0;
+  }
+  double bound = 0.0;
+  for (int k = 1; k <= 5; ++k) {
+    double a = cabs(c[5 - k] / c[5]);
+    if (k == 5) a *= 0.5;
+    double t = pow(a, 1.0 / k);
+    if (t > bound) bound = t;
+  }
+  bound *= 2.0;
+  double rad = pow(cabs(c[0] / c[5]), 0.2);
+  if (!(rad > 0.0) || rad > bound) rad = 0.5 * bound;
+  for (int k = 0; k < 5; ++k) {
+    double ang = 2.0 * PI_D * k / 5.0 + 0.4;
+    r[k] = rad * CMPLX(cos(ang), sin(ang));
+  }
+  int it;
+  int settled = 0;
+  for (it = 1; it <= 500; ++it) {
+    double worst = 0.0;
+    for (int k = 0; k < 5; ++k) {
+      cplx p, dp;
+      horner2(c, r[k], &p, &dp);
+      if (p == 0.0) continue;
+      cplx ratio = p / dp;
+      cplx rep = 0.0;
+      for (int j = 0; j < 5; ++j)
+        if (j != k) rep += 1.0 / (r[k] - r[j]);
+      cplx w = ratio / (1.0 - ratio * rep);
+      if (!isfinite(creal(w)) || !isfinite(cimag(w))) {
+        /* dp vanished or two iterates coincide: nudge and continue. */
+        r[k] += 1e-3 * rad * CMPLX(0.6, 0.8);
+        worst = 1.0;
+        continue;
+      }
+      r[k] -= w;
+      double rel = cabs(w) / fmax(cabs(r[k]), DBL_MIN);
+      if (rel > worst) worst = rel;
+    }
+    if (worst < 4.0 * DBL_EPSILON) {
+      if (++settled >= 2) break;
+    } else {
+      settled = 0;
+    }
+  }
+  /* Newton polish on the full polynomial, kept only if |P| decreases. */
+  for (int k = 0; k < 5; ++k) {
+    for (int pass = 0; pass < 2; ++pass) {
+      cplx p, dp;
+      horner2(c, r[k], &p, &dp);
+      if (p == 0.0 || dp == 0.0) break;
+      cplx cand = r[k] - p / dp;
+      cplx p2, dp2;
+      horner2(c, cand, &p2, &dp2);
+      if (cabs(p2) < cabs(p)) r[k] = cand;
+      else break;
+    }
+  }
+  return it;
+}
+
+/* ------------------------------------------------------------------ */
+/* Image classification.                                                 */
+/* Residual (Sec. 2.4.1): R = zeta - r + m1/(conj(r) - conj(z1))          */
+/*                            + m2/(conj(r) - conj(z2)),                  */
+/* in the lens-2 frame: R = y - eta + m1/(conj(eta) + s) + m2/conj(eta). */
+/* Jacobian (Eq. jacobian): f(z) = m1/(z1-z) + m2/(z2-z), J = 1 - |f'|^2. */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int n;            /* real images (3 or 5)                    */
+  cplx z[5];        /* lens-2 frame; real images first, ghosts last */
+  cplx R[5];        /* residuals in the same order              */
+  double J[5];      /* Jacobians in the same order               */
+  int par[5];       /* parity sign(J) for the real images        */
+  uint32_t flags;
+} images_t;
+
+static cplx residual(const lens_t *L, cplx y, cplx eta) {
+  cplx eb = conj(eta);
+  return y - eta + L->m1 / (eb + L->s) + L->m2 / eb;
+}
+
+static cplx fprime(const lens_t *L, cplx eta) {
+  /* f'(z) = m1/(z1-z)^2 + m2/(z2-z)^2 ; z1-z = -(eta+s), z2-z = -eta */
+  cplx a = eta + L->s;
+  return L->m1 / (a * a) + L->m2 / (eta * eta);
+}
+
+static cplx fsecond(const lens_t *L, cplx eta) {
+  /* f''(z) = 2 m1/(z1-z)^3 + 2 m2/(z2-z)^3 */
+  cplx a = eta + L->s;
+  return -2.0 * L->m1 / (a * a * a) - 2.0 * L->m2 / (eta * eta * eta);
+}
+
+/* READING of the residual detector (the paper states the principle only):
+ * sort |R| in decreasing order.  The two largest are a ghost pair when the
+ * second largest exceeds kgap times both the third largest and the
+ * rounding scale sigma = 64 eps (|y| + |eta| + m1/|eta+s| + m2/|eta|) of
+ * the roots with the three smallest residuals; otherwise all five are
+ * real.  Equal length of the two largest (they must be opposite, since the
+ * residuals sum to zero) is checked and a violation is flagged.  A decision
+ * margin within a factor 30 of the gap is flagged as near-degenerate. */
+static void classify(const lens_t *L, cplx y, const cplx r[5], double kgap,
+                     images_t *out) {
+  cplx R[5];
+  double aR[5], sig[5];
+  int o[5];
+  for (int k = 0; k < 5; ++k) {
+    R[k] = residual(L, y, r[k]);
+    aR[k] = cabs(R[k]);
+    sig[k] = 64.0 * DBL_EPSILON *
+             (cabs(y) + cabs(r[k]) + L->m1 / cabs(r[k] + L->s) +
+              L->m2 / cabs(r[k]));
+    o[k] = k;
+  }
+  /* insertion sort, decreasing |R|; ties keep root order */
+  for (int i = 1; i < 5; ++i) {
+    int t = o[i], j = i - 1;
+    while (j >= 0 && aR[o[j]] < aR[t]) {
+      o[j + 1] = o[j];
+      --j;
+    }
+    o[j + 1] = t;
+  }
+  double noise = aR[o[2]];
+  for (int k = 2; k < 5; ++k)
+    if (sig[o[k]] > noise) noise = sig[o[k]];
+  double margin = aR[o[1]] / noise;
+  int ghosts = margin > kgap;
+  out->flags = 0;
+  if (margin > kgap / 30.0 && margin < kgap * 30.0)
+    out->flags |= TWK_REF_FLAG_NEARDEGEN;
+  int order[5];
+  int m = 0;
+  if (ghosts) {
+    if (fabs(aR[o[0]] - aR[o[1]]) > 0.1 * aR[o[0]])
+      out->flags |= TWK_REF_FLAG_ANOMALY;
+    for (int k = 0; k < 5; ++k)
+      if (k != o[0] && k != o[1]) order[m++] = k;
+    order[m++] = o[0];
+    order[m++] = o[1];
+    out->n = 3;
+  } else {
+    for (int k = 0; k < 5; ++k) order[m++] = k;
+    out->n = 5;
+  }
+  int psum = 0;
+  for (int k = 0; k < 5; ++k) {
+    int i = order[k];
+    out->z[k] = r[i];
+    out->R[k] = R[i];
+    cplx fp = fprime(L, r[i]);
+    out->J[k] = 1.0 - creal(fp * conj(fp));
+    out->par[k] = out->J[k] > 0.0 ? 1 : -1;
+    if (k < out->n) psum += out->par[k];
+  }
+  /* Parity sum of the real images is -1 (Sec. 2.3). */
+  if (psum != -1) out->flags |= TWK_REF_FLAG_ANOMALY;
+}
+
+static void solve_point(const lens_t *L, cplx y, double kgap, images_t *im) {
+  cplx c[6], r[5];
+  coeffs_refined(L, y, c);
+  roots5(c, r);
+  classify(L, y, r, kgap, im);
+}
+
+/* ------------------------------------------------------------------ */
+/* Public: coefficients, roots, images, point magnification.             */
+/* ------------------------------------------------------------------ */
+int twk_ref_coeffs(double s, double q, double zx, double zy, double *out) {
+  if (!lens_ok(s, q) || !out) return TWK_REF_EINVAL;
+  lens_t L = lens_make(s, q);
+  cplx c[6];
+  coeffs_refined(&L, CMPLX(zx - L.z2, zy), c);
+  for (int k = 0; k < 6; ++k) {
+    out[2 * k] = creal(c[k]);
+    out[2 * k + 1] = cimag(c[k]);
+  }
+  return TWK_REF_OK;
+}
+
+int twk_ref_coeffs_conventional(double s, double q, double zx, double zy,
+                                double *out) {
+  if (!lens_ok(s, q) || !out) return TWK_REF_EINVAL;
+  lens_t L = lens_make(s, q);
+  cplx c[6];
+  coeffs_conventional(&L, CMPLX(zx - L.z2, zy), c);
+  for (int k = 0; k < 6; ++k) {
+    out[2 * k] = creal(c[k]);
+    out[2 * k + 1] = cimag(c[k]);
+  }
+  return TWK_REF_OK;
+}
+
+int twk_ref_roots(const double *c12, double *roots10) {
+  if (!c12 || !roots10) return TWK_REF_EINVAL;
+  cplx c[6], r[5];
+  for (int k = 0; k < 6; ++k) c[k] = CMPLX(c12[2 * k], c12[2 * k + 1]);
+  if (c[5] == 0.0) return TWK_REF_EINVAL;
+  int it = roots5(c, r);
+  for (int k = 0; k < 5; ++k) {
+    roots10[2 * k] = creal(r[k]);
+    roots10[2 * k + 1] = cimag(r[k]);
+  }
+  return it;
+}
+
+int twk_ref_images(double s, double q, double zx, double zy, double *img10,
+                   double *res10, double *jac5, int32_t *n_real,
+                   uint32_t *flags) {
+  if (!lens_ok(s, q) || !isfinite(zx) || !isfinite(zy)) return TWK_REF_EINVAL;
+  lens_t L = lens_make(s, q);
+  images_t im;
+  solve_point(&L, CMPLX(zx - L.z2, zy), 100.0, &im);
+  for (int k = 0; k < 5; ++k) {
+    if (img10) {
+      img10[2 * k] = creal(im.z[k]) + L.z2;
+      img10[2 * k + 1] = cimag(im.z[k]);
+    }
+    if (res10) {
+      res10[2 * k] = creal(im.R[k]);
+      res10[2 * k + 1] = cimag(im.R[k]);
+    }
+    if (jac5) jac5[k] = im.J[k];
+  }
+  if (n_real) *n_real = im.n;
+  if (flags) *flags = im.flags;
+  return TWK_REF_OK;
+}
+
+static double mu_point(const images_t *im) {
+  double mu = 0.0;
+  for (int k = 0; k < im->n; ++k) mu += 1.0 / fabs(im->J[k]);
+  return mu;
+}
+
+int twk_ref_point_mag(double s, double q, int64_t n, const double *zx,
+                      const double *zy, double *mag, int32_t *n_images,
+                      uint32_t *flags) {
+  if (!lens_ok(s, q) || n < 0 || (n > 0 && (!zx || !zy || !mag)))
+    return TWK_REF_EINVAL;
+  lens_t L = lens_make(s, q);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!isfinite(zx[i]) || !isfinite(zy[i])) {
+      mag[i] = NAN;
+      if (n_images) n_images[i] = 0;
+      if (flags) flags[i] = TWK_REF_FLAG_NONFINITE;
+      continue;
+    }
+    images_t im;
+    solve_point(&L, CMPLX(zx[i] - L.z2, zy[i]), 100.0, &im);
+    mag[i] = mu_point(&im);
+    if (n_images) n_images[i] = im.n;
+    if (flags) flags[i] = im.flags;
+  }
+  return TWK_REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Limb derivatives.  The source limb is zeta(theta) = zeta_c + rho      */
+/* e^{i theta}, counter-clockwise from +x (Sec. 2.3).  The lens equation */
+/* zeta = z + conj(f(z)) differentiated once gives                       */
+/*   zeta' = z' + conj(f') conj(z'),                                     */
+/* hence z' = (zeta' - conj(f') conj(zeta'))/J (READING of the printed    */
+/* formula, which must carry conj(f')), and differentiated twice gives   */
+/*   zeta'' = z'' + conj(f'' z'^2) + conj(f') conj(z''),                 */
+/* which the oracle solves for z'' directly.  z' ^ z'' = Im(conj(z') z''). */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  double theta;
+  images_t im;
+  cplx dz[5];   /* z' of the real images          */
+  double w[5];  /* z' ^ z'' of the real images    */
+  int n_eff;    /* real images after the slope detector */
+  int demote[2];/* indices of a pair demoted to ghosts, or -1 */
+} sample_t;
+
+static void limb_derivs(const lens_t *L, double rho, double theta,
+                        sample_t *sm) {
+  cplx e = CMPLX(cos(theta), sin(theta));
+  cplx zp = CMPLX(0.0, rho) * e; /* zeta'  = i rho e^{i theta} */
+  cplx zpp = -rho * e;           /* zeta'' = -rho e^{i theta}  */
+  for (int k = 0; k < sm->im.n; ++k) {
+    cplx eta = sm->im.z[k];
+    cplx fp = fprime(L, eta), fpp = fsecond(L, eta);
+    double J = sm->im.J[k];
+    cplx d1 = (zp - conj(fp) * conj(zp)) / J;
+    cplx g = zpp - conj(fpp * d1 * d1);
+    cplx d2 = (g - conj(fp) * conj(g)) / J;
+    sm->dz[k] = d1;
+    sm->w[k] = cimag(conj(d1) * d2);
+  }
+}
+
+int twk_ref_limb_derivs(double s, double q, double zcx, double zcy,
+                        double rho, double theta, double *img10,
+                        double *dz10, double *wedge5, int32_t *n_real) {
+  if (!lens_ok(s, q) || !(rho > 0.0)) return TWK_REF_EINVAL;
+  lens_t L = lens_make(s, q);
+  sample_t sm;
+  cplx y = CMPLX(zcx - L.z2, zcy) + rho * CMPLX(cos(theta), sin(theta));
+  solve_point(&L, y, 100.0, &sm.im);
+  limb_derivs(&L, rho, theta, &sm);
+  for (int k = 0; k < 5; ++k) {
+    if (img10) {
+      img10[2 * k] = creal(sm.im.z[k]) + L.z2;
+      img10[2 * k + 1] = cimag(sm.im.z[k]);
+    }
+    if (dz10) {
+      dz10[2 * k] = k < sm.im.n ? creal(sm.dz[k]) : 0.0;
+      dz10[2 * k + 1] = k < sm.im.n ? cimag(sm.dz[k]) : 0.0;
+    }
+    if (wedge5) wedge5[k] = k < sm.im.n ? sm.w[k] : 0.0;
+  }
+  if (n_real) *n_real = sm.im.n;
+  return TWK_REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Linking of adjacent samples (Sec. 2.3).                               */
+/* Same-parity images of adjacent samples are linked by the assignment   */
+/* with the least total distance.  When the counts differ, one positive  */
+/* and one negative image of the sample with more images are left over:  */
+/* that pair is created (or destroyed) on the critical curve and is      */
+/* joined to itself.                                                     */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int na, nb;        /* real images at each end (after slope detector)  */
+  int nlink;
+  int la[5], lb[5];  /* linked image indices at a and b                 */
+  int par[5];        /* parity of each link                             */
+  int kind;          /* 0 none, +1 pair created at b, -1 destroyed at a */
+  int cp, cn;        /* indices of the + and - image of that pair        */
+  int anomaly;
+} links_t;
+
+/* effective real-image list of a sample (slope detector applied) */
+static int eff_list(const sample_t *sm, int idx[5]) {
+  int m = 0;
+  for (int k = 0; k < sm->im.n; ++k) {
+    if (k == sm->demote[0] || k == sm->demote[1]) continue;
+    idx[m++] = k;
+  }
+  return m;
+}
+
+/* Least total distance injection of the smaller list into the larger.
+ * Enumeration order: lexicographic over ordered choices; first minimum
+ * wins on ties. */
+static void assign(const cplx *za, const int *ia, int na, const cplx *zb,
+                   const int *ib, int nb, int *ma, int *mb, int *nm) {
+  if (na == 0 || nb == 0) {
+    *nm = 0;
+    return;
+  }
+  /* swap so that a is the smaller side */
+  int swapped = 0;
+  if (na > nb) {
+    const cplx *tz = za; za = zb; zb = tz;
+    const int *ti = ia; ia = ib; ib = ti;
+    int t = na; na = nb; nb = t;
+    swapped = 1;
+  }
+  double best = INFINITY;
+  int bestp[3] = {0, 1, 2};
+  int p[3];
+  /* ordered choices of na distinct elements from nb (na <= 3, nb <= 3) */
+  for (p[0] = 0; p[0] < nb; ++p[0]) {
+    if (na == 1) {
+      double d = cabs(za[ia[0]] - zb[ib[p[0]]]);
+      if (d < best) { best = d; bestp[0] = p[0]; }
+      continue;
+    }
+    for (p[1] = 0; p[1] < nb; ++p[1]) {
+      if (p[1] == p[0]) continue;
+      if (na == 2) {
+        double d = cabs(za[ia[0]] - zb[ib[p[0]]]) + cabs(za[ia[1]] - zb[ib[p[1]]]);
+        if (d < best) { best = d; bestp[0] = p[0]; bestp[1] = p[1]; }
+        continue;
+      }
+      for (p[2] = 0; p[2] < nb; ++p[2]) {
+        if (p[2] == p[0] || p[2] == p[1]) continue;
+        double d = cabs(za[ia[0]] - zb[ib[p[0]]]) + cabs(za[ia[1]] - zb[ib[p[1]]]) +
+                   cabs(za[ia[2]] - zb[ib[p[2]]]);
+        if (d < best) { best = d; bestp[0] = p[0]; bestp[1] = p[1]; bestp[2] = p[2]; }
+      }
+    }
+  }
+  for (int k = 0; k < na; ++k) {
+    int x = ia[k], yv = ib[bestp[k]];
+    if (swapped) { ma[k] = yv; mb[k] = x; }
+    else { ma[k] = x; mb[k] = yv; }
+  }
+  *nm = na;
+}
+
+static void link_samples(const sample_t *a, const sample_t *b, links_t *lk) {
+  int ea[5], eb[5];
+  int na = eff_list(a, ea), nb = eff_list(b, eb);
+  int pa[5], npa = 0, ma_[5], nma = 0, pb[5], npb = 0, mb_[5], nmb = 0;
+  for (int k = 0; k < na; ++k) {
+    if (a->im.par[ea[k]] > 0) pa[npa++] = ea[k]; else ma_[nma++] = ea[k];
+  }
+  for (int k = 0; k < nb; ++k) {
+    if (b->im.par[eb[k]] > 0) pb[npb++] = eb[k]; else mb_[nmb++] = eb[k];
+  }
+  lk->na = na;
+  lk->nb = nb;
+  lk->nlink = 0;
+  lk->kind = 0;
+  lk->cp = lk->cn = -1;
+  lk->anomaly = 0;
+  int xa[3], xb[3], nm;
+  /* positive parity class */
+  assign(a->im.z, pa, npa, b->im.z, pb, npb, xa, xb, &nm);
+  for (int k = 0; k < nm; ++k) {
+    lk->la[lk->nlink] = xa[k];
+    lk->lb[lk->nlink] = xb[k];
+    lk->par[lk->nlink] = 1;
+    lk->nlink++;
+  }
+  int usedp_a[5] = {0}, usedp_b[5] = {0};
+  for (int k = 0; k < nm; ++k) { usedp_a[xa[k]] = 1; usedp_b[xb[k]] = 1; }
+  /* negative parity class */
+  assign(a->im.z, ma_, nma, b->im.z, mb_, nmb, xa, xb, &nm);
+  int usedn_a[5] = {0}, usedn_b[5] = {0};
+  for (int k = 0; k < nm; ++k) {
+    lk->la[lk->nlink] = xa[k];
+    lk->lb[lk->nlink] = xb[k];
+    lk->par[lk->nlink] = -1;
+    lk->nlink++;
+    usedn_a[xa[k]] = 1;
+    usedn_b[xb[k]] = 1;
+  }
+  /* left-over images */
+  int lpa = -1, lna = -1, lpb = -1, lnb = -1, cnt_a = 0, cnt_b = 0;
+  for (int k = 0; k < npa; ++k) if (!usedp_a[pa[k]]) { lpa = pa[k]; cnt_a++; }
+  for (int k = 0; k < nma; ++k) if (!usedn_a[ma_[k]]) { lna = ma_[k]; cnt_a++; }
+  for (int k = 0; k < npb; ++k) if (!usedp_b[pb[k]]) { lpb = pb[k]; cnt_b++; }
+  for (int k = 0; k < nmb; ++k) if (!usedn_b[mb_[k]]) { lnb = mb_[k]; cnt_b++; }
+  if (cnt_a == 0 && cnt_b == 0) return;
+  if (cnt_a == 0 && cnt_b == 2 && lpb >= 0 && lnb >= 0) {
+    lk->kind = 1; lk->cp = lpb; lk->cn = lnb;
+  } else if (cnt_b == 0 && cnt_a == 2 && lpa >= 0 && lna >= 0) {
+    lk->kind = -1; lk->cp = lpa; lk->cn = lna;
+  } else {
+    lk->anomaly = 1;
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Area and error of one interval (Sec. 2.3 Stokes area with trapezium  */
+/* and parabolic corrections, Eq. area_cal and the cross-caustic form;  */
+/* Sec. 2.5 errors, Eqs. area_normal and area_cross).                    */
+/* Wedge a^b = Im(conj(a) b); dot a.b = Re(conj(a) b).                    */
+/* Positive images run with theta, negative against it, so each linked   */
+/* piece enters the area with the parity as sign.                        */
+/* ------------------------------------------------------------------ */
+static double wedge(cplx a, cplx b) { return cimag(conj(a) * b); }
+static double dot(cplx a, cplx b) { return creal(conj(a) * b); }
+
+typedef struct {
+  double dA, E;
+  int cross;
+  int anomaly;
+} piece_t;
+
+static piece_t interval_piece(const sample_t *a, const sample_t *b,
+                              double dth) {
+  links_t lk;
+  link_samples(a, b, &lk);
+  piece_t out = {0.0, 0.0, 0, lk.anomaly};
+  double dth2 = dth * dth, dth3 = dth2 * dth;
+  for (int k = 0; k < lk.nlink; ++k) {
+    int i = lk.la[k], j = lk.lb[k];
+    cplx za = a->im.z[i], zb = b->im.z[j];
+    cplx da = a->dz[i], db = b->dz[j];
+    double wa = a->w[i], wb = b->w[j];
+    double p = (double)lk.par[k];
+    double dAt = 0.5 * wedge(za, zb);
+    double dAp1 = (wa + wb) * dth3 / 24.0;
+    double dAp2 = wedge(zb - za, db - da) * dth / 12.0;
+    double dAp = 0.5 * (dAp1 + dAp2);
+    out.dA += p * (dAt + dAp);
+    double E1 = fabs(wa - wb) * dth3 / 48.0;
+    double ch = cabs(za - zb);
+    double E2 = 1.5 * fabs(dAp * (ch * ch / (dth2 * fabs(dot(da, db))) - 1.0));
+    double E3 = 0.1 * fabs(dAp) * dth2;
+    double E4 = fabs(dAp1 - dAp2);
+    out.E += E1 + E2 + E3 + E4;
+  }
+  if (lk.kind != 0) {
+    /* the created pair lives at b, the destroyed pair at a */
+    const sample_t *c = lk.kind > 0 ? b : a;
+    cplx zp = c->im.z[lk.cp], zm = c->im.z[lk.cn];
+    cplx dp = c->dz[lk.cp], dm = c->dz[lk.cn];
+    double wp = c->w[lk.cp], wm = c->w[lk.cn];
+    double dd = sqrt(fabs(dot(dp, dm)));
+    double sep = cabs(zp - zm);
+    double dtt = sep / dd;  /* effective step across the critical curve */
+    double dtt3 = dtt * dtt * dtt;
+    double dAp = (wp - wm) * dtt3 / 24.0;
+    /* boundary runs from the - image to the + image where the pair is
+     * created, and from + to - where it is destroyed */
+    double chord = lk.kind > 0 ? 0.5 * wedge(zm, zp) : 0.5 * wedge(zp, zm);
+    out.dA += chord + dAp;
+    double E1 = fabs(wp + wm) * dtt3 / 48.0;
+    /* READING of the garbled cross-caustic E2: "-" for a pair created
+     * along +theta, "+" for a destroyed one. */
+    double sgn = lk.kind > 0 ? 1.0 : -1.0;
+    double E2 = 1.5 * fabs(dot(zp - zm, dp - dm) - sgn * 2.0 * sep * dd) * dtt;
+    double E3 = 0.1 * fabs(dAp) * dth2;
+    out.E += E1 + E2 + E3;
+    out.cross = 1;
+  }
+  return out;
+}
+
+/* ------------------------------------------------------------------ */
+/* Slope detector (Sec. 2.4.2).                                           */
+/* READING: at a change of the real-image count between adjacent samples, */
+/* D is the difference (+ minus -) of the left-over pair at the 5-image   */
+/* sample and G the ghost-pair difference at the 3-image sample.  The     */
+/* crossing is accepted when the two are perpendicular enough,            */
+/* |Re(conj(D) G)| <= cos(pi/4) |D| |G|.  Otherwise the pair is followed   */
+/* into the 5-image run; the first step at which consecutive pair         */
+/* differences are perpendicular marks the true crossing and the samples  */
+/* walked over are reclassified (their pair becomes a ghost pair).  When  */
+/* the run ends first, the whole run is reclassified (the piece deleted). */
+/* ------------------------------------------------------------------ */
+static int perp_enough(cplx D, cplx G) {
+  return fabs(dot(D, G)) <= 0.70710678118654752440 * cabs(D) * cabs(G);
+}
+
+static void reset_demotions(sample_t *sm, int nsm) {
+  for (int i = 0; i < nsm; ++i) {
+    sm[i].demote[0] = sm[i].demote[1] = -1;
+    sm[i].n_eff = sm[i].im.n;
+  }
+}
+
+/* ord: sorted sample indices, N of them (cyclic).  Returns number of
+ * reclassified samples. */
+static int slope_detector(sample_t *sm, const int *ord, int N) {
+  int changed = 0;
+  /* find a 3-image sample to anchor the cyclic walk */
+  int anchor = -1;
+  for (int i = 0; i < N; ++i)
+    if (sm[ord[i]].im.n == 3) { anchor = i; break; }
+  if (anchor < 0) return 0;
+  /* scan runs of 5-image samples in cyclic order starting after anchor */
+  int i = 0;
+  while (i < N) {
+    int pos = (anchor + i) % N;
+    if (sm[ord[pos]].im.n != 5) { ++i; continue; }
+    /* run from pos forward */
+    int start = i, len = 0;
+    while (i < N && sm[ord[(anchor + i) % N]].im.n == 5) { ++len; ++i; }
+    int k_in = (anchor + start - 1 + N) % N;  /* 3-image sample before  */
+    int k_out = (anchor + start + len) % N;   /* 3-image sample after   */
+    int first = (anchor + start) % N;
+    /* entry boundary: pair created at run[0] */
+    int del_from = -1, del_to = -1;  /* run offsets to demote [from,to) */
+    {
+      links_t lk;
+      sample_t *a = &sm[ord[k_in]], *b = &sm[ord[first]];
+      link_samples(a, b, &lk);
+      if (lk.kind == 1) {
+        cplx D = b->im.z[lk.cp] - b->im.z[lk.cn];
+        cplx G = a->im.z[3] - a->im.z[4];
+        if (!perp_enough(D, G)) {
+          int cp = lk.cp, cn = lk.cn, j;
+          int found = -1;
+          for (j = 0; j + 1 < len; ++j) {
+            sample_t *c0 = &sm[ord[(first + j) % N]];
+            sample_t *c1 = &sm[ord[(first + j + 1) % N]];
+            links_t l2;
+            link_samples(c0, c1, &l2);
+            int np = -1, nn = -1;
+            for (int t = 0; t < l2.nlink; ++t) {
+              if (l2.la[t] == cp) np = l2.lb[t];
+              if (l2.la[t] == cn) nn = l2.lb[t];
+            }
+            if (np < 0 || nn < 0) break;
+            cplx D0 = c0->im.z[cp] - c0->im.z[cn];
+            cplx D1 = c1->im.z[np] - c1->im.z[nn];
+            if (perp_enough(D0, D1)) { found = j; break; }
+            cp = np; cn = nn;
+          }
+          if (found >= 0) { del_from = 0; del_to = found + 1; }
+          else { del_from = 0; del_to = len; }
+        }
+      }
+    }
+    int del2_from = -1, del2_to = -1;
+    if (!(del_from == 0 && del_to == len)) {
+      /* exit boundary: pair destroyed after run[len-1] */
+      links_t lk;
+      int last = (first + len - 1) % N;
+      sample_t *a = &sm[ord[last]], *b = &sm[ord[k_out]];
+      link_samples(a, b, &lk);
+      if (lk.kind == -1) {
+        cplx D = a->im.z[lk.cp] - a->im.z[lk.cn];
+        cplx G = b->im.z[3] - b->im.z[4];
+        if (!perp_enough(D, G)) {
+          int cp = lk.cp, cn = lk.cn;
+          int found = -1;
+          for (int j = len - 1; j - 1 >= 0; --j) {
+            sample_t *c0 = &sm[ord[(first + j) % N]];
+            sample_t *c1 = &sm[ord[(first + j - 1) % N]];
+            links_t l2;
+            link_samples(c0, c1, &l2);
+            int np = -1, nn = -1;
+            for (int t = 0; t < l2.nlink; ++t) {
+              if (l2.la[t] == cp) np = l2.lb[t];
+              if (l2.la[t] == cn) nn = l2.lb[t];
+            }
+            if (np < 0 || nn < 0) break;
+            cplx D0 = c0->im.z[cp] - c0->im.z[cn];
+            cplx D1 = c1->im.z[np] - c1->im.z[nn];
+            if (perp_enough(D0, D1)) { found = j; break; }
+            cp = np; cn = nn;
+          }
+          if (found >= 0) { del2_from = found; del2_to = len; }
+          else { del2_from = 0; del2_to = len; }
+        }
+      }
+    }
+    /* apply demotions: the walked pair of each reclassified sample is
+     * demoted.  The pair is re-identified per sample by following links
+     * from the boundary, as in the walk. */
+    for (int pass = 0; pass < 2; ++pass) {
+      int f = pass == 0 ? del_from : del2_from;
+      int t = pass == 0 ? del_to : del2_to;
+      if (f < 0) continue;
+      /* follow the pair from the boundary that triggered this pass */
+      links_t lk;
+      int cp, cn;
+      if (pass == 0) {
+        link_samples(&sm[ord[k_in]], &sm[ord[first]], &lk);
+        cp = lk.cp; cn = lk.cn;
+        for (int j = 0; j < t; ++j) {
+          sample_t *c0 = &sm[ord[(first + j) % N]];
+          if (c0->demote[0] < 0) {
+            c0->demote[0] = cp; c0->demote[1] = cn; c0->n_eff = 3; ++changed;
+          }
+          if (j + 1 >= t) break;
+          sample_t *c1 = &sm[ord[(first + j + 1) % N]];
+          links_t l2;
+          /* link with full image sets, ignoring demotions just applied */
+          int s0 = c0->demote[0], s1 = c0->demote[1];
+          c0->demote[0] = c0->demote[1] = -1;
+          link_samples(c0, c1, &l2);
+          c0->demote[0] = s0; c0->demote[1] = s1;
+          int np = -1, nn = -1;
+          for (int u = 0; u < l2.nlink; ++u) {
+            if (l2.la[u] == cp) np = l2.lb[u];
+            if (l2.la[u] == cn) nn = l2.lb[u];
+          }
+          if (np < 0 || nn < 0) break;
+          cp = np; cn = nn;
+        }
+      } else {
+        int last = (first + len - 1) % N;
+        link_samples(&sm[ord[last]], &sm[ord[k_out]], &lk);
+        cp = lk.cp; cn = lk.cn;
+        for (int j = len - 1; j >= f; --j) {
+          sample_t *c0 = &sm[ord[(first + j) % N]];
+          if (c0->demote[0] < 0) {
+            c0->demote[0] = cp; c0->demote[1] = cn; c0->n_eff = 3; ++changed;
+          }
+          if (j - 1 < f) break;
+          sample_t *c1 = &sm[ord[(first + j - 1) % N]];
+          links_t l2;
+          int s0 = c0->demote[0], s1 = c0->demote[1];
+          c0->demote[0] = c0->demote[1] = -1;
+          link_samples(c0, c1, &l2);
+          c0->demote[0] = s0; c0->demote[1] = s1;
+          int np = -1, nn = -1;
+          for (int u = 0; u < l2.nlink; ++u) {
+            if (l2.la[u] == cp) np = l2.lb[u];
+            if (l2.la[u] == cn) nn = l2.lb[u];
+          }
+          if (np < 0 || nn < 0) break;
+          cp = np; cn = nn;
+        }
+      }
+    }
+  }
+  return changed;
+}
+
+/* ------------------------------------------------------------------ */
+/* Contour integration with adaptive sampling (Secs. 2.3, 2.5, 3).        */
+/*  - start from n0 uniform limb angles theta_j = 2 pi j / n0 (READING);  */
+/*  - area A = sum of interval pieces, error E = sum of interval errors;  */
+/*  - stop when E <= tol |A| (relative tolerance, READING);               */
+/*  - otherwise weight each interval by max(E_i - tol|A|/N_int, 0)        */
+/*    (tolerance subtraction), build the normalised cumulative weight,    */
+/*    and invert it at quantiles (j + 1/2)/nnew by linear interpolation   */
+/*    inside each interval (inverse transform sampling);                  */
+/*  - the sample cap ends the refinement; mu and err are still returned.  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  double sum, comp;
+} nsum_t;
+
+/* Neumaier's compensated summation */
+static void nsum_add(nsum_t *s, double x) {
+  double t = s->sum + x;
+  if (fabs(s->sum) >= fabs(x)) s->comp += (s->sum - t) + x;
+  else s->comp += (x - t) + s->sum;
+  s->sum = t;
+}
+
+static void sample_at(const lens_t *L, cplx yc, double rho, double theta,
+                      double kgap, sample_t *sm) {
+  sm->theta = theta;
+  cplx y = yc + rho * CMPLX(cos(theta), sin(theta));
+  solve_point(L, y, kgap, &sm->im);
+  limb_derivs(L, rho, theta, sm);
+  sm->n_eff = sm->im.n;
+  sm->demote[0] = sm->demote[1] = -1;
+}
+
+void twk_ref_cfg_default(twk_ref_cfg *cfg, double tol) {
+  cfg->tol = tol;
+  cfg->n0 = 64;
+  cfg->nnew = 64;
+  cfg->cap = 4096;
+  cfg->grow = 0;
+  cfg->slope = 1;
+  cfg->kgap = 100.0;
+}
+
+static int contour(const lens_t *L, cplx yc, double rho, const twk_ref_cfg *cfg,
+                   double *mag, double *err, int32_t *nsamp, uint32_t *flags,
+                   double *theta_out, int32_t max_out) {
+  int cap = cfg->cap;
+  sample_t *sm = (sample_t *)malloc(sizeof(sample_t) * (size_t)cap);
+  int *ord = (int *)malloc(sizeof(int) * (size_t)cap);
+  int *ord2 = (int *)malloc(sizeof(int) * (size_t)cap);
+  double *wcum = (double *)malloc(sizeof(double) * ((size_t)cap + 1));
+  double *Ei = (double *)malloc(sizeof(double) * (size_t)cap);
+  double *newth = (double *)malloc(sizeof(double) * (size_t)cap);
+  int *newiv = (int *)malloc(sizeof(int) * (size_t)cap);
+  if (!sm || !ord || !ord2 || !wcum || !Ei || !newth || !newiv) {
+    free(sm); free(ord); free(ord2); free(wcum); free(Ei); free(newth); free(newiv);
+    return TWK_REF_ENOMEM;
+  }
+  uint32_t fl = 0;
+  int N = cfg->n0 < cap ? cfg->n0 : cap;
+  for (int j = 0; j < N; ++j) {
+    sample_at(L, yc, rho, 2.0 * PI_D * j / N, cfg->kgap, &sm[j]);
+    ord[j] = j;
+  }
+  const double tol = cfg->tol;
+  double A = 0.0, E = 0.0;
+  for (;;) {
+    for (int i = 0; i < N; ++i) fl |= sm[i].im.flags & (TWK_REF_FLAG_ANOMALY | TWK_REF_FLAG_NEARDEGEN);
+    if (cfg->slope) {
+      reset_demotions(sm, N);
+      if (slope_detector(sm, ord, N) > 0) fl |= TWK_REF_FLAG_SLOPE;
+    }
+    nsum_t sa = {0.0, 0.0};
+    double se = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const sample_t *a = &sm[ord[i]];
+      const sample_t *b = &sm[ord[(i + 1) % N]];
+      double dth = (i + 1 < N ? b->theta : b->theta + 2.0 * PI_D) - a->theta;
+      piece_t pc = interval_piece(a, b, dth);
+      if (pc.anomaly) fl |= TWK_REF_FLAG_ANOMALY;
+      nsum_add(&sa, pc.dA);
+      Ei[i] = pc.E;
+      se += pc.E;
+    }
+    A = sa.sum + sa.comp;
+    E = se;
+    if (E <= tol * fabs(A)) break;
+    int nnew = cfg->nnew;
+    if (cfg->grow > 0 && N / cfg->grow > nnew) nnew = N / cfg->grow;
+    if (N + nnew > cap) nnew = cap - N;
+    if (nnew <= 0) { fl |= TWK_REF_FLAG_CAP; break; }
+    /* tolerance-subtracted weights and their cumulative sum */
+    double avg = tol * fabs(A) / N;
+    wcum[0] = 0.0;
+    for (int i = 0; i < N; ++i) {
+      double w = Ei[i] - avg;
+      wcum[i + 1] = wcum[i] + (w > 0.0 ? w : 0.0);
+    }
+    double W = wcum[N];
+    if (!(W > 0.0)) break;
+    /* invert the cumulative weight at nnew quantiles */
+    int m = 0, iv = 0;
+    for (int j = 0; j < nnew; ++j) {
+      double u = (j + 0.5) / nnew * W;
+      while (iv < N - 1 && wcum[iv + 1] <= u) ++iv;
+      double wi = wcum[iv + 1] - wcum[iv];
+      if (!(wi > 0.0)) continue;
+      const sample_t *a = &sm[ord[iv]];
+      double tb = iv + 1 < N ? sm[ord[iv + 1]].theta : 2.0 * PI_D;
+      double th = a->theta + (u - wcum[iv]) / wi * (tb - a->theta);
+      if (!(th > a->theta && th < tb)) continue;
+      if (m > 0 && newiv[m - 1] == iv && !(th > newth[m - 1])) continue;
+      newth[m] = th;
+      newiv[m] = iv;
+      ++m;
+    }
+    if (m == 0) { fl |= TWK_REF_FLAG_CAP; break; }
+    /* solve the new samples and merge them into the sorted order */
+    for (int j = 0; j < m; ++j) sample_at(L, yc, rho, newth[j], cfg->kgap, &sm[N + j]);
+    int o = 0, j = 0;
+    for (int i = 0; i < N; ++i) {
+      ord2[o++] = ord[i];
+      while (j < m && newiv[j] == i) { ord2[o++] = N + j; ++j; }
+    }
+    N += m;
+    memcpy(ord, ord2, sizeof(int) * (size_t)N);
+  }
+  double area = PI_D * rho * rho;
+  *mag = A / area;
+  *err = E / area;
+  *nsamp = N;
+  *flags = fl;
+  if (theta_out) {
+    for (int i = 0; i < N && i < max_out; ++i) theta_out[i] = sm[ord[i]].theta;
+  }
+  free(sm); free(ord); free(ord2); free(wcum); free(Ei); free(newth); free(newiv);
+  return TWK_REF_OK;
+}
+
+int twk_ref_finite_mag(double s, double q, int64_t n, const double *zx,
+                       const double *zy, double rho, double tol,
+                       const twk_ref_cfg *cfg_in, double *mag, double *err,
+                       int32_t *nsamp, uint32_t *flags) {
+  if (!lens_ok(s, q) || !(rho > 0.0) || !isfinite(rho) || !(tol > 0.0) ||
+      n < 0 || (n > 0 && (!zx || !zy || !mag || !err || !nsamp || !flags)))
+    return TWK_REF_EINVAL;
+  twk_ref_cfg cfg;
+  if (cfg_in) cfg = *cfg_in;
+  else twk_ref_cfg_default(&cfg, tol);
+  cfg.tol = tol;
+  if (cfg.n0 < 4 || cfg.nnew < 1 || cfg.cap < cfg.n0) return TWK_REF_EINVAL;
+  lens_t L = lens_make(s, q);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!isfinite(zx[i]) || !isfinite(zy[i])) {
+      mag[i] = NAN; err[i] = NAN; nsamp[i] = 0; flags[i] = TWK_REF_FLAG_NONFINITE;
+      continue;
+    }
+    int rc = contour(&L, CMPLX(zx[i] - L.z2, zy[i]), rho, &cfg, &mag[i], &err[i],
+                     &nsamp[i], &flags[i], NULL, 0);
+    if (rc) return rc;
+  }
+  return TWK_REF_OK;
+}
+
+int twk_ref_finite_trace(double s, double q, double zx, double zy, double rho,
+                         const twk_ref_cfg *cfg, double *mag, double *err,
+                         int32_t *nsamp, uint32_t *flags, double *theta_out,
+                         int32_t max_out) {
+  if (!lens_ok(s, q) || !(rho > 0.0) || !cfg || !mag || !err || !nsamp || !flags)
+    return TWK_REF_EINVAL;
+  lens_t L = lens_make(s, q);
+  return contour(&L, CMPLX(zx - L.z2, zy), rho, cfg, mag, err, nsamp, flags,
+                 theta_out, max_out);
+}
+
+/* ------------------------------------------------------------------ */
+/* Trajectory (not in the paper): straight line in the CM frame with    */
+/* impact parameter u0 and angle alpha, tau = (t - t0)/tE.               */
+/* ------------------------------------------------------------------ */
+int twk_ref_trajectory(double u0, double alpha, int64_t n, const double *tau,
+                       double *zx, double *zy) {
+  if (n < 0 || (n > 0 && (!tau || !zx || !zy))) return TWK_REF_EINVAL;
+  double ca = cos(alpha), sa = sin(alpha);
+  for (int64_t i = 0; i < n; ++i) {
+    zx[i] = tau[i] * ca - u0 * sa;
+    zy[i] = tau[i] * sa + u0 * ca;
+  }
+  return TWK_REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Linear limb darkening (not in the paper; the paper only notes that    */
+/* limb darkening is costly with contours).  Intensity relative to the    */
+/* disk mean: I(r) = 1 - Gamma (1 - 1.5 sqrt(1 - r^2/rho^2)).  Annuli of   */
+/* equal area: r_k = rho sqrt(k/na).  Annulus mean intensity I_k =        */
+/* 1 - Gamma + Gamma * [(1-x_{k-1})^{3/2} - (1-x_k)^{3/2}] / (x_k - x_{k-1})*/
+/* with x_k = r_k^2/rho^2.  mu_LD = sum_k I_k (x_k mu_k - x_{k-1} mu_{k-1}) */
+/*                          / sum_k I_k (x_k - x_{k-1}).                   */
+/* ------------------------------------------------------------------ */
+int twk_ref_ld_combine(double gamma, int32_t na, const double *mu_k,
+                       double *mu_ld) {
+  if (na < 1 || !mu_k || !mu_ld) return TWK_REF_EINVAL;
+  double num = 0.0, den = 0.0, xprev = 0.0, mprev = 0.0;
+  for (int k = 1; k <= na; ++k) {
+    double x = (double)k / na;
+    double Ik = 1.0 - gamma +
+                gamma * (pow(1.0 - xprev, 1.5) - pow(1.0 - x, 1.5)) / (x - xprev);
+    num += Ik * (x * mu_k[k - 1] - xprev * mprev);
+    den += Ik * (x - xprev);
+    xprev = x;
+    mprev = mu_k[k - 1];
+  }
+  *mu_ld = num / den;
+  return TWK_REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Point-source adequacy (Sec. 2.3 names a quadrupole test and a ghost   */
+/* image test without formulas).  READING:                               */
+/*  - quadrupole: the four-point mean of mu at zeta_c +- rho, +- i rho   */
+/*    exceeds mu(zeta_c) by (rho^2/4) Lap(mu) while the disk mean exceeds */
+/*    it by (rho^2/8) Lap(mu); the finite-source correction is estimated  */
+/*    as dQ = (mean4 - mu0)/2 and must satisfy CQ |dQ| < tol mu0;         */
+/*  - every one of the five points has three images;                      */
+/*  - ghost test: a ghost root g with residual R_g sits near the critical */
+/*    curve when the source is near a fold; |R_g| grows like sqrt(d) with */
+/*    the distance d to the caustic, with a scale set by f''.  The        */
+/*    statistic |f''(g)| |R_g|^2 estimates d and must exceed CG rho for   */
+/*    both ghosts of all five points.                                     */
+/* ------------------------------------------------------------------ */
+#define PS_CQ 20.0
+#define PS_CG 8.0
+
+int twk_ref_ps_adequate(double s, double q, double zx, double zy, double rho,
+                        double tol, int32_t *adequate, double *mu_ps) {
+  if (!lens_ok(s, q) || !(rho > 0.0) || !(tol > 0.0) || !adequate || !mu_ps)
+    return TWK_REF_EINVAL;
+  lens_t L = lens_make(s, q);
+  cplx yc = CMPLX(zx - L.z2, zy);
+  cplx pts[5] = {yc, yc + rho, yc + CMPLX(0.0, rho), yc - rho, yc - CMPLX(0.0, rho)};
+  double mu[5];
+  int ok = 1;
+  for (int k = 0; k < 5; ++k) {
+    images_t im;
+    solve_point(&L, pts[k], 100.0, &im);
+    mu[k] = mu_point(&im);
+    if (im.n != 3) ok = 0;
+    for (int g = im.n; g < 5; ++g) {
+      double d = cabs(fsecond(&L, im.z[g])) * creal(im.R[g] * conj(im.R[g]));
+      if (!(d > PS_CG * rho)) ok = 0;
+    }
+  }
+  double dq = 0.5 * (0.25 * (mu[1] + mu[2] + mu[3] + mu[4]) - mu[0]);
+  if (!(PS_CQ * fabs(dq) < tol * mu[0])) ok = 0;
+  *adequate = ok;
+  *mu_ps = mu[0];
+  return TWK_REF_OK;
+}

@@ -1,0 +1,391 @@
+"""Pins of the FP64 oracle against facts the paper and mathematics fix,
+independently of the oracle's own code (CPU only)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import pins
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
+RNG = np.random.default_rng(12345)
+
+
+def _random_configs(n, logq=(-6, -1), logs=(-0.5, 0.5), box=1.6):
+    out = []
+    for _ in range(n):
+        s = 10 ** RNG.uniform(*logs)
+        q = 10 ** RNG.uniform(*logq)
+        zeta = RNG.uniform(-box, box) + 1j * RNG.uniform(-box, box)
+        out.append((s, q, zeta))
+    return out
+
+
+# ---------------------------------------------------------------- coefficients
+def test_refined_coefficients_match_symbolic_quintic(oracle):
+    """Sec. 2.2 Eq. method-transformed: the refined c0..c5 equal the
+    numerator of y - (eta - m1/(conj(eta)+s) - m2/conj(eta)) after
+    conj(eta) is eliminated through the conjugated lens equation, derived
+    here with sympy and evaluated in 50-digit arithmetic."""
+    sp = pytest.importorskip("sympy")
+    import mpmath
+    eta, yr, yi, s, m2 = sp.symbols("eta yr yi s m2")
+    y = yr + sp.I * yi
+    yb = yr - sp.I * yi
+    m1 = 1 - m2
+    etab = yb + m1 / (eta + s) + m2 / eta
+    expr = y - (eta - m1 / (etab + s) - m2 / etab)
+    P = sp.Poly(sp.expand(sp.numer(sp.together(expr))), eta)
+    cs = P.all_coeffs()[::-1]
+    fns = [sp.lambdify((yr, yi, s, m2), c, "mpmath") for c in cs]
+    mpmath.mp.dps = 50
+    for (sv, qv, zeta) in _random_configs(30) + [(0.5, 1e-6, complex(*GOLD["fig1_coefficients"]["zeta"]))]:
+        # the same binary64 inputs the oracle forms (m2, y), then exact algebra
+        m2v = mpmath.mpf(qv / (1.0 + qv))
+        yv = mpmath.mpc(zeta.real - sv / (1.0 + qv), zeta.imag)
+        exact = [complex(f(yv.real, yv.imag, mpmath.mpf(sv), m2v)) for f in fns]
+        got = oracle.coeffs(sv, qv, zeta)
+        for k in range(6):
+            assert abs(got[k] - exact[k]) <= 1e-13 * abs(exact[k]), (k, sv, qv, zeta)
+
+
+def test_coefficients_vanish_at_forward_mapped_images(oracle):
+    """Any image position z maps to a source zeta by the lens equation
+    (Sec. 2.1); the quintic of that zeta must vanish at eta = z - z2."""
+    for (s, q, _) in _random_configs(40):
+        z = RNG.uniform(-2, 2) + 1j * RNG.uniform(-2, 2)
+        zeta = complex(pins.forward_map(s, q, z))
+        c = oracle.coeffs(s, q, zeta)
+        eta = z - pins.lens_setup(s, q)[3]
+        terms = np.array([c[k] * eta ** k for k in range(6)])
+        assert abs(terms.sum()) <= 1e-13 * np.abs(terms).sum()
+
+
+def test_conventional_coefficients_lose_digits_at_small_q(oracle):
+    """Sec. 2.2 and Fig. 1: at s=0.5, q=1e-6 near the planetary caustic the
+    conventional form suffers cancellation while the refined one does not."""
+    import mpmath
+    g = GOLD["fig1_coefficients"]
+    s, q, rho = g["s"], g["q"], g["rho"]
+    zc = complex(*g["zeta"])
+    mpmath.mp.dps = 50
+    worst_ref = worst_conv = 0.0
+    for th in np.linspace(0, 2 * np.pi, 64, endpoint=False):
+        zeta = zc + rho * np.exp(1j * th)
+        ref = oracle.coeffs(s, q, zeta)
+        conv = oracle.coeffs(s, q, zeta, conventional=True)
+        # exact: both forms are the same polynomial; evaluate the refined
+        # formula in 50 digits through the conventional one is circular, so
+        # use agreement between the two on a 50-digit re-evaluation of the
+        # conventional expression instead.
+        m2 = mpmath.mpf(q) / (1 + q)
+        m1 = 1 - m2
+        sv = mpmath.mpf(s)
+        y = mpmath.mpc(zeta.real, zeta.imag) - sv / (1 + mpmath.mpf(q))
+        yb = mpmath.conj(y)
+        c2 = y * (1 + sv ** 3 * yb) + sv * (m1 + 2 * y * yb * (1 + m2)) + sv ** 2 * (yb * (m1 - m2) + y * (1 + m2 + yb * yb))
+        e2 = complex(c2)
+        worst_ref = max(worst_ref, abs(ref[2] - e2) / abs(e2))
+        worst_conv = max(worst_conv, abs(conv[2] - e2) / abs(e2))
+    assert worst_ref < 1e-14
+    assert worst_conv > 1e3 * worst_ref
+
+
+# ---------------------------------------------------------------- roots, residuals
+def test_roots_match_lapack_companion(oracle):
+    for (s, q, zeta) in _random_configs(60):
+        c = oracle.coeffs(s, q, zeta)
+        r, it = oracle.roots(c)
+        lap = np.roots(c[::-1])
+        for x in lap:
+            d = np.min(np.abs(r - x))
+            assert d <= 1e-7 * max(1.0, abs(x)), (s, q, zeta)
+        # every oracle root is a root to working precision
+        for x in r:
+            terms = np.array([c[k] * x ** k for k in range(6)])
+            assert abs(terms.sum()) <= 1e-12 * np.abs(terms).sum()
+
+
+def test_residual_sum_vanishes(oracle):
+    """Sec. 2.4.1 Eqs. sum_r, sum_r2: the five residuals sum to zero."""
+    for (s, q, zeta) in _random_configs(200):
+        im = oracle.images(s, q, zeta)
+        R = im["R"]
+        assert abs(R.sum()) <= 1e-12 * max(1.0, np.abs(R).max()), (s, q, zeta, R)
+
+
+def test_image_counts_parity_and_newton_census(oracle):
+    """Sec. 2.3: 3 or 5 real images, parity sum -1.  The real images are
+    exactly the solutions of the lens equation, found here independently by
+    Newton's method on the lens equation itself from many starts."""
+    seen = {3: 0, 5: 0}
+    cfgs = _random_configs(40, logq=(-3, -0.3), box=0.6) + _random_configs(20, logq=(-4, -1), box=1.2)
+    for (s, q, zeta) in cfgs:
+        im = oracle.images(s, q, zeta)
+        n = im["n"]
+        assert n in (3, 5)
+        par = np.sign(im["J"][:n])
+        assert par.sum() == -1
+        sols = pins.real_images_newton(s, q, zeta)
+        assert len(sols) == n, (s, q, zeta, n, len(sols))
+        zr = im["z"][:n]
+        for x in sols:
+            assert np.min(np.abs(zr - x)) < 1e-8
+        seen[n] += 1
+    assert seen[3] > 0 and seen[5] > 0
+
+
+def test_point_magnification_paczynski_limit(oracle):
+    """q -> 0: the binary reduces to a point lens of mass m1 at z1, whose
+    Einstein radius is sqrt(m1): mu = (u^2+2)/(u sqrt(u^2+4))."""
+    s, q = 1.3, 1e-10
+    m1, m2, z1, z2 = pins.lens_setup(s, q)
+    u = np.geomspace(1e-3, 3.0, 40)
+    zeta = z1 + u * np.exp(1j * 2.1)
+    mag, n, fl = oracle.point_mag(s, q, zeta.real, zeta.imag)
+    assert np.all(n == 3)
+    np.testing.assert_allclose(mag, pins.paczynski(u / np.sqrt(m1)), rtol=1e-7)
+
+
+def test_point_magnification_symmetric_about_axis(oracle):
+    for (s, q, zeta) in _random_configs(50):
+        a, _, _ = oracle.point_mag(s, q, [zeta.real], [zeta.imag])
+        b, _, _ = oracle.point_mag(s, q, [zeta.real], [-zeta.imag])
+        assert abs(a[0] - b[0]) <= 1e-9 * a[0]
+
+
+# ---------------------------------------------------------------- limb derivatives
+def test_limb_derivatives_by_finite_differences(oracle):
+    """z' and z'^z'' along the limb (Sec. 2.3, Eq. area_cal) against central
+    differences of the images themselves."""
+    cases = [(1.0, 0.1, 0.2 + 0.2j, 0.1), (0.8, 1e-3, 0.1 - 0.05j, 0.05), (1.2, 0.3, -0.3 + 0.4j, 0.2)]
+    h = 1e-4
+    for (s, q, zc, rho) in cases:
+        for th in np.linspace(0.1, 6.1, 7):
+            z0, d0, w0, n0 = oracle.limb_derivs(s, q, zc, rho, th)
+            zm, _, _, nm = oracle.limb_derivs(s, q, zc, rho, th - h)
+            zp, _, _, np_ = oracle.limb_derivs(s, q, zc, rho, th + h)
+            if not (n0 == nm == np_):
+                continue
+            for k in range(n0):
+                im_ = zm[np.argmin(np.abs(zm[:nm] - z0[k]))]
+                ip_ = zp[np.argmin(np.abs(zp[:np_] - z0[k]))]
+                d1 = (ip_ - im_) / (2 * h)
+                d2 = (ip_ - 2 * z0[k] + im_) / (h * h)
+                wfd = (np.conj(d1) * d2).imag
+                assert abs(d1 - d0[k]) <= 1e-6 * abs(d0[k]) + 1e-12
+                assert abs(wfd - w0[k]) <= 1e-4 * abs(w0[k]) + 1e-9
+
+
+def test_compact_wedge_formula_reading(oracle):
+    """READING of Eq. area_cal: with conj(f') in z' and a division by J,
+    z'^z'' = [rho^2 + Im(z'^2 zeta' f'')]/J reproduces the directly solved
+    value."""
+    for (s, q, zc, rho) in [(1.0, 0.1, 0.2 + 0.2j, 0.1), (0.7, 1e-4, -0.9 + 0.3j, 0.01)]:
+        m1, m2, z1, z2 = pins.lens_setup(s, q)
+        for th in np.linspace(0, 6.2, 9):
+            z, dz, w, n = oracle.limb_derivs(s, q, zc, rho, th)
+            zp = 1j * rho * np.exp(1j * th)
+            for k in range(n):
+                fpp = 2 * m1 / (z1 - z[k]) ** 3 + 2 * m2 / (z2 - z[k]) ** 3
+                J = pins.jacobian(s, q, z[k])
+                compact = (rho ** 2 + (dz[k] ** 2 * zp * fpp).imag) / J
+                assert abs(compact - w[k]) <= 1e-9 * abs(w[k])
+
+
+# ---------------------------------------------------------------- finite source
+@pytest.mark.parametrize("u,rho", [(0.5, 0.1), (0.05, 0.1), (0.1, 0.1001), (0.1001, 0.1), (1.0, 0.01),
+                                   (1.1e-3, 1e-3), (0.3, 1.0), (2e-4, 1e-3)])
+def test_finite_source_witt_mao_limit(oracle, u, rho):
+    """q -> 0 far from the planetary caustic: a uniform disk on a point lens
+    of mass m1 (Witt & Mao 1994, itself checked against radial quadrature)."""
+    s, q = 2.0, 1e-11
+    m1, m2, z1, z2 = pins.lens_setup(s, q)
+    e = np.sqrt(m1)
+    zeta = z1 + u * e * np.exp(-1.9j)
+    mag, err, ns, fl = oracle.finite_mag(s, q, [zeta.real], [zeta.imag], rho * e, oracle.JUDGE_TOL,
+                                         oracle.judge_cfg())
+    wm = pins.witt_mao(u, rho)
+    assert abs(wm - pins.disk_point_lens_radial(u, rho)) < 1e-10 * wm
+    assert abs(mag[0] / wm - 1) < 2e-7, (mag[0], wm)
+
+
+def test_limb_through_lens_is_flagged(oracle):
+    """Degenerate case: the limb passes exactly through the lens (u = rho),
+    where one limb point has a ring image.  The oracle must not return a
+    confident value: the error estimate or the flags must say so."""
+    s, q = 2.0, 1e-11
+    m1, m2, z1, z2 = pins.lens_setup(s, q)
+    e = np.sqrt(m1)
+    zeta = z1 + 0.1 * e * np.exp(-1.9j)
+    mag, err, ns, fl = oracle.finite_mag(s, q, [zeta.real], [zeta.imag], 0.1 * e, oracle.JUDGE_TOL,
+                                         oracle.judge_cfg())
+    wm = pins.witt_mao(0.1, 0.1)
+    assert (fl[0] & (oracle.FLAG_CAP | oracle.FLAG_ANOMALY)) or abs(mag[0] - wm) <= err[0]
+
+
+@pytest.mark.parametrize("case", [
+    (1.0, 0.1, 0.2 + 0.2j, 0.1, (-2.5, 2.5, -2.5, 2.5)),      # Fig. 2 example
+    (1.0, 1e-2, 0.02 + 0.01j, 0.02, (-1.8, 1.8, -1.8, 1.8)),  # resonant caustic crossing
+    (0.8, 5e-3, -0.45 + 0.12j, 0.03, (-2.2, 2.2, -2.2, 2.2)),
+])
+def test_finite_source_ray_shooting(oracle, case):
+    """Binary lens with caustic crossings: contour integration against brute-
+    force inverse ray shooting of the image area."""
+    s, q, zc, rho, box = case
+    mag, err, ns, fl = oracle.finite_mag(s, q, [zc.real], [zc.imag], rho, oracle.JUDGE_TOL,
+                                         oracle.judge_cfg())
+    area = pins.ray_shoot_area(s, q, zc, rho, box, n0=1024, depth=7)
+    ray = area / (np.pi * rho * rho)
+    assert abs(mag[0] / ray - 1) < 1e-5, (mag[0], ray)
+
+
+def test_fig2_topology(oracle):
+    """Fig. 2: the limb crosses the caustic twice, so limb samples with 3 and
+    with 5 real images both occur and exactly two count changes appear."""
+    g = GOLD["fig2_topology"]
+    s, q, rho = g["s"], g["q"], g["rho"]
+    zc = complex(*g["zeta"])
+    ns = []
+    for th in np.linspace(0, 2 * np.pi, 720, endpoint=False):
+        ns.append(oracle.images(s, q, zc + rho * np.exp(1j * th))["n"])
+    ns = np.array(ns)
+    changes = np.sum(ns != np.roll(ns, 1))
+    assert set(ns) == {3, 5} and changes == 2
+
+
+def test_fig1_zoom_centre_on_critical_curve(oracle):
+    """Fig. 1 caption: the zoom centre (0.5000595, 0.000535) is where real and
+    ghost images meet on the critical curve; with the centre-of-mass origin
+    it lies on the critical curve of s=0.5, q=1e-6 to 1e-8 (a frame shifted
+    to lens 1 would miss by 5e-7)."""
+    g = GOLD["fig1_coefficients"]
+    cc = pins.critical_curve(g["s"], g["q"], 40000)
+    Z = complex(*g["zoom_centre_image_plane"])
+    assert np.abs(cc - Z).min() < 5e-8
+
+
+def test_fig4_caustics_at_grid_centres(oracle):
+    """Fig. 4 caption: the source grids are centred on the planetary caustic
+    (s=0.5, s=3) and the resonant caustic (s=1); the caustics computed in
+    the centre-of-mass frame must lie at those centres."""
+    for c in GOLD["fig4_grid_centres"]["cases"]:
+        ca = pins.caustic(c["s"], c["q"], 8192)
+        cx, cy = c["centre"]
+        d = np.abs(ca - (cx + 1j * cy))
+        assert d.min() < 2e-3, (c, d.min())
+    # sharper: s=0.5 planetary caustic x-extent brackets -1.5, s=3 brackets 2.666
+    ca = pins.caustic(0.5, 1e-4, 8192)
+    pl = ca[(ca.real < -1.2) & (ca.imag > 0)]
+    assert pl.real.min() < -1.5 < pl.real.max() and pl.imag.min() < 0.035 < pl.imag.max()
+    ca = pins.caustic(3.0, 1e-4, 8192)
+    pl = ca[ca.real > 2.0]
+    assert pl.real.min() < 2.666 < pl.real.max()
+
+
+def test_convergence_order_point_lens(oracle):
+    """Uniform sampling without refinement: trapezium + mean parabolic
+    correction converges far faster than the trapezium order 2."""
+    s, q = 2.0, 1e-11
+    m1, m2, z1, z2 = pins.lens_setup(s, q)
+    e = np.sqrt(m1)
+    u, rho = 0.5, 0.1
+    zeta = z1 + u * e
+    exact = pins.witt_mao(u, rho)
+    errs = []
+    for N in (16, 32, 64, 128):
+        c = oracle.cfg(1e-30, n0=N, nnew=1, cap=N)
+        mag, err, ns, fl = oracle.finite_mag(s, q, [zeta.real], [zeta.imag], rho * e, 1e-30, c)
+        errs.append(abs(mag[0] / exact - 1))
+        assert err[0] >= abs(mag[0] - exact)  # the estimate is conservative
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 3.0), (errs, orders)
+
+
+def test_error_estimate_bounds_true_error(oracle):
+    """At the paper's 1e-4 tolerance the returned error bounds the true error
+    (judged by the tight-tolerance oracle run) on crossing and non-crossing
+    sources."""
+    cases = [(1.0, 0.1, 0.2 + 0.2j, 0.1), (1.0, 1e-3, 0.05 + 0.01j, 1e-3), (0.5, 1e-6, -1.49981640625 + 0.0035j, 1e-4),
+             (1.0, 1e-2, 0.02 + 0.01j, 0.02), (3.0, 1e-4, 2.666 + 0.0005j, 1e-4)]
+    for (s, q, zc, rho) in cases:
+        m, e, n, f = oracle.finite_mag(s, q, [zc.real], [zc.imag], rho, 1e-4)
+        mj, ej, nj, fj = oracle.finite_mag(s, q, [zc.real], [zc.imag], rho, oracle.JUDGE_TOL, oracle.judge_cfg())
+        assert abs(m[0] - mj[0]) <= e[0] + ej[0]
+        assert e[0] <= 1e-4 * m[0] or (f[0] & oracle.FLAG_CAP)
+        assert abs(m[0] / mj[0] - 1) < 1e-4
+
+
+def test_finite_source_symmetric_about_axis(oracle):
+    for (s, q, zc, rho) in [(1.0, 0.1, 0.2 + 0.2j, 0.1), (0.8, 5e-3, -0.45 + 0.12j, 0.03)]:
+        a = oracle.finite_mag(s, q, [zc.real], [zc.imag], rho, 1e-6, oracle.judge_cfg())[0][0]
+        b = oracle.finite_mag(s, q, [zc.real], [-zc.imag], rho, 1e-6, oracle.judge_cfg())[0][0]
+        assert abs(a / b - 1) < 2e-8
+
+
+def test_slope_detector_repairs_misjudged_ghosts(oracle):
+    """Sec. 2.4.2 and Fig. 3: with the residual detector deliberately made
+    blind (huge gap factor, so near-caustic ghost pairs are taken as real),
+    the slope detector must restore the correct magnification; without it
+    the result is badly wrong.  The planted mistake is in the oracle's
+    classification only."""
+    g = GOLD["fig1_coefficients"]
+    s, q, rho = g["s"], g["q"], g["rho"]
+    zc = complex(*g["zeta"])
+    good = oracle.finite_mag(s, q, [zc.real], [zc.imag], rho, 1e-6, oracle.judge_cfg())
+    c = oracle.judge_cfg()
+    c.kgap = 1e9
+    fixed = oracle.finite_mag(s, q, [zc.real], [zc.imag], rho, 1e-6, c)
+    c.slope = 0
+    broken = oracle.finite_mag(s, q, [zc.real], [zc.imag], rho, 1e-6, c)
+    assert fixed[3][0] & oracle.FLAG_SLOPE
+    assert abs(fixed[0][0] / good[0][0] - 1) < 1e-6
+    assert abs(broken[0][0] / good[0][0] - 1) > 1e-2
+
+
+def test_fig5_no_spikes(oracle):
+    """Fig. 5: at the two source positions where the comparison code spikes,
+    the magnification is smooth: it agrees with the mean of close neighbours
+    along the light curve to well within the curve's own curvature."""
+    g = GOLD["fig5_light_curve"]
+    s, q, rho, ty = g["s"], g["q"], g["rho"], g["theta_y"]
+    for tx in g["spike_theta_x"]:
+        xs = tx + np.array([-2e-6, 0.0, 2e-6])
+        mag = oracle.finite_mag(s, q, xs, np.full(3, ty), rho, 1e-6, oracle.judge_cfg())[0]
+        mid = 0.5 * (mag[0] + mag[2])
+        assert abs(mag[1] / mid - 1) < 2e-4, (tx, mag)
+
+
+def test_limb_darkening_annulus_algebra(oracle):
+    """Equal-area annuli of the linear law (readings): the combination of
+    nested-disk magnifications equals the annulus-weighted integral of the
+    point-lens magnification computed by radial quadrature, and tends to the
+    continuous limb-darkened integral as the number of annuli grows."""
+    u, rho, gam = 0.15, 0.1, 0.45
+    na = 10
+    mu_k = [pins.witt_mao(u, rho * np.sqrt(k / na)) for k in range(1, na + 1)]
+    got = oracle.ld_combine(gam, mu_k)
+    # direct: flux-weighted annulus sum from disk integrals
+    disk = [0.0] + [pins.disk_point_lens_radial(u, rho * np.sqrt(k / na)) * (k / na) for k in range(1, na + 1)]
+    num = den = 0.0
+    for k in range(1, na + 1):
+        x0, x1 = (k - 1) / na, k / na
+        Ik = 1 - gam + gam * ((1 - x0) ** 1.5 - (1 - x1) ** 1.5) / (x1 - x0)
+        num += Ik * (disk[k] - disk[k - 1])
+        den += Ik * (x1 - x0)
+    assert abs(got / (num / den) - 1) < 1e-9
+    # uniform source: Gamma = 0 gives the plain disk value
+    assert abs(oracle.ld_combine(0.0, mu_k) / mu_k[-1] - 1) < 1e-14
+    # many annuli approach the continuous law
+    fine = 400
+    mu_f = [pins.witt_mao(u, rho * np.sqrt(k / fine)) for k in range(1, fine + 1)]
+    coarse_err = abs(got - oracle.ld_combine(gam, mu_f))
+    assert coarse_err / got < 2e-3
+
+
+def test_trajectory_closed_form(oracle):
+    tau = np.linspace(-2, 2, 11)
+    zx, zy = oracle.trajectory(0.01, 0.5, tau)
+    np.testing.assert_allclose(zx ** 2 + zy ** 2, tau ** 2 + 0.01 ** 2, rtol=1e-14)
+    assert abs(zx[5] + 0.01 * np.sin(0.5)) < 1e-16 and abs(zy[5] - 0.01 * np.cos(0.5)) < 1e-16
