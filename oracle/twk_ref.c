@@ -194,6 +194,7 @@ typedef struct {
   cplx R[5];        /* residuals in the same order              */
   double J[5];      /* Jacobians in the same order               */
   int par[5];       /* parity sign(J) for the real images        */
+  double margin;    /* second-largest |R| over the noise level  */
   uint32_t flags;
 } images_t;
 
@@ -215,13 +216,17 @@ static cplx fsecond(const lens_t *L, cplx eta) {
 }
 
 /* READING of the residual detector (the paper states the principle only):
- * sort |R| in decreasing order.  The two largest are a ghost pair when the
- * second largest exceeds kgap times both the third largest and the
- * rounding scale sigma = 64 eps (|y| + |eta| + m1/|eta+s| + m2/|eta|) of
- * the roots with the three smallest residuals; otherwise all five are
- * real.  Equal length of the two largest (they must be opposite, since the
- * residuals sum to zero) is checked and a violation is flagged.  A decision
- * margin within a factor 30 of the gap is flagged as near-degenerate. */
+ * the five residuals sum to zero exactly, so a ghost pair shows as two
+ * residuals of equal length, opposite direction, standing far above the
+ * numerical noise of the solve.  The noise level is the largest of: the
+ * third-largest |R|, the rounding scale sigma = 64 eps (|y| + |eta| +
+ * m1/|eta+s| + m2/|eta|) of the three roots with the smallest residuals, and
+ * the computed |sum R| (which vanishes in exact arithmetic, so its value
+ * measures the rounding of this particular solve, coefficients included).
+ * The two largest residuals are a ghost pair when the second largest
+ * exceeds kgap times the noise; otherwise all five roots are real.  A
+ * violation of equal length is flagged; a margin within a factor 30 of
+ * kgap is flagged as near-degenerate. */
 static void classify(const lens_t *L, cplx y, const cplx r[5], double kgap,
                      images_t *out) {
   cplx R[5];
@@ -244,11 +249,13 @@ static void classify(const lens_t *L, cplx y, const cplx r[5], double kgap,
     }
     o[j + 1] = t;
   }
-  double noise = aR[o[2]];
+  cplx Rsum = R[0] + R[1] + R[2] + R[3] + R[4];
+  double noise = fmax(aR[o[2]], cabs(Rsum));
   for (int k = 2; k < 5; ++k)
     if (sig[o[k]] > noise) noise = sig[o[k]];
   double margin = aR[o[1]] / noise;
   int ghosts = margin > kgap;
+  out->margin = margin;
   out->flags = 0;
   if (margin > kgap / 30.0 && margin < kgap * 30.0)
     out->flags |= TWK_REF_FLAG_NEARDEGEN;
@@ -280,10 +287,32 @@ static void classify(const lens_t *L, cplx y, const cplx r[5], double kgap,
   if (psum != -1) out->flags |= TWK_REF_FLAG_ANOMALY;
 }
 
+/* Near the critical curve a real image is a near-double root of the
+ * quintic and the polynomial solve leaves it with errors far above
+ * rounding, correlated within the pair, so that the pair's residuals can
+ * mimic a ghost pair.  Real images solve the lens equation itself, so each
+ * root receives one Newton step on the lens equation (z' + conj(f')
+ * conj(z') = -F gives dz = (R - conj(f') conj(R))/J), kept only when the
+ * step is tiny (a root correction, <= 1e-8 (1 + |eta|)) and lowers |R|.
+ * A ghost has no nearby solution: its step is large and is refused. */
+static void polish_lens(const lens_t *L, cplx y, cplx r[5]) {
+  for (int k = 0; k < 5; ++k) {
+    cplx R = residual(L, y, r[k]);
+    cplx fp = fprime(L, r[k]);
+    double J = 1.0 - creal(fp * conj(fp));
+    cplx dz = (R - conj(fp) * conj(R)) / J;
+    double scale = fmin(cabs(r[k]), cabs(r[k] + L->s));
+    if (!(cabs(dz) <= 1e-8 * scale)) continue;
+    cplx cand = r[k] + dz;
+    if (cabs(residual(L, y, cand)) < 0.5 * cabs(R)) r[k] = cand;
+  }
+}
+
 static void solve_point(const lens_t *L, cplx y, double kgap, images_t *im) {
   cplx c[6], r[5];
   coeffs_refined(L, y, c);
   roots5(c, r);
+  polish_lens(L, y, r);
   classify(L, y, r, kgap, im);
 }
 
@@ -641,19 +670,33 @@ static piece_t interval_piece(const sample_t *a, const sample_t *b,
 
 /* ------------------------------------------------------------------ */
 /* Slope detector (Sec. 2.4.2).                                           */
-/* READING: at a change of the real-image count between adjacent samples, */
-/* D is the difference (+ minus -) of the left-over pair at the 5-image   */
-/* sample and G the ghost-pair difference at the 3-image sample.  The     */
-/* crossing is accepted when the two are perpendicular enough,            */
-/* |Re(conj(D) G)| <= cos(pi/4) |D| |G|.  Otherwise the pair is followed   */
-/* into the 5-image run; the first step at which consecutive pair         */
-/* differences are perpendicular marks the true crossing and the samples  */
-/* walked over are reclassified (their pair becomes a ghost pair).  When  */
-/* the run ends first, the whole run is reclassified (the piece deleted). */
+/* The detector acts only near caustics, where a ghost pair may pass the  */
+/* residual test as real.  READING: a 5-image sample is "suspect" when    */
+/* the two largest residuals still stand above the noise by more than     */
+/* SUSPECT (but below the gap factor); only suspect samples can be        */
+/* reclassified.  At a change of the real-image count next to a suspect   */
+/* 5-image sample, D is the difference (+ minus -) of the left-over pair  */
+/* at that sample and G the ghost-pair difference at the 3-image sample.  */
+/* The crossing is accepted when D and G are perpendicular enough,        */
+/* |Re(conj(D) G)| <= cos(pi/4) |D| |G|.  Otherwise the pair is followed  */
+/* into the 5-image run, demoting each suspect sample passed: the walk     */
+/* stops at the first step whose consecutive pair differences are         */
+/* perpendicular, or at the first non-suspect sample (the crossing lies    */
+/* there).  When the whole run is walked, the run is deleted.              */
+/* Pair differences below PAIR_FLOOR (1 + |z|) are below the resolution   */
+/* of near-double roots in binary64; the direction test is meaningless    */
+/* there and the crossing is accepted as found.                           */
 /* ------------------------------------------------------------------ */
-static int perp_enough(cplx D, cplx G) {
+#define SUSPECT 8.0
+#define PAIR_FLOOR 1e-7
+
+static int perp_enough(cplx D, cplx G, cplx zref) {
+  double floor_ = PAIR_FLOOR * (1.0 + cabs(zref));
+  if (cabs(D) < floor_ || cabs(G) < floor_) return 1;
   return fabs(dot(D, G)) <= 0.70710678118654752440 * cabs(D) * cabs(G);
 }
+
+static int suspect(const sample_t *sm) { return sm->im.n == 5 && sm->im.margin > SUSPECT; }
 
 static void reset_demotions(sample_t *sm, int nsm) {
   for (int i = 0; i < nsm; ++i) {
@@ -662,153 +705,83 @@ static void reset_demotions(sample_t *sm, int nsm) {
   }
 }
 
-/* ord: sorted sample indices, N of them (cyclic).  Returns number of
+/* follow the pair (cp, cn) of sample c0 to sample c1 through the 5<->5
+ * links (full image sets); returns 0 if the pair is lost */
+static int follow_pair(const sample_t *c0, const sample_t *c1, int *cp, int *cn) {
+  sample_t t0 = *c0, t1 = *c1;
+  t0.demote[0] = t0.demote[1] = t1.demote[0] = t1.demote[1] = -1;
+  links_t l2;
+  link_samples(&t0, &t1, &l2);
+  int np = -1, nn = -1;
+  for (int u = 0; u < l2.nlink; ++u) {
+    if (l2.la[u] == *cp) np = l2.lb[u];
+    if (l2.la[u] == *cn) nn = l2.lb[u];
+  }
+  if (np < 0 || nn < 0) return 0;
+  *cp = np;
+  *cn = nn;
+  return 1;
+}
+
+/* Walk from the boundary sample b (3 images) into the run: positions of
+ * the run are visited as run[0], run[step], ... (step = +1 entering at the
+ * start, -1 entering at the end).  Returns the number of samples demoted. */
+static int walk_run(sample_t *sm, const int *ord, int N, int kb, int first, int len,
+                    int from_start) {
+  int j0 = from_start ? 0 : len - 1;
+  int dj = from_start ? 1 : -1;
+  sample_t *b = &sm[ord[kb]];
+  sample_t *c = &sm[ord[(first + j0) % N]];
+  if (!suspect(c) || c->demote[0] >= 0) return 0;
+  links_t lk;
+  if (from_start) link_samples(b, c, &lk);
+  else link_samples(c, b, &lk);
+  int want = from_start ? 1 : -1;
+  if (lk.kind != want) return 0;
+  int cp = lk.cp, cn = lk.cn;
+  cplx D = c->im.z[cp] - c->im.z[cn];
+  cplx G = b->im.z[3] - b->im.z[4];
+  if (perp_enough(D, G, c->im.z[cp])) return 0;
+  int demoted = 0;
+  for (int j = j0; j >= 0 && j < len; j += dj) {
+    sample_t *cj = &sm[ord[(first + j) % N]];
+    if (cj->demote[0] >= 0) break;
+    cj->demote[0] = cp;
+    cj->demote[1] = cn;
+    cj->n_eff = 3;
+    ++demoted;
+    int jn = j + dj;
+    if (jn < 0 || jn >= len) break; /* whole run walked: deleted */
+    sample_t *cn1 = &sm[ord[(first + jn) % N]];
+    if (!suspect(cn1)) break;
+    int np = cp, nn = cn;
+    if (!follow_pair(cj, cn1, &np, &nn)) break;
+    cplx D1 = cn1->im.z[np] - cn1->im.z[nn];
+    if (perp_enough(cj->im.z[cp] - cj->im.z[cn], D1, cj->im.z[cp])) break;
+    cp = np;
+    cn = nn;
+  }
+  return demoted;
+}
+
+/* ord: sorted sample indices, N of them (cyclic).  Returns the number of
  * reclassified samples. */
 static int slope_detector(sample_t *sm, const int *ord, int N) {
   int changed = 0;
-  /* find a 3-image sample to anchor the cyclic walk */
   int anchor = -1;
   for (int i = 0; i < N; ++i)
     if (sm[ord[i]].im.n == 3) { anchor = i; break; }
   if (anchor < 0) return 0;
-  /* scan runs of 5-image samples in cyclic order starting after anchor */
   int i = 0;
   while (i < N) {
-    int pos = (anchor + i) % N;
-    if (sm[ord[pos]].im.n != 5) { ++i; continue; }
-    /* run from pos forward */
+    if (sm[ord[(anchor + i) % N]].im.n != 5) { ++i; continue; }
     int start = i, len = 0;
     while (i < N && sm[ord[(anchor + i) % N]].im.n == 5) { ++len; ++i; }
-    int k_in = (anchor + start - 1 + N) % N;  /* 3-image sample before  */
-    int k_out = (anchor + start + len) % N;   /* 3-image sample after   */
+    int k_in = (anchor + start - 1 + N) % N;
+    int k_out = (anchor + start + len) % N;
     int first = (anchor + start) % N;
-    /* entry boundary: pair created at run[0] */
-    int del_from = -1, del_to = -1;  /* run offsets to demote [from,to) */
-    {
-      links_t lk;
-      sample_t *a = &sm[ord[k_in]], *b = &sm[ord[first]];
-      link_samples(a, b, &lk);
-      if (lk.kind == 1) {
-        cplx D = b->im.z[lk.cp] - b->im.z[lk.cn];
-        cplx G = a->im.z[3] - a->im.z[4];
-        if (!perp_enough(D, G)) {
-          int cp = lk.cp, cn = lk.cn, j;
-          int found = -1;
-          for (j = 0; j + 1 < len; ++j) {
-            sample_t *c0 = &sm[ord[(first + j) % N]];
-            sample_t *c1 = &sm[ord[(first + j + 1) % N]];
-            links_t l2;
-            link_samples(c0, c1, &l2);
-            int np = -1, nn = -1;
-            for (int t = 0; t < l2.nlink; ++t) {
-              if (l2.la[t] == cp) np = l2.lb[t];
-              if (l2.la[t] == cn) nn = l2.lb[t];
-            }
-            if (np < 0 || nn < 0) break;
-            cplx D0 = c0->im.z[cp] - c0->im.z[cn];
-            cplx D1 = c1->im.z[np] - c1->im.z[nn];
-            if (perp_enough(D0, D1)) { found = j; break; }
-            cp = np; cn = nn;
-          }
-          if (found >= 0) { del_from = 0; del_to = found + 1; }
-          else { del_from = 0; del_to = len; }
-        }
-      }
-    }
-    int del2_from = -1, del2_to = -1;
-    if (!(del_from == 0 && del_to == len)) {
-      /* exit boundary: pair destroyed after run[len-1] */
-      links_t lk;
-      int last = (first + len - 1) % N;
-      sample_t *a = &sm[ord[last]], *b = &sm[ord[k_out]];
-      link_samples(a, b, &lk);
-      if (lk.kind == -1) {
-        cplx D = a->im.z[lk.cp] - a->im.z[lk.cn];
-        cplx G = b->im.z[3] - b->im.z[4];
-        if (!perp_enough(D, G)) {
-          int cp = lk.cp, cn = lk.cn;
-          int found = -1;
-          for (int j = len - 1; j - 1 >= 0; --j) {
-            sample_t *c0 = &sm[ord[(first + j) % N]];
-            sample_t *c1 = &sm[ord[(first + j - 1) % N]];
-            links_t l2;
-            link_samples(c0, c1, &l2);
-            int np = -1, nn = -1;
-            for (int t = 0; t < l2.nlink; ++t) {
-              if (l2.la[t] == cp) np = l2.lb[t];
-              if (l2.la[t] == cn) nn = l2.lb[t];
-            }
-            if (np < 0 || nn < 0) break;
-            cplx D0 = c0->im.z[cp] - c0->im.z[cn];
-            cplx D1 = c1->im.z[np] - c1->im.z[nn];
-            if (perp_enough(D0, D1)) { found = j; break; }
-            cp = np; cn = nn;
-          }
-          if (found >= 0) { del2_from = found; del2_to = len; }
-          else { del2_from = 0; del2_to = len; }
-        }
-      }
-    }
-    /* apply demotions: the walked pair of each reclassified sample is
-     * demoted.  The pair is re-identified per sample by following links
-     * from the boundary, as in the walk. */
-    for (int pass = 0; pass < 2; ++pass) {
-      int f = pass == 0 ? del_from : del2_from;
-      int t = pass == 0 ? del_to : del2_to;
-      if (f < 0) continue;
-      /* follow the pair from the boundary that triggered this pass */
-      links_t lk;
-      int cp, cn;
-      if (pass == 0) {
-        link_samples(&sm[ord[k_in]], &sm[ord[first]], &lk);
-        cp = lk.cp; cn = lk.cn;
-        for (int j = 0; j < t; ++j) {
-          sample_t *c0 = &sm[ord[(first + j) % N]];
-          if (c0->demote[0] < 0) {
-            c0->demote[0] = cp; c0->demote[1] = cn; c0->n_eff = 3; ++changed;
-          }
-          if (j + 1 >= t) break;
-          sample_t *c1 = &sm[ord[(first + j + 1) % N]];
-          links_t l2;
-          /* link with full image sets, ignoring demotions just applied */
-          int s0 = c0->demote[0], s1 = c0->demote[1];
-          c0->demote[0] = c0->demote[1] = -1;
-          link_samples(c0, c1, &l2);
-          c0->demote[0] = s0; c0->demote[1] = s1;
-          int np = -1, nn = -1;
-          for (int u = 0; u < l2.nlink; ++u) {
-            if (l2.la[u] == cp) np = l2.lb[u];
-            if (l2.la[u] == cn) nn = l2.lb[u];
-          }
-          if (np < 0 || nn < 0) break;
-          cp = np; cn = nn;
-        }
-      } else {
-        int last = (first + len - 1) % N;
-        link_samples(&sm[ord[last]], &sm[ord[k_out]], &lk);
-        cp = lk.cp; cn = lk.cn;
-        for (int j = len - 1; j >= f; --j) {
-          sample_t *c0 = &sm[ord[(first + j) % N]];
-          if (c0->demote[0] < 0) {
-            c0->demote[0] = cp; c0->demote[1] = cn; c0->n_eff = 3; ++changed;
-          }
-          if (j - 1 < f) break;
-          sample_t *c1 = &sm[ord[(first + j - 1) % N]];
-          links_t l2;
-          int s0 = c0->demote[0], s1 = c0->demote[1];
-          c0->demote[0] = c0->demote[1] = -1;
-          link_samples(c0, c1, &l2);
-          c0->demote[0] = s0; c0->demote[1] = s1;
-          int np = -1, nn = -1;
-          for (int u = 0; u < l2.nlink; ++u) {
-            if (l2.la[u] == cp) np = l2.lb[u];
-            if (l2.la[u] == cn) nn = l2.lb[u];
-          }
-          if (np < 0 || nn < 0) break;
-          cp = np; cn = nn;
-        }
-      }
-    }
+    changed += walk_run(sm, ord, N, k_in, first, len, 1);
+    changed += walk_run(sm, ord, N, k_out, first, len, 0);
   }
   return changed;
 }
