@@ -1,0 +1,369 @@
+// twk_device.h -- device numerics for the binary-lens hot path (gfx950).
+//
+// Paper: Wang, Wang & Dong, "Twinkle: A GPU-based binary-lens microlensing
+// code with contour integration method" (arXiv 2501.03322).
+//
+// Everything here runs per lane: one lane owns one point source (a source
+// centre, a stencil point or one limb sample).  Complex numbers are carried
+// as two doubles (or two floats for the mixed-precision root iterations).
+// Frame: lens-2 frame of Sec. 2.2, y = zeta - z2, eta = z - z2; lens 1 at -s.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace twk {
+
+// ---------------------------------------------------------------- complex
+struct c64 {
+  double x, y;
+};
+struct c32 {
+  float x, y;
+};
+
+__device__ __forceinline__ c64 cz(double x, double y) { return c64{x, y}; }
+__device__ __forceinline__ c64 operator+(c64 a, c64 b) { return c64{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c64 operator-(c64 a, c64 b) { return c64{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ c64 operator-(c64 a) { return c64{-a.x, -a.y}; }
+__device__ __forceinline__ c64 operator*(c64 a, c64 b) {
+  return c64{__builtin_fma(a.x, b.x, -a.y * b.y), __builtin_fma(a.x, b.y, a.y * b.x)};
+}
+__device__ __forceinline__ c64 operator*(double s, c64 a) { return c64{s * a.x, s * a.y}; }
+__device__ __forceinline__ c64 operator+(c64 a, double s) { return c64{a.x + s, a.y}; }
+__device__ __forceinline__ c64 operator-(c64 a, double s) { return c64{a.x - s, a.y}; }
+__device__ __forceinline__ c64 cconj(c64 a) { return c64{a.x, -a.y}; }
+__device__ __forceinline__ double cnorm(c64 a) { return __builtin_fma(a.x, a.x, a.y * a.y); }
+__device__ __forceinline__ double cabs64(c64 a) { return sqrt(cnorm(a)); }
+// a ^ b = Im(conj(a) b);  a . b = Re(conj(a) b)
+__device__ __forceinline__ double cwedge(c64 a, c64 b) { return __builtin_fma(a.x, b.y, -a.y * b.x); }
+__device__ __forceinline__ double cdot(c64 a, c64 b) { return __builtin_fma(a.x, b.x, a.y * b.y); }
+
+// Reciprocal of a positive double to full precision: hardware estimate plus
+// two Newton steps (each squares the relative error).  The quotients on the
+// hot path never need IEEE rounding, only full precision.
+__device__ __forceinline__ double rcp64(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = __builtin_fma(-a, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-a, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ c64 cinv(c64 b) {
+  double r = rcp64(cnorm(b));
+  return c64{b.x * r, -b.y * r};
+}
+__device__ __forceinline__ c64 cdiv(c64 a, c64 b) { return a * cinv(b); }
+
+__device__ __forceinline__ c32 operator+(c32 a, c32 b) { return c32{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c32 operator-(c32 a, c32 b) { return c32{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ c32 operator*(c32 a, c32 b) {
+  return c32{__builtin_fmaf(a.x, b.x, -a.y * b.y), __builtin_fmaf(a.x, b.y, a.y * b.x)};
+}
+__device__ __forceinline__ float cnorm(c32 a) { return __builtin_fmaf(a.x, a.x, a.y * a.y); }
+__device__ __forceinline__ c32 cinv(c32 b) {
+  float r = __builtin_amdgcn_rcpf(cnorm(b));
+  return c32{b.x * r, -b.y * r};
+}
+
+// ---------------------------------------------------------------- lens
+// Sec. 2.1: masses normalised by the total mass; m1 = 1/(1+q), m2 = q/(1+q);
+// lens 2 at z2 = s/(1+q) in the centre-of-mass frame.
+struct Lens {
+  double s, m1, m2, z2;
+};
+__device__ __forceinline__ Lens make_lens(double s, double q) {
+  double r = 1.0 / (1.0 + q);
+  return Lens{s, r, q * r, s * r};
+}
+
+// Sec. 2.2, Eq. method-transformed: the cancellation-free coefficients of
+// sum_i c_i eta^i = 0, with v_c = conj(y) + s, v_p = 1 + s conj(y).
+// Each coefficient is a sum of terms of the same order in q, so none of the
+// subtractions of the conventional form appears.
+__device__ __forceinline__ void coefficients(const Lens& L, c64 y, c64 c[6]) {
+  const double s = L.s, m2 = L.m2, ms = m2 * s;
+  const c64 yb = cconj(y);
+  const c64 iy = cz(0.0, y.y);
+  const c64 vc = yb + s;
+  const c64 vp = cz(1.0 + s * y.x, -s * y.y);
+  const double revp = 1.0 + s * y.x, revc = y.x + s, re1sy = 1.0 - s * y.x;
+  c[5] = -(yb * vc);
+  c[4] = ((yb * y) - 1.0 - 2.0 * s * yb) * vc + ms;
+  c[3] = (2.0 * y - s) * ((vp * vc) + 2.0 * iy - ms) + (4.0 * (cz(ms, 0.0) - y)) * iy;
+  c[2] = cz(revp * revp * revc, y.y * revp * re1sy) + (s * y.y * y.y) * ((s * vc) + 2.0) +
+         ms * (2.0 * (yb * (y - s)) - cz(1.0 - s * y.x, -s * y.y));
+  c[1] = ms * (((2.0 * y) + s) * vp + s * cz(-m2, 2.0 * s * y.y));
+  c[0] = (s * s * m2 * m2) * y;
+}
+
+// ---------------------------------------------------------------- roots
+// All five roots by the Aberth-Ehrlich simultaneous iteration (each root is
+// corrected by Newton's ratio deflated against the others), updating in
+// place (Gauss-Seidel order).  Warm starts come from a neighbouring limb
+// sample, cold starts from a circle.  The paper delegates this step to the
+// Skowron & Gould solver; any all-roots method of full precision serves.
+__device__ __forceinline__ void horner64(const c64 c[6], c64 x, c64& p, c64& d) {
+  p = c[5];
+  d = cz(0.0, 0.0);
+#pragma unroll
+  for (int k = 4; k >= 0; --k) {
+    d = d * x + p;
+    p = p * x + c[k];
+  }
+}
+
+__device__ __forceinline__ void cold_start(const c64 c[6], c64 r[5]) {
+  // circle of radius |c0/c5|^(1/5) (geometric mean of the root moduli)
+  double rad = pow(sqrt(cnorm(c[0]) / cnorm(c[5])), 0.2);
+  if (!(rad > 0.0) || !(rad < 1e30)) rad = 1.0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double a = 1.2566370614359172 * k + 0.7;
+    r[k] = cz(rad * cos(a), rad * sin(a));
+  }
+}
+
+// Returns the number of sweeps used (maxit + 1 when not converged).
+__device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
+  int it = 0;
+  for (; it < maxit; ++it) {
+    double worst = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      c64 p, d;
+      horner64(c, r[k], p, d);
+      c64 ratio = cdiv(p, d);
+      c64 rep = cz(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < 5; ++j)
+        if (j != k) rep = rep + cinv(r[k] - r[j]);
+      c64 w = cdiv(ratio, cz(1.0, 0.0) - ratio * rep);
+      double nw = cnorm(w);
+      if (!(nw < 1e300)) {  // vanishing derivative or coincident iterates
+        w = cz(-1e-3 * (1.0 + cabs64(r[k])), 7e-4 * (1.0 + cabs64(r[k])));
+        nw = 1.0;
+        worst = 1.0;
+      }
+      r[k] = r[k] - w;
+      double rel = nw / fmax(cnorm(r[k]), 1e-300);
+      worst = fmax(worst, rel);
+    }
+    if (worst < 1e-28) return it + 1;
+  }
+  return maxit + 1;
+}
+
+// Mixed precision: the bulk sweeps in FP32 from a start given in FP64,
+// then the FP64 sweeps above polish the result.
+__device__ inline int aberth32(const c64 c64c[6], c64 r64[5], int maxit) {
+  // scale the polynomial so that FP32 keeps its range: divide by c5
+  c64 inv5 = cinv(c64c[5]);
+  c32 c[6], r[5];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    c64 t = c64c[k] * inv5;
+    c[k] = c32{(float)t.x, (float)t.y};
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r[k] = c32{(float)r64[k].x, (float)r64[k].y};
+  int it = 0;
+  for (; it < maxit; ++it) {
+    float worst = 0.f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      c32 p = c[5], d = c32{0.f, 0.f};
+#pragma unroll
+      for (int j = 4; j >= 0; --j) {
+        d = d * r[k] + p;
+        p = p * r[k] + c[j];
+      }
+      c32 ratio = p * cinv(d);
+      c32 rep = c32{0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < 5; ++j)
+        if (j != k) rep = rep + cinv(r[k] - r[j]);
+      c32 w = ratio * cinv(c32{1.f, 0.f} - ratio * rep);
+      float nw = cnorm(w);
+      if (!(nw < 1e30f)) {
+        w = c32{1e-3f, -7e-4f};
+        nw = 1.f;
+        worst = 1.f;
+      }
+      r[k] = r[k] - w;
+      worst = fmaxf(worst, nw / fmaxf(cnorm(r[k]), 1e-30f));
+    }
+    if (worst < 1e-12f) break;
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r64[k] = cz((double)r[k].x, (double)r[k].y);
+  return it + 1;
+}
+
+// ---------------------------------------------------------------- images
+// Residual of a root (Sec. 2.4.1) in the lens-2 frame:
+//   R = y - eta + m1/(conj(eta) + s) + m2/conj(eta).
+// f(z) = m1/(z1-z) + m2/(z2-z) (Eq. jacobian): in this frame
+//   f'  = m1/(eta+s)^2 + m2/eta^2,  f'' = -2 m1/(eta+s)^3 - 2 m2/eta^3.
+struct Images {
+  c64 z[5];      // real images first, then the ghost pair
+  double J[5];
+  int n;         // 3 or 5
+  uint32_t par;  // bit k set: image k has positive parity
+  uint32_t flags;
+  double margin; // second-largest |R| over the noise level
+};
+
+enum : uint32_t {
+  F_POINT = 1u << 0,
+  F_CAP = 1u << 1,
+  F_ANOMALY = 1u << 2,
+  F_SLOPE = 1u << 3,
+  F_NONFINITE = 1u << 4,
+  F_NEARDEGEN = 1u << 5,
+};
+
+__device__ __forceinline__ c64 residual(const Lens& L, c64 y, c64 eta) {
+  const c64 eb = cconj(eta);
+  return y - eta + L.m1 * cinv(eb + L.s) + L.m2 * cinv(eb);
+}
+
+// Polish: near the critical curve a real image is a near-double root of the
+// quintic, and the polynomial solve leaves it with an error far above
+// rounding, correlated within the pair, so that the pair's residuals can
+// mimic a ghost pair.  Real images solve the lens equation itself: each
+// root gets one Newton step on it, dz = (R - conj(f') conj(R)) / J, kept
+// only when the step is tiny against the distance to the nearer lens
+// (<= 1e-8 min(|eta|, |eta + s|)) and at least halves |R|; a ghost has no
+// nearby solution and its step is refused.  On return R holds the residual
+// of each (possibly polished) root.
+__device__ inline void polish_lens(const Lens& L, c64 y, c64 r[5], c64 R[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const c64 e = r[k];
+    const c64 Rk = residual(L, y, e);
+    const c64 a1 = e + L.s;
+    const c64 fp = L.m1 * cinv(a1 * a1) + L.m2 * cinv(e * e);
+    const double J = 1.0 - cnorm(fp);
+    const c64 dz = (1.0 / J) * (Rk - cconj(fp) * cconj(Rk));
+    const double scale = fmin(cnorm(e), cnorm(a1));
+    R[k] = Rk;
+    if (cnorm(dz) <= 1e-16 * scale) {
+      const c64 cand = e + dz;
+      const c64 Rc = residual(L, y, cand);
+      if (cnorm(Rc) < 0.25 * cnorm(Rk)) {
+        r[k] = cand;
+        R[k] = Rc;
+      }
+    }
+  }
+}
+
+// Residual detector.  The five residuals sum to zero (Eqs. sum_r, sum_r2),
+// so a ghost pair shows as two residuals of equal length and opposite
+// direction standing far above the numerical noise of the solve.  Noise:
+// the largest of the third-largest |R|, the computed |sum R| (zero in exact
+// arithmetic, so it measures this solve's rounding, coefficients included)
+// and the rounding scale sigma = 64 eps (|y| + |eta| + m1/|eta+s| + m2/|eta|)
+// of the three other roots.  Ghosts: the second largest |R| exceeds KGAP
+// times the noise.  A margin within a factor 30 of KGAP is flagged
+// near-degenerate; a ghost pair of unequal length is flagged anomalous.
+constexpr double KGAP = 100.0;
+constexpr double EPS64 = 2.220446049250313e-16;
+
+__device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 R[5], Images& im) {
+  double aR[5], sg[5];
+  const double ay = cabs64(y);
+  c64 Rs = cz(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    aR[k] = cabs64(R[k]);
+    Rs = Rs + R[k];
+    const double ae = cabs64(r[k]);
+    sg[k] = 64.0 * EPS64 * (ay + ae + L.m1 / cabs64(r[k] + L.s) + L.m2 / ae);
+  }
+  int a = 0;
+#pragma unroll
+  for (int k = 1; k < 5; ++k)
+    if (aR[k] > aR[a]) a = k;
+  int b = a == 0 ? 1 : 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    if (k != a && aR[k] > aR[b]) b = k;
+  double noise = cabs64(Rs);
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    if (k != a && k != b) noise = fmax(noise, fmax(aR[k], sg[k]));
+  const double margin = aR[b] / noise;
+  const bool ghosts = margin > KGAP;
+  im.margin = margin;
+  im.flags = 0;
+  if (margin > KGAP / 30.0 && margin < KGAP * 30.0) im.flags |= F_NEARDEGEN;
+  int m = 0;
+  if (ghosts) {
+    if (fabs(aR[a] - aR[b]) > 0.1 * aR[a]) im.flags |= F_ANOMALY;
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      if (k != a && k != b) im.z[m++] = r[k];
+    im.z[3] = r[a];
+    im.z[4] = r[b];
+    im.n = 3;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) im.z[k] = r[k];
+    im.n = 5;
+  }
+  im.par = 0;
+  int psum = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    c64 a1 = im.z[k] + L.s;
+    c64 fp = L.m1 * cinv(a1 * a1) + L.m2 * cinv(im.z[k] * im.z[k]);
+    im.J[k] = 1.0 - cnorm(fp);
+    if (im.J[k] > 0.0) im.par |= 1u << k;
+    if (k < im.n) psum += im.J[k] > 0.0 ? 1 : -1;
+  }
+  if (psum != -1) im.flags |= F_ANOMALY;
+}
+
+// Roots -> polished roots, residuals and classification.
+__device__ inline void finish_images(const Lens& L, c64 y, c64 r[5], Images& im) {
+  c64 R[5];
+  polish_lens(L, y, r, R);
+  classify(L, y, r, R, im);
+}
+
+__device__ __forceinline__ double point_mag(const Images& im) {
+  double mu = 0.0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    if (k < im.n) mu += 1.0 / fabs(im.J[k]);
+  return mu;
+}
+
+// Full FP64 point solve from a cold start.
+__device__ inline void solve_point_cold(const Lens& L, c64 y, Images& im, int& iters) {
+  c64 c[6], r[5];
+  coefficients(L, y, c);
+  cold_start(c, r);
+  iters = aberth64(c, r, 200);
+  finish_images(L, y, r, im);
+}
+
+// Limb derivatives (Sec. 2.3, Eq. area_cal) for a real image at eta, with
+// zeta' = i rho e^{i theta}:
+//   z'      = (zeta' - conj(f') conj(zeta')) / J
+//   z' ^ z'' = (rho^2 + Im(z'^2 zeta' f'')) / J
+__device__ __forceinline__ void limb_derivs(const Lens& L, c64 eta, double J, c64 zp1, double rho,
+                                            c64& dz, double& w) {
+  c64 a1 = eta + L.s;
+  c64 ia1 = cinv(a1), ie = cinv(eta);
+  c64 ia2 = ia1 * ia1, ie2 = ie * ie;
+  c64 fp = L.m1 * ia2 + L.m2 * ie2;
+  c64 fpp = -2.0 * (L.m1 * (ia2 * ia1) + L.m2 * (ie2 * ie));
+  double iJ = 1.0 / J;
+  dz = iJ * (zp1 - cconj(fp) * cconj(zp1));
+  w = iJ * (rho * rho + ((dz * dz) * zp1 * fpp).y);
+}
+
+}  // namespace twk

@@ -1,0 +1,183 @@
+"""ctypes binding of libtwk.so (C ABI in include/twk.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Torch tensors supply device memory and the stream.
+The binding refuses to run when the library is missing: there is no CPU
+fallback.
+"""
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtwk.so")
+
+OK, EINVAL, EDEVICE, ENOMEM, ENOMLP = 0, -1, -2, -3, -4
+MODE_FP64 = 0
+MODE_MIXED = 1 << 0
+MODE_MLP = 1 << 2
+MODE_ALL_FS = 1 << 3
+
+FLAG_POINT = 1 << 0
+FLAG_CAP = 1 << 1
+FLAG_ANOMALY = 1 << 2
+FLAG_SLOPE = 1 << 3
+FLAG_NONFINITE = 1 << 4
+FLAG_NEARDEGEN = 1 << 5
+
+EXPORTS = ("twk_create", "twk_destroy", "twk_sync", "twk_last_hip_error", "twk_strerror",
+           "twk_point_mag", "twk_finite_mag", "twk_lightcurves", "twk_last_stats",
+           "twk_enable_timing", "twk_kernel_times")
+
+_lib = None
+_vp = C.c_void_p
+
+
+class TwkError(RuntimeError):
+    def __init__(self, status, what, hip=0):
+        self.status = status
+        super().__init__(f"{what} failed: {status} ({strerror(status)}), hip error {hip}")
+
+
+def load():
+    """Load libtwk.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2501_03322_amd/build.py "
+                          "(there is no fallback path)")
+    L = C.CDLL(LIB_PATH)
+    L.twk_create.argtypes = [C.POINTER(_vp), C.c_int, _vp]
+    L.twk_destroy.argtypes = [_vp]
+    L.twk_sync.argtypes = [_vp]
+    L.twk_last_hip_error.argtypes = [_vp]
+    L.twk_strerror.argtypes = [C.c_int]
+    L.twk_strerror.restype = C.c_char_p
+    L.twk_point_mag.argtypes = [_vp, C.c_double, C.c_double, C.c_int64, _vp, _vp, _vp, _vp, _vp]
+    L.twk_finite_mag.argtypes = [_vp, C.c_double, C.c_double, C.c_int64, _vp, _vp, C.c_double,
+                                 C.c_double, C.c_uint32, _vp, _vp, _vp, _vp]
+    L.twk_lightcurves.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int64, _vp,
+                                  C.c_int32, C.c_double, C.c_uint32, _vp, _vp, _vp, _vp]
+    L.twk_last_stats.argtypes = [_vp, C.POINTER(C.c_int64)]
+    L.twk_enable_timing.argtypes = [_vp, C.c_int]
+    L.twk_kernel_times.argtypes = [_vp, C.POINTER(C.c_double)]
+    for f in ("twk_create", "twk_destroy", "twk_sync", "twk_last_hip_error", "twk_point_mag",
+              "twk_finite_mag", "twk_lightcurves", "twk_last_stats", "twk_enable_timing",
+              "twk_kernel_times"):
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def strerror(status):
+    return load().twk_strerror(status).decode()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("arrays must be device tensors")
+    if not t.is_contiguous():
+        raise ValueError("arrays must be contiguous")
+    return t.data_ptr()
+
+
+def _dev(x, device, dtype=torch.float64):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(x, dtype=dtype, device=device).contiguous()
+
+
+class Context:
+    """A library context bound to one device and one stream."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = _vp()
+        rc = self.lib.twk_create(C.byref(h), device, _vp(stream.cuda_stream))
+        if rc:
+            raise TwkError(rc, "twk_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.twk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc:
+            raise TwkError(rc, what, self.lib.twk_last_hip_error(self.h))
+
+    def sync(self):
+        self._check(self.lib.twk_sync(self.h), "twk_sync")
+
+    def stats(self):
+        out = (C.c_int64 * 8)()
+        self._check(self.lib.twk_last_stats(self.h, out), "twk_last_stats")
+        return dict(fs_tasks=out[0], full_cap_reruns=out[1], samples=out[2], waves=out[3],
+                    sweeps32=out[4], sweeps64=out[5], intervals=out[6], runs=out[7])
+
+    def enable_timing(self, on=True):
+        self._check(self.lib.twk_enable_timing(self.h, 1 if on else 0), "twk_enable_timing")
+
+    def kernel_times(self):
+        out = (C.c_double * 4)()
+        self._check(self.lib.twk_kernel_times(self.h, out), "twk_kernel_times")
+        return dict(ps_ms=out[0], fs_ms=out[1], fs_full_cap_ms=out[2], total_ms=out[3])
+
+    def point_mag(self, s, q, zx, zy):
+        zx = _dev(zx, self.device)
+        zy = _dev(zy, self.device)
+        n = zx.numel()
+        mag = torch.empty(n, dtype=torch.float64, device=self.device)
+        nimg = torch.empty(n, dtype=torch.int32, device=self.device)
+        fl = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._check(self.lib.twk_point_mag(self.h, s, q, n, _ptr(zx), _ptr(zy), _ptr(mag),
+                                           _ptr(nimg), _ptr(fl)), "twk_point_mag")
+        return mag, nimg, fl
+
+    def finite_mag(self, s, q, zx, zy, rho, tol, mode=MODE_FP64, out=None):
+        zx = _dev(zx, self.device)
+        zy = _dev(zy, self.device)
+        n = zx.numel()
+        if out is None:
+            out = self.alloc_out(n)
+        mag, err, ns, fl = out
+        self._check(self.lib.twk_finite_mag(self.h, s, q, n, _ptr(zx), _ptr(zy), rho, tol, mode,
+                                            _ptr(mag), _ptr(err), _ptr(ns), _ptr(fl)),
+                    "twk_finite_mag")
+        return out
+
+    def alloc_out(self, n):
+        return (torch.empty(n, dtype=torch.float64, device=self.device),
+                torch.empty(n, dtype=torch.float64, device=self.device),
+                torch.empty(n, dtype=torch.int32, device=self.device),
+                torch.empty(n, dtype=torch.int32, device=self.device))
+
+    def lightcurves(self, s, q, u0, alpha, rho, tau, tol, mode=MODE_FP64, gamma=None,
+                    n_annuli=1, out=None):
+        s, q, u0, alpha, rho = (_dev(a, self.device) for a in (s, q, u0, alpha, rho))
+        tau = _dev(tau, self.device)
+        g = None if gamma is None else _dev(gamma, self.device)
+        nsets, nep = s.numel(), tau.numel()
+        if out is None:
+            out = self.alloc_out(nsets * nep)
+        mag, err, ns, fl = out
+        self._check(self.lib.twk_lightcurves(self.h, nsets, _ptr(s), _ptr(q), _ptr(u0), _ptr(alpha),
+                                             _ptr(rho), _ptr(g), nep, _ptr(tau), n_annuli, tol, mode,
+                                             _ptr(mag), _ptr(err), _ptr(ns), _ptr(fl)),
+                    "twk_lightcurves")
+        return out

@@ -1,0 +1,192 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Gate (stated by the project): relative magnification error <= 1e-4 against
+the oracle run at a tight tolerance, image counts equal exactly except where
+either side flags a near-degenerate ghost/real decision.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GATE = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_03322_amd import twk
+    c = twk.Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+FS_CASES = [
+    # (s, q, zeta, rho)  caustic crossings, cusps, planetary and central caustics
+    (1.0, 0.1, 0.2 + 0.2j, 0.1),
+    (1.0, 1e-2, 0.02 + 0.01j, 0.02),
+    (0.8, 5e-3, -0.45 + 0.12j, 0.03),
+    (1.0, 1e-3, 0.05 + 0.01j, 1e-3),
+    (0.5, 1e-6, -1.49981640625 + 0.0035j, 1e-4),
+    (3.0, 1e-4, 2.666 + 0.0005j, 1e-4),
+    (0.5, 1e-4, -1.5 + 0.035j, 5e-5),
+    (1.0, 1e-4, 0.0 + 0.0j, 1e-3),
+    (0.5, 1e-6, -1.49998960 - 0.0035j, 1e-4),
+    (0.5, 1e-6, -1.49993410 - 0.0035j, 1e-4),
+    (2.0, 1e-9, 1.5 + 0.01j, 1e-3),
+]
+
+
+def test_point_mag_parity(ctx, oracle):
+    rng = np.random.default_rng(7)
+    for trial in range(6):
+        s = 10 ** rng.uniform(-0.5, 0.5)
+        q = 10 ** rng.uniform(-6, -1)
+        zx = rng.uniform(-1.5, 1.5, 4000)
+        zy = rng.uniform(-1.5, 1.5, 4000)
+        _log(f"point_mag s={s:.4g} q={q:.3g}")
+        mag, nimg, fl = ctx.point_mag(s, q, zx, zy)
+        rmag, rn, rfl = oracle.point_mag(s, q, zx, zy)
+        mag, nimg, fl = _np(mag), _np(nimg), _np(fl)
+        ok = ((fl & 32) == 0) & ((rfl & 32) == 0)
+        assert np.array_equal(nimg[ok], rn[ok])
+        np.testing.assert_allclose(mag[ok], rmag[ok], rtol=1e-10)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_finite_mag_cases(ctx, oracle, mode):
+    for (s, q, z, rho) in FS_CASES:
+        _log(f"finite case s={s} q={q} z={z} rho={rho} mode={mode}")
+        mag, err, ns, fl = ctx.finite_mag(s, q, [z.real], [z.imag], rho, 1e-4, mode | 8)
+        rm, re_, rn, rf = oracle.finite_mag(s, q, [z.real], [z.imag], rho, oracle.JUDGE_TOL,
+                                            oracle.judge_cfg())
+        m = _np(mag)[0]
+        assert abs(m / rm[0] - 1) <= GATE, (s, q, z, rho, m, rm[0])
+        assert _np(ns)[0] >= 64
+
+
+def _near_caustic_sources(s, q, rho, n, seed):
+    import pins
+    rng = np.random.default_rng(seed)
+    ca = pins.caustic(s, q, 2048)
+    pick = ca[rng.integers(0, ca.size, n)]
+    off = rho * rng.uniform(0, 2.0, n) * np.exp(2j * np.pi * rng.uniform(0, 1, n))
+    z = pick + off
+    return z.real.copy(), z.imag.copy()
+
+
+@pytest.mark.parametrize("lens", [(1.0, 1e-3, 1e-3), (0.7, 1e-4, 3e-4), (1.3, 3e-2, 5e-3),
+                                  (0.5, 1e-6, 1e-4), (2.5, 1e-5, 2e-4)])
+def test_finite_mag_near_caustics(ctx, oracle, lens):
+    s, q, rho = lens
+    zx, zy = _near_caustic_sources(s, q, rho, 96, seed=int(1e6 * q) % 1000 + 11)
+    for mode in (0, 1):
+        _log(f"near caustic s={s} q={q} rho={rho} mode={mode}")
+        mag, err, ns, fl = ctx.finite_mag(s, q, zx, zy, rho, 1e-4, mode | 8)
+        rm, re_, rn, rf = oracle.finite_mag(s, q, zx, zy, rho, oracle.JUDGE_TOL, oracle.judge_cfg())
+        rel = np.abs(_np(mag) / rm - 1)
+        assert rel.max() <= GATE, (lens, mode, rel.max(), int(rel.argmax()))
+
+
+def test_fp64_engine_follows_paper_sampler(ctx, oracle):
+    """The FP64 engine and the oracle's serial run of the same sampler
+    (64 initial, 64 per round, cap 4096) agree closely, and mostly use the
+    same number of samples."""
+    s, q, rho = 1.0, 1e-3, 1e-3
+    zx, zy = _near_caustic_sources(s, q, rho, 128, seed=5)
+    mag, err, ns, fl = ctx.finite_mag(s, q, zx, zy, rho, 1e-4, 8)
+    rm, re_, rn, rf = oracle.finite_mag(s, q, zx, zy, rho, 1e-4)
+    rel = np.abs(_np(mag) / rm - 1)
+    assert np.median(rel) < 1e-9
+    assert np.mean(_np(ns) == rn) > 0.8
+
+
+def test_lightcurve_single(ctx, oracle):
+    """One lens, 1000 epochs (s=1, q=1e-3, rho=1e-3, u0=0.01, alpha=0.5): the
+    full path (point-source test + contour) on every epoch."""
+    from paper_2501_03322_amd import inputs
+    c = inputs.single_curve()
+    zx, zy = oracle.trajectory(c.u0[0], c.alpha[0], c.tau)
+    rm, re_, rn, rf = oracle.finite_mag(c.s[0], c.q[0], zx, zy, c.rho[0], oracle.JUDGE_TOL,
+                                        oracle.judge_cfg())
+    for mode in (0, 1):
+        _log(f"single light curve mode={mode}")
+        mag, err, ns, fl = ctx.lightcurves(c.s, c.q, c.u0, c.alpha, c.rho, c.tau, 1e-4, mode)
+        rel = np.abs(_np(mag) / rm - 1)
+        assert rel.max() <= GATE, (mode, rel.max(), int(rel.argmax()))
+        ps = (_np(fl) & 1) != 0
+        dec = np.array([oracle.ps_adequate(c.s[0], c.q[0], complex(x, y), c.rho[0], 1e-4)[0]
+                        for x, y in zip(zx, zy)])
+        assert np.array_equal(ps, dec)
+
+
+def test_lightcurve_batch_sampled(ctx, oracle):
+    """The full fit-style batch (1024 sets x 2000 epochs) in one call, checked
+    on a stratified sample of epochs against the oracle one by one."""
+    from paper_2501_03322_amd import inputs
+    c = inputs.batched_curves()
+    _log("batch: 1024 x 2000")
+    mag, err, ns, fl = ctx.lightcurves(c.s, c.q, c.u0, c.alpha, c.rho, c.tau, 1e-4, 1)
+    mag, ns, fl = _np(mag), _np(ns), _np(fl)
+    assert np.all(np.isfinite(mag)) and np.all(mag >= 1.0 - 1e-9)
+    fs = np.nonzero((fl & 1) == 0)[0]
+    pt = np.nonzero((fl & 1) != 0)[0]
+    rng = np.random.default_rng(3)
+    pick = np.concatenate([rng.choice(fs, min(240, fs.size), replace=False),
+                           rng.choice(pt, min(160, pt.size), replace=False)])
+    worst = 0.0
+    for i in pick:
+        k, j = divmod(int(i), c.nepochs)
+        zx, zy = oracle.trajectory(c.u0[k], c.alpha[k], c.tau[j:j + 1])
+        rm, _, _, _ = oracle.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], oracle.JUDGE_TOL,
+                                        oracle.judge_cfg())
+        worst = max(worst, abs(mag[i] / rm[0] - 1))
+        assert abs(mag[i] / rm[0] - 1) <= GATE, (i, k, j, mag[i], rm[0])
+    _log(f"batch sampled worst rel {worst:.3g} fs={fs.size}")
+
+
+def test_edge_cases(ctx, oracle):
+    import torch
+    from paper_2501_03322_amd import twk
+    # empty input
+    out = ctx.finite_mag(1.0, 1e-3, [], [], 1e-3, 1e-4)
+    assert out[0].numel() == 0
+    # non-finite inputs are flagged and return NaN
+    mag, err, ns, fl = ctx.finite_mag(1.0, 1e-3, [np.nan, 0.1], [0.0, 0.0], 1e-3, 1e-4)
+    mag, fl = _np(mag), _np(fl)
+    assert np.isnan(mag[0]) and (fl[0] & twk.FLAG_NONFINITE)
+    assert np.isfinite(mag[1])
+    # invalid arguments
+    for bad in [dict(s=-1.0), dict(q=0.0), dict(rho=0.0), dict(tol=-1.0)]:
+        a = dict(s=1.0, q=1e-3, rho=1e-3, tol=1e-4)
+        a.update(bad)
+        with pytest.raises(twk.TwkError):
+            ctx.finite_mag(a["s"], a["q"], [0.1], [0.0], a["rho"], a["tol"])
+    with pytest.raises(twk.TwkError):
+        ctx.finite_mag(1.0, 1e-3, [0.1], [0.0], 1e-3, 1e-4, mode=1 << 20)
+    # extreme lenses of the robust domain (0.1 <= s <= 10, q >= 1e-9)
+    for (s, q, z, rho) in [(0.1, 1e-9, 0.01 + 0.001j, 1e-3), (10.0, 1e-9, 9.9 + 0.0j, 1e-3),
+                           (0.1, 0.5, 0.0 + 0.0j, 1e-2), (10.0, 1.0, 4.9 + 0.01j, 1e-2)]:
+        mag, err, ns, fl = ctx.finite_mag(s, q, [z.real], [z.imag], rho, 1e-4, 8)
+        rm = oracle.finite_mag(s, q, [z.real], [z.imag], rho, oracle.JUDGE_TOL, oracle.judge_cfg())[0]
+        assert abs(_np(mag)[0] / rm[0] - 1) <= GATE, (s, q, z)
+    torch.cuda.synchronize()
+
+
+def test_deterministic(ctx):
+    s, q, rho = 1.0, 1e-3, 1e-3
+    zx, zy = _near_caustic_sources(s, q, rho, 64, seed=9)
+    a = [_np(t).copy() for t in ctx.finite_mag(s, q, zx, zy, rho, 1e-4, 9)]
+    b = [_np(t).copy() for t in ctx.finite_mag(s, q, zx, zy, rho, 1e-4, 9)]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)

@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every symbol include/twk.h declares
+(CPU only: no compute call is made without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(twk_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_entry_points():
+    names = _declared("twk.h")
+    for must in ("twk_create", "twk_point_mag", "twk_finite_mag", "twk_lightcurves"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2501_03322_amd import twk
+    if not os.path.exists(twk.LIB_PATH):
+        pytest.skip("libtwk.so not built")
+    lib = ctypes.CDLL(twk.LIB_PATH)
+    for name in _declared("twk.h"):
+        assert hasattr(lib, name), name
+    assert set(twk.EXPORTS) <= set(_declared("twk.h"))
+
+
+def test_strerror_without_gpu():
+    from paper_2501_03322_amd import twk
+    if not os.path.exists(twk.LIB_PATH):
+        pytest.skip("libtwk.so not built")
+    assert twk.strerror(0) == "ok"
+    assert "invalid" in twk.strerror(-1)
+
+
+def test_binding_refuses_missing_library(monkeypatch, tmp_path):
+    from paper_2501_03322_amd import twk
+    monkeypatch.setattr(twk, "_lib", None)
+    monkeypatch.setattr(twk, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        twk.load()
