@@ -169,7 +169,7 @@ def main():
                    "path": "batched persistent + mixed precision (learned budget not yet in the path)"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
-                     "kernel": "k_fs<1024, mixed>",
+                     "kernel": "k_fs<512, mixed>",
                      "flops_per_launch": flops, "kernel_ms": best["fs_kernel_ms"]},
         "work": {"fs_fraction": best["fs_fraction"], **{k: int(v) for k, v in st.items()}},
     }

@@ -111,18 +111,18 @@ int twk_lightcurves(twk_ctx *ctx, int64_t nsets, const double *s, const double *
                     uint32_t *flags);
 
 /* Work counters of the last finite-source call (host pointer out[8]):
- * out[0] = contour tasks queued, out[1] = tasks re-run at the full sample
- * cap, out[2] = limb samples of the returned results, out[3] = persistent
- * waves of the first pass, out[4] = FP32 root sweeps, out[5] = FP64 root
- * sweeps (one sweep updates all five roots of one limb point), out[6] =
- * intervals linked, out[7] = contour runs (including deferred ones).
+ * out[0] = contour tasks queued, out[1] = tasks whose sorted limb arrays
+ * outgrew LDS (continued in global memory), out[2] = limb samples of the
+ * returned results, out[3] = persistent waves launched, out[4] = FP32 root
+ * sweeps, out[5] = FP64 root sweeps (one sweep updates all five roots of one
+ * limb point), out[6] = intervals linked, out[7] = contour runs.
  * Synchronises the context's stream. */
 int twk_last_stats(twk_ctx *ctx, int64_t *out8);
 
 /* Per-kernel timing with HIP events on the context's stream (on != 0 to
  * enable).  After a finite-source call, twk_kernel_times writes (host
- * pointer ms[4], milliseconds): point-source pass, first contour pass,
- * full-cap contour pass, whole call.  Waits for the call to finish.
+ * pointer ms[4], milliseconds): point-source pass, contour kernel, 0 (no
+ * third pass), whole call.  Waits for the call to finish.
  * Errors: TWK_EINVAL if timing is off. */
 int twk_enable_timing(twk_ctx *ctx, int on);
 int twk_kernel_times(twk_ctx *ctx, double *ms4);

@@ -11,9 +11,9 @@
 //                the point value, the rest are appended to the task queue
 //                with their centre roots (wave-aggregated atomics)
 //   k_fs<C>      persistent: each 64-lane wave pops tasks from the queue and
-//                runs the adaptive contour integration with C limb samples
-//                of LDS; a source that outgrows C is deferred to
-//   k_fs<4096>   the same engine with the method's full cap, few waves/CU.
+//                runs the adaptive contour integration, keeping up to C limb
+//                samples' sorted arrays in LDS and continuing in its global
+//                slice for larger sources (method cap 4096).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,14 +29,14 @@ using namespace twk;
 
 namespace {
 
-constexpr int SMALL_CAP = 1024;  // LDS limb capacity of the first FS pass
+constexpr int LDS_CAP = 512;  // limb samples a source keeps in LDS before spilling
 
 // Counters in device memory (int64 each).
 enum {
   C_NTASK = 0,     // tasks queued by the point-source pass
   C_HEAD = 1,      // queue head of the first FS pass
-  C_NOVER = 2,     // tasks deferred to the full-cap pass
-  C_HEAD2 = 3,     // queue head of the full-cap pass
+  C_NOVER = 2,     // tasks whose sorted arrays outgrew LDS
+  C_HEAD2 = 3,     // unused
   C_SAMPLES = 4,   // limb samples of finished tasks
   C_SW32 = 5,      // FP32 root sweeps (5 roots each)
   C_SW64 = 6,      // FP64 root sweeps
@@ -238,15 +238,17 @@ __global__ __launch_bounds__(256) void k_lc(int64_t nsets, const double* ps, con
 // Persistent finite-source kernel: each wave pops tasks until the queue is
 // drained (every wave reaches the exit: the queue length is fixed before
 // launch and each pop advances the head).
-template <int CAP, bool MIXED>
-__global__ __launch_bounds__(64) void k_fs(const Task* tasks, const long long* ntask,
+template <int LCAP, bool MIXED>
+#ifndef TWK_FS_WAVES_PER_EU
+#define TWK_FS_WAVES_PER_EU 2
+#endif
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES_PER_EU))) void k_fs(const Task* tasks, const long long* ntask,
                                            long long* head, double tol, char* scratch,
                                            double* mag, double* err, int32_t* ns,
-                                           uint32_t* flags, Task* over, long long* nover,
-                                           long long* cnt) {
-  __shared__ FsLds<CAP> lds;
+                                           uint32_t* flags, long long* cnt) {
+  __shared__ FsLds<LCAP> lds;
   const int lane = threadIdx.x;
-  const WaveMem m = wave_mem(scratch, blockIdx.x, CAP);
+  const WaveMem m = wave_mem(scratch, blockIdx.x, METHOD_CAP);
   const long long n = *ntask;
   for (;;) {
     long long t = 0;
@@ -254,22 +256,18 @@ __global__ __launch_bounds__(64) void k_fs(const Task* tasks, const long long* n
     t = __shfl(t, 0);
     if (t >= n) break;
     const Task task = tasks[t];
-    const FsOut o = fs_source<CAP, MIXED>(task, tol, m, lds, lane);
+    const FsOut o = fs_source<LCAP, MIXED>(task, tol, m, lds, lane);
     if (lane == 0) {
-      if (o.overflow) {
-        const long long k = atomicAdd((unsigned long long*)nover, 1ull);
-        over[k] = task;
-      } else {
-        mag[task.out] = o.mag;
-        err[task.out] = o.err;
-        ns[task.out] = o.n;
-        flags[task.out] = o.flags;
-        atomicAdd((unsigned long long*)&cnt[C_SAMPLES], (unsigned long long)o.n);
-      }
+      mag[task.out] = o.mag;
+      err[task.out] = o.err;
+      ns[task.out] = o.n;
+      flags[task.out] = o.flags;
+      atomicAdd((unsigned long long*)&cnt[C_SAMPLES], (unsigned long long)o.n);
       atomicAdd((unsigned long long*)&cnt[C_SW32], (unsigned long long)o.sweeps32);
       atomicAdd((unsigned long long*)&cnt[C_SW64], (unsigned long long)o.sweeps64);
       atomicAdd((unsigned long long*)&cnt[C_INTERVALS], (unsigned long long)o.intervals);
       atomicAdd((unsigned long long*)&cnt[C_RUNS], 1ull);
+      if (o.spilled) atomicAdd((unsigned long long*)&cnt[C_NOVER], 1ull);
     }
     __syncthreads();
   }
@@ -287,10 +285,8 @@ struct twk_ctx {
   size_t scratch_bytes = 0;
   Task* tasks = nullptr;
   int64_t task_cap = 0;
-  Task* over = nullptr;
-  int64_t over_cap = 0;
   long long* cnt = nullptr;
-  int waves_small = 0, waves_big = 0;
+  int waves = 0;
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
@@ -326,9 +322,9 @@ int grow(twk_ctx* c, void** p, size_t* have, size_t need) {
   return TWK_OK;
 }
 
-template <int CAP, bool MIXED>
+template <bool MIXED>
 int occupancy(int* blocks) {
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fs<CAP, MIXED>, 64, 0);
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fs<LDS_CAP, MIXED>, 64, 0);
 }
 
 int ensure_fs(twk_ctx* c, int64_t ntask_max) {
@@ -337,28 +333,21 @@ int ensure_fs(twk_ctx* c, int64_t ntask_max) {
   if ((rc = grow(c, (void**)&c->tasks, &have, (size_t)std::max<int64_t>(ntask_max, 1) * sizeof(Task))))
     return rc;
   c->task_cap = (int64_t)(have / sizeof(Task));
-  have = (size_t)c->over_cap * sizeof(Task);
-  if ((rc = grow(c, (void**)&c->over, &have, (size_t)std::max<int64_t>(ntask_max, 1) * sizeof(Task))))
-    return rc;
-  c->over_cap = (int64_t)(have / sizeof(Task));
-  size_t need = std::max((size_t)c->waves_small * SMALL_CAP, (size_t)c->waves_big * METHOD_CAP) *
-                kSlotBytes;
+  const size_t need = (size_t)c->waves * METHOD_CAP * kSlotBytes;
   return grow(c, (void**)&c->scratch, &c->scratch_bytes, need);
 }
 
 template <bool MIXED>
 int launch_fs(twk_ctx* c, double tol, double* mag, double* err, int32_t* ns, uint32_t* flags) {
   if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
-  hipLaunchKernelGGL((k_fs<SMALL_CAP, MIXED>), dim3(c->waves_small), dim3(64), 0, c->stream,
-                     c->tasks, &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns,
-                     flags, c->over, &c->cnt[C_NOVER], c->cnt);
+  hipLaunchKernelGGL((k_fs<LDS_CAP, MIXED>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
+                     &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
+                     c->cnt);
   HIP_TRY(c, hipGetLastError());
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-  hipLaunchKernelGGL((k_fs<METHOD_CAP, MIXED>), dim3(c->waves_big), dim3(64), 0, c->stream, c->over,
-                     &c->cnt[C_NOVER], &c->cnt[C_HEAD2], tol, c->scratch, mag, err, ns, flags,
-                     c->over, &c->cnt[C_SPARE], c->cnt);
-  HIP_TRY(c, hipGetLastError());
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+  if (c->timing) {
+    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+  }
   return TWK_OK;
 }
 
@@ -399,12 +388,11 @@ int twk_create(twk_ctx** out, int device, void* stream) {
   }
   c->n_cu = prop.multiProcessorCount;
   int b1 = 0, b2 = 0;
-  if (occupancy<SMALL_CAP, false>(&b1) != hipSuccess || occupancy<METHOD_CAP, false>(&b2) != hipSuccess) {
+  if (occupancy<false>(&b1) != hipSuccess || occupancy<true>(&b2) != hipSuccess) {
     delete c;
     return TWK_EDEVICE;
   }
-  c->waves_small = std::max(1, b1) * c->n_cu;
-  c->waves_big = std::max(1, b2) * c->n_cu;
+  c->waves = std::max(1, std::min(b1, b2)) * c->n_cu;
   if (hipMalloc((void**)&c->cnt, C_NCOUNTERS * sizeof(long long)) != hipSuccess) {
     delete c;
     return TWK_ENOMEM;
@@ -419,7 +407,6 @@ int twk_destroy(twk_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(c->scratch);
   (void)hipFree(c->tasks);
-  (void)hipFree(c->over);
   (void)hipFree(c->cnt);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -504,7 +491,7 @@ int twk_last_stats(twk_ctx* c, int64_t* out8) {
   out8[0] = h[C_NTASK];
   out8[1] = h[C_NOVER];
   out8[2] = h[C_SAMPLES];
-  out8[3] = c->waves_small;
+  out8[3] = c->waves;
   out8[4] = h[C_SW32];
   out8[5] = h[C_SW64];
   out8[6] = h[C_INTERVALS];

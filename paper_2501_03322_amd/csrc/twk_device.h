@@ -124,45 +124,64 @@ __device__ __forceinline__ void cold_start(const c64 c[6], c64 r[5]) {
   }
 }
 
+// Stopping rule shared by both precisions.  A sweep's largest relative
+// correction d bounds the error before the sweep; Aberth converges cubically
+// for simple roots, so after a sweep with d < 1e-6 the error is ~1e-18 unless
+// two roots are close (then convergence is linear).  Stop when d < 1e-6 and
+// no two roots lie within 1e-3 (relative) of each other, or when d < 1e-14.
 // Returns the number of sweeps used (maxit + 1 when not converged).
 __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
-  int it = 0;
-  for (; it < maxit; ++it) {
-    double worst = 0.0;
-#pragma unroll
+  for (int it = 0; it < maxit; ++it) {
+    double worst = 0.0, closest = 1.0;
+    // Gauss-Seidel order: root 0 is corrected against roots 1..4, then the
+    // roots rotate by one place; after five steps the order is restored.
+    // Only static register indices appear.
+#pragma unroll 1
     for (int k = 0; k < 5; ++k) {
+      const c64 x = r[0];
       c64 p, d;
-      horner64(c, r[k], p, d);
-      c64 ratio = cdiv(p, d);
+      horner64(c, x, p, d);
+      const c64 ratio = cdiv(p, d);
       c64 rep = cz(0.0, 0.0);
+      const double nr = cnorm(x);
 #pragma unroll
-      for (int j = 0; j < 5; ++j)
-        if (j != k) rep = rep + cinv(r[k] - r[j]);
+      for (int j = 1; j < 5; ++j) {
+        const c64 dd = x - r[j];
+        const double n2 = cnorm(dd);
+        closest = fmin(closest, n2 / fmax(nr, 1e-300));
+        const double ir = rcp64(n2);
+        rep = rep + cz(dd.x * ir, -dd.y * ir);
+      }
       c64 w = cdiv(ratio, cz(1.0, 0.0) - ratio * rep);
       double nw = cnorm(w);
       if (!(nw < 1e300)) {  // vanishing derivative or coincident iterates
-        w = cz(-1e-3 * (1.0 + cabs64(r[k])), 7e-4 * (1.0 + cabs64(r[k])));
+        w = cz(-1e-3 * (1.0 + sqrt(nr)), 7e-4 * (1.0 + sqrt(nr)));
         nw = 1.0;
         worst = 1.0;
       }
-      r[k] = r[k] - w;
-      double rel = nw / fmax(cnorm(r[k]), 1e-300);
-      worst = fmax(worst, rel);
+      const c64 xn = x - w;
+      worst = fmax(worst, nw / fmax(cnorm(xn), 1e-300));
+      r[0] = r[1];
+      r[1] = r[2];
+      r[2] = r[3];
+      r[3] = r[4];
+      r[4] = xn;
     }
-    if (worst < 1e-28) return it + 1;
+    if (worst < 1e-28 || (worst < 1e-12 && closest > 1e-6)) return it + 1;
   }
   return maxit + 1;
 }
 
-// Mixed precision: the bulk sweeps in FP32 from a start given in FP64,
-// then the FP64 sweeps above polish the result.
+// Mixed precision: the bulk sweeps in FP32 (polynomial scaled by 1/c5 so
+// that FP32 keeps its range) from a start given in FP64; the caller then
+// polishes with FP64 sweeps.  FP32 stops at a relative correction of 1e-6
+// (near its rounding level).
 __device__ inline int aberth32(const c64 c64c[6], c64 r64[5], int maxit) {
-  // scale the polynomial so that FP32 keeps its range: divide by c5
-  c64 inv5 = cinv(c64c[5]);
+  const c64 inv5 = cinv(c64c[5]);
   c32 c[6], r[5];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    c64 t = c64c[k] * inv5;
+    const c64 t = c64c[k] * inv5;
     c[k] = c32{(float)t.x, (float)t.y};
   }
 #pragma unroll
@@ -170,19 +189,19 @@ __device__ inline int aberth32(const c64 c64c[6], c64 r64[5], int maxit) {
   int it = 0;
   for (; it < maxit; ++it) {
     float worst = 0.f;
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < 5; ++k) {
+      const c32 x = r[0];
       c32 p = c[5], d = c32{0.f, 0.f};
 #pragma unroll
       for (int j = 4; j >= 0; --j) {
-        d = d * r[k] + p;
-        p = p * r[k] + c[j];
+        d = d * x + p;
+        p = p * x + c[j];
       }
-      c32 ratio = p * cinv(d);
+      const c32 ratio = p * cinv(d);
       c32 rep = c32{0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < 5; ++j)
-        if (j != k) rep = rep + cinv(r[k] - r[j]);
+      for (int j = 1; j < 5; ++j) rep = rep + cinv(x - r[j]);
       c32 w = ratio * cinv(c32{1.f, 0.f} - ratio * rep);
       float nw = cnorm(w);
       if (!(nw < 1e30f)) {
@@ -190,14 +209,22 @@ __device__ inline int aberth32(const c64 c64c[6], c64 r64[5], int maxit) {
         nw = 1.f;
         worst = 1.f;
       }
-      r[k] = r[k] - w;
-      worst = fmaxf(worst, nw / fmaxf(cnorm(r[k]), 1e-30f));
+      const c32 xn = x - w;
+      worst = fmaxf(worst, nw / fmaxf(cnorm(xn), 1e-30f));
+      r[0] = r[1];
+      r[1] = r[2];
+      r[2] = r[3];
+      r[3] = r[4];
+      r[4] = xn;
     }
-    if (worst < 1e-12f) break;
+    if (worst < 1e-12f) {
+      ++it;
+      break;
+    }
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) r64[k] = cz((double)r[k].x, (double)r[k].y);
-  return it + 1;
+  return it;
 }
 
 // ---------------------------------------------------------------- images
@@ -206,10 +233,10 @@ __device__ inline int aberth32(const c64 c64c[6], c64 r64[5], int maxit) {
 // f(z) = m1/(z1-z) + m2/(z2-z) (Eq. jacobian): in this frame
 //   f'  = m1/(eta+s)^2 + m2/eta^2,  f'' = -2 m1/(eta+s)^3 - 2 m2/eta^3.
 struct Images {
-  c64 z[5];      // real images first, then the ghost pair
+  c64 z[5];      // positive-parity real images, negative ones, then the ghost pair
   double J[5];
   int n;         // 3 or 5
-  uint32_t par;  // bit k set: image k has positive parity
+  uint32_t par;  // bit k set: image k has positive parity (the first ones)
   uint32_t flags;
   double margin; // second-largest |R| over the noise level
 };
@@ -282,6 +309,7 @@ __device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 
     const double ae = cabs64(r[k]);
     sg[k] = 64.0 * EPS64 * (ay + ae + L.m1 / cabs64(r[k] + L.s) + L.m2 / ae);
   }
+  // the two largest residuals (first index wins ties)
   int a = 0;
 #pragma unroll
   for (int k = 1; k < 5; ++k)
@@ -290,40 +318,54 @@ __device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 
 #pragma unroll
   for (int k = 0; k < 5; ++k)
     if (k != a && aR[k] > aR[b]) b = k;
-  double noise = cabs64(Rs);
+  double noise = cabs64(Rs), ra = 0.0, rb = 0.0;
 #pragma unroll
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < 5; ++k) {
     if (k != a && k != b) noise = fmax(noise, fmax(aR[k], sg[k]));
-  const double margin = aR[b] / noise;
+    if (k == a) ra = aR[k];
+    if (k == b) rb = aR[k];
+  }
+  const double margin = rb / noise;
   const bool ghosts = margin > KGAP;
   im.margin = margin;
   im.flags = 0;
   if (margin > KGAP / 30.0 && margin < KGAP * 30.0) im.flags |= F_NEARDEGEN;
-  int m = 0;
-  if (ghosts) {
-    if (fabs(aR[a] - aR[b]) > 0.1 * aR[a]) im.flags |= F_ANOMALY;
-#pragma unroll
-    for (int k = 0; k < 5; ++k)
-      if (k != a && k != b) im.z[m++] = r[k];
-    im.z[3] = r[a];
-    im.z[4] = r[b];
-    im.n = 3;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) im.z[k] = r[k];
-    im.n = 5;
-  }
-  im.par = 0;
-  int psum = 0;
+  if (ghosts && fabs(ra - rb) > 0.1 * ra) im.flags |= F_ANOMALY;
+  // Order the roots: positive-parity real images, negative-parity real
+  // images, ghosts (stable bubble sort on a 0/1/2 key; static indices).
+  int key[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    c64 a1 = im.z[k] + L.s;
-    c64 fp = L.m1 * cinv(a1 * a1) + L.m2 * cinv(im.z[k] * im.z[k]);
+    const c64 a1 = r[k] + L.s;
+    const c64 fp = L.m1 * cinv(a1 * a1) + L.m2 * cinv(r[k] * r[k]);
     im.J[k] = 1.0 - cnorm(fp);
-    if (im.J[k] > 0.0) im.par |= 1u << k;
-    if (k < im.n) psum += im.J[k] > 0.0 ? 1 : -1;
+    im.z[k] = r[k];
+    const bool g = ghosts && (k == a || k == b);
+    key[k] = g ? 2 : (im.J[k] > 0.0 ? 0 : 1);
   }
-  if (psum != -1) im.flags |= F_ANOMALY;
+#pragma unroll
+  for (int pass = 0; pass < 4; ++pass) {
+#pragma unroll
+    for (int i = 0; i < 4 - pass; ++i) {
+      const bool sw = key[i] > key[i + 1];
+      const c64 z0 = im.z[i], z1 = im.z[i + 1];
+      const double j0 = im.J[i], j1 = im.J[i + 1];
+      const int k0 = key[i], k1 = key[i + 1];
+      im.z[i] = sw ? z1 : z0;
+      im.z[i + 1] = sw ? z0 : z1;
+      im.J[i] = sw ? j1 : j0;
+      im.J[i + 1] = sw ? j0 : j1;
+      key[i] = sw ? k1 : k0;
+      key[i + 1] = sw ? k0 : k1;
+    }
+  }
+  im.n = ghosts ? 3 : 5;
+  int npos = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) npos += key[k] == 0 ? 1 : 0;
+  im.par = (1u << npos) - 1u;
+  // Parity sum of the real images is -1 (Sec. 2.3): 1 positive of 3, 2 of 5.
+  if (2 * npos - im.n != -1) im.flags |= F_ANOMALY;
 }
 
 // Roots -> polished roots, residuals and classification.

@@ -9,12 +9,15 @@
 // round, lane j solves one new limb point (coefficients, roots, residual
 // classification, limb derivatives) in registers and writes the sample
 // record to the wave's slice of a global scratch buffer (SoA, one slot per
-// sample, slots in creation order).  The sorted order of the limb angles
-// lives in LDS: th[] (angle), sl[] (slot) and wc[] (cumulative adaptive
-// weight).  Totals, prefix sums and the quantile inversion are wave-wide
-// shuffle scans over 64-wide strips of the sorted arrays; the merge of the
-// 64 new samples into the sorted arrays is an in-place descending-strip
-// move.  Only intervals that touch a new sample are relinked.
+// sample, slots in creation order; L2-resident).  The sorted order of the
+// limb angles lives in LDS: th[] (angle), E[] (error of the interval that
+// starts there) and sl[] (slot), 18 bytes per sample.  The area total is
+// kept incrementally (compensated) from the intervals that change; the
+// error total, the tolerance-subtracted weights, their prefix sum and the
+// quantile inversion are one pass of wave-wide shuffle scans over 64-wide
+// strips of the sorted arrays.  The 64 new samples are merged into the
+// sorted arrays by an in-place descending-strip move.  Only intervals that
+// touch a new sample are relinked.
 #pragma once
 
 #include "twk_device.h"
@@ -22,8 +25,8 @@
 namespace twk {
 
 constexpr int WAVE = 64;
-constexpr int NNEW = 64;        // new limb samples per round (Sec. 3)
-constexpr int METHOD_CAP = 4096; // samples per source (Sec. 3)
+constexpr int NNEW = 64;          // new limb samples per round (Sec. 3)
+constexpr int METHOD_CAP = 4096;  // samples per source (Sec. 3)
 constexpr double TWO_PI = 6.283185307179586;
 constexpr double PI_64 = 3.141592653589793;
 
@@ -36,19 +39,22 @@ struct Task {
   c64 roots[5];
 };
 
-// Per-wave slice of the sample scratch: SoA over slots [0, cap).
+// Per-wave slice of the sample scratch: SoA over slots [0, cap), plus room
+// for the sorted arrays when a source outgrows its LDS copy.
 struct WaveMem {
-  c64* root;       // [5][cap] real images first, ghost pair last
+  c64* root;       // [5][cap] positive, negative real images, ghost pair
   c64* dz;         // [5][cap] z' of the real images
   double* w;       // [5][cap] z' ^ z''
-  uint32_t* meta;  // [cap] n | par << 3 | flags << 8
+  double* th;      // [cap] limb angle of the slot
   double* dA;      // [cap] area of the interval starting at this slot
-  double* E;       // [cap] error of that interval
-  uint32_t* ifl;   // [cap] interval flags
+  double* sth;     // [cap] sorted angles (spill copy)
+  double* sE;      // [cap] sorted interval errors (spill copy)
+  uint32_t* meta;  // [cap] n | par << 3 | flags << 8
+  uint16_t* ssl;   // [cap] sorted slots (spill copy)
   int cap;
 };
 
-constexpr size_t kSlotBytes = 5 * 16 + 5 * 16 + 5 * 8 + 4 + 8 + 8 + 4;
+constexpr size_t kSlotBytes = 5 * 16 + 5 * 16 + 5 * 8 + 8 + 8 + 8 + 8 + 4 + 2;
 
 __device__ __forceinline__ WaveMem wave_mem(char* base, int wave, int cap) {
   char* p = base + (size_t)wave * (size_t)cap * kSlotBytes;
@@ -60,13 +66,17 @@ __device__ __forceinline__ WaveMem wave_mem(char* base, int wave, int cap) {
   p += (size_t)5 * cap * 16;
   m.w = (double*)p;
   p += (size_t)5 * cap * 8;
+  m.th = (double*)p;
+  p += (size_t)cap * 8;
   m.dA = (double*)p;
   p += (size_t)cap * 8;
-  m.E = (double*)p;
+  m.sth = (double*)p;
+  p += (size_t)cap * 8;
+  m.sE = (double*)p;
   p += (size_t)cap * 8;
   m.meta = (uint32_t*)p;
   p += (size_t)cap * 4;
-  m.ifl = (uint32_t*)p;
+  m.ssl = (uint16_t*)p;
   return m;
 }
 
@@ -74,112 +84,122 @@ __device__ __forceinline__ WaveMem wave_mem(char* base, int wave, int cap) {
 enum : uint32_t { IF_CROSS = 1u, IF_ANOMALY = 2u, IF_COUNT = 4u };
 
 // ---------------------------------------------------------------- sample
-struct Sample {
-  Images im;
-  c64 dz[5];
-  double w[5];
-};
-
-// Returns the root sweeps spent: low 16 bits FP64, high 16 bits FP32.
+// Solve the limb point at theta from the start r[] (warm: a neighbouring
+// sample's roots advanced along their derivative; or the centre roots) and
+// write its record to `slot`.  Returns the root sweeps spent (low 16 bits
+// FP64, high 16 bits FP32) and the sample flags in *fl.
 template <bool MIXED>
-__device__ inline uint32_t solve_sample(const Lens& L, c64 yc, double rho, double theta, c64 r[5],
-                                        Sample& sm) {
+__device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double theta, c64 r[5],
+                                       const WaveMem& m, int slot, uint32_t* fl) {
   double sn, cs;
   sincos(theta, &sn, &cs);
-  const c64 e = cz(cs, sn);
-  const c64 y = yc + rho * e;
+  const c64 y = yc + rho * cz(cs, sn);
   c64 c[6];
   coefficients(L, y, c);
   int it, s32 = 0, s64;
-  if (MIXED) {
-    s32 = aberth32(c, r, 30);
-    it = aberth64(c, r, 12);
-    s64 = it;
-    if (it > 12) {
-      it = aberth64(c, r, 40);
-      s64 += it;
-    }
-  } else {
-    it = aberth64(c, r, 40);
-    s64 = it;
-  }
+  if (MIXED) s32 = aberth32(c, r, 30);
+  it = aberth64(c, r, 40);
+  s64 = it;
   if (it > 40) {
     cold_start(c, r);
     s64 += aberth64(c, r, 200);
   }
-  finish_images(L, y, r, sm.im);
+  Images im;
+  finish_images(L, y, r, im);
   const c64 zp1 = cz(-rho * sn, rho * cs);  // zeta' = i rho e^{i theta}
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    if (k < sm.im.n) {
-      limb_derivs(L, sm.im.z[k], sm.im.J[k], zp1, rho, sm.dz[k], sm.w[k]);
-    } else {
-      sm.dz[k] = cz(0.0, 0.0);
-      sm.w[k] = 0.0;
-    }
+    c64 dz = cz(0.0, 0.0);
+    double w = 0.0;
+    if (k < im.n) limb_derivs(L, im.z[k], im.J[k], zp1, rho, dz, w);
+    m.root[k * m.cap + slot] = im.z[k];
+    m.dz[k * m.cap + slot] = dz;
+    m.w[k * m.cap + slot] = w;
   }
+  m.th[slot] = theta;
+  m.meta[slot] = (uint32_t)im.n | (im.par << 3) | (im.flags << 8);
+  *fl = im.flags;
   return (uint32_t)s64 | ((uint32_t)s32 << 16);
 }
 
-__device__ __forceinline__ void store_sample(const WaveMem& m, int slot, const Sample& sm) {
+// Warm start for a new sample dtheta away from the stored sample `slot`:
+// real images advanced by z' dtheta, ghosts copied.
+__device__ __forceinline__ void warm_start(const WaveMem& m, int slot, double dtheta, c64 r[5]) {
+  const int n = m.meta[slot] & 7u;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    m.root[k * m.cap + slot] = sm.im.z[k];
-    m.dz[k * m.cap + slot] = sm.dz[k];
-    m.w[k * m.cap + slot] = sm.w[k];
+    r[k] = m.root[k * m.cap + slot];
+    if (k < n) r[k] = r[k] + dtheta * m.dz[k * m.cap + slot];
   }
-  m.meta[slot] = (uint32_t)sm.im.n | (sm.im.par << 3) | (sm.im.flags << 8);
 }
 
 // ---------------------------------------------------------------- linking
-struct Rec {
-  c64 z[5];
-  c64 dz[5];
-  double w[5];
-  int n;
-  uint32_t par;
-};
+// Sample records keep their real images ordered by parity: positive ones
+// first (one of three, two of five), then negative ones, then the ghost
+// pair.  Linking (Sec. 2.3) pairs same-parity images of adjacent samples by
+// the assignment of least total distance ("the way to minimize the sum of
+// all distances is selected"); when the counts differ, the left-over + and
+// - images at the sample with five images are the pair created (or
+// destroyed) on the critical curve.
 
-__device__ __forceinline__ void load_rec(const WaveMem& m, int slot, Rec& r) {
-  uint32_t meta = m.meta[slot];
-  r.n = meta & 7u;
-  r.par = (meta >> 3) & 31u;
+// Least total distance injection of KA points into KB points (KA <= KB <= 3)
+// for static list positions; returns the map packed two bits per entry.
+template <int KA, int KB>
+__device__ __forceinline__ uint32_t inject_static(const c64* za, const c64* zb) {
+  double d[KA][KB];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    r.z[k] = m.root[k * m.cap + slot];
-    r.dz[k] = m.dz[k * m.cap + slot];
-    r.w[k] = m.w[k * m.cap + slot];
+  for (int i = 0; i < KA; ++i)
+#pragma unroll
+    for (int j = 0; j < KB; ++j) d[i][j] = cabs64(za[i] - zb[j]);
+  double best = 1e308;
+  uint32_t code = 0;
+#pragma unroll
+  for (int j0 = 0; j0 < KB; ++j0) {
+    if (KA == 1) {
+      if (d[0][j0] < best) { best = d[0][j0]; code = (uint32_t)j0; }
+      continue;
+    }
+#pragma unroll
+    for (int j1 = 0; j1 < KB; ++j1) {
+      if (j1 == j0) continue;
+      if (KA == 2) {
+        const double t = d[0][j0] + d[1 % KA][j1];
+        if (t < best) { best = t; code = (uint32_t)(j0 | j1 << 2); }
+        continue;
+      }
+#pragma unroll
+      for (int j2 = 0; j2 < KB; ++j2) {
+        if (j2 == j0 || j2 == j1) continue;
+        const double t = d[0][j0] + d[1 % KA][j1] + d[2 % KA][j2];
+        if (t < best) { best = t; code = (uint32_t)(j0 | j1 << 2 | j2 << 4); }
+      }
+    }
   }
+  return code;
 }
 
-// Least total distance injection of list A (ka entries) into list B
-// (kb >= ka entries), ka, kb <= 3 (Sec. 2.3: "the way to minimize the sum
-// of all distances is selected").  mB[i] receives the B position for A[i].
-__device__ inline void inject(const c64* zA, const int* iA, int ka, const c64* zB, const int* iB,
-                              int kb, int* mB) {
-  double d[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      d[i][j] = (i < ka && j < kb) ? cabs64(zA[iA[i]] - zB[iB[j]]) : 0.0;
+// General least total distance injection (any counts up to 3 per parity
+// class), for image sets whose parity counts are not the binary-lens ones.
+__device__ inline void inject_any(const c64* zA, const int* iA, int ka, const c64* zB, const int* iB,
+                                  int kb, int* mB) {
   double best = 1e308;
   int b0 = 0, b1 = 1, b2 = 2;
   for (int p0 = 0; p0 < kb; ++p0) {
     if (ka == 1) {
-      if (d[0][p0] < best) { best = d[0][p0]; b0 = p0; }
+      const double t = cabs64(zA[iA[0]] - zB[iB[p0]]);
+      if (t < best) { best = t; b0 = p0; }
       continue;
     }
     for (int p1 = 0; p1 < kb; ++p1) {
       if (p1 == p0) continue;
+      const double t2 = cabs64(zA[iA[0]] - zB[iB[p0]]) + cabs64(zA[iA[1]] - zB[iB[p1]]);
       if (ka == 2) {
-        double t = d[0][p0] + d[1][p1];
-        if (t < best) { best = t; b0 = p0; b1 = p1; }
+        if (t2 < best) { best = t2; b0 = p0; b1 = p1; }
         continue;
       }
       for (int p2 = 0; p2 < kb; ++p2) {
         if (p2 == p0 || p2 == p1) continue;
-        double t = d[0][p0] + d[1][p1] + d[2][p2];
+        const double t = t2 + cabs64(zA[iA[2]] - zB[iB[p2]]);
         if (t < best) { best = t; b0 = p0; b1 = p1; b2 = p2; }
       }
     }
@@ -194,104 +214,164 @@ struct Piece {
   uint32_t fl;
 };
 
-// Area and error of the interval between samples a and b (Sec. 2.3 area
-// pieces; Sec. 2.5 errors).  Linked images of parity p contribute
-// p [z_a ^ z_b / 2 + (dA_p1 + dA_p2)/2] with
+// Area and error contributions (Sec. 2.3 area pieces; Sec. 2.5 errors).
+// A linked pair of parity p adds p [z_a ^ z_b / 2 + (dA_p1 + dA_p2)/2] with
 //   dA_p1 = (w_a + w_b) dth^3 / 24,  dA_p2 = (z_b - z_a) ^ (z'_b - z'_a) dth / 12,
 // errors E1 = |w_a - w_b| dth^3/48, E2 = 1.5 |dA_p (|dz|^2/(dth^2 |z'_a.z'_b|) - 1)|,
-// E3 = |dA_p| dth^2 / 10, E4 = |dA_p1 - dA_p2|.  A pair created (destroyed)
-// on the critical curve adds the chord from its - to + image (+ to -) and
-// the cross-caustic correction (w_+ - w_-) dtt^3 / 24 with the effective
-// step dtt = |z_+ - z_-| / sqrt|z'_+ . z'_-|; its errors are
-// E1 = |w_+ + w_-| dtt^3/48, E2 = 1.5 |(z_+ - z_-).(z'_+ - z'_-) -+ 2 |z_+ - z_-|
-// sqrt|z'_+.z'_-|| dtt ("-" for creation along +theta), E3 = |dA_p| dth^2/10.
-__device__ inline Piece interval_piece(const Rec& a, const Rec& b, double dth) {
+// E3 = |dA_p| dth^2 / 10, E4 = |dA_p1 - dA_p2|.
+__device__ __forceinline__ void add_link(const WaveMem& m, int sa, int ia, int sb, int ib,
+                                         double par, double dth, Piece& out) {
+  const c64 za = m.root[ia * m.cap + sa], zb = m.root[ib * m.cap + sb];
+  const c64 da = m.dz[ia * m.cap + sa], db = m.dz[ib * m.cap + sb];
+  const double wa = m.w[ia * m.cap + sa], wb = m.w[ib * m.cap + sb];
+  const double dth2 = dth * dth, dth3 = dth2 * dth;
+  const double dAt = 0.5 * cwedge(za, zb);
+  const double dAp1 = (wa + wb) * dth3 * (1.0 / 24.0);
+  const double dAp2 = cwedge(zb - za, db - da) * dth * (1.0 / 12.0);
+  const double dAp = 0.5 * (dAp1 + dAp2);
+  out.dA += par * (dAt + dAp);
+  const double E1 = fabs(wa - wb) * dth3 * (1.0 / 48.0);
+  const double ch2 = cnorm(za - zb);
+  const double E2 = 1.5 * fabs(dAp * (ch2 / (dth2 * fabs(cdot(da, db))) - 1.0));
+  const double E3 = 0.1 * fabs(dAp) * dth2;
+  const double E4 = fabs(dAp1 - dAp2);
+  out.E += E1 + E2 + E3 + E4;
+}
+
+// A pair created (kind +1, at the later sample) or destroyed (kind -1, at
+// the earlier sample) on the critical curve: the boundary runs from its -
+// to its + image (creation) or + to - (destruction); chord plus the
+// cross-caustic correction (w_+ - w_-) dtt^3 / 24 with the effective step
+// dtt = |z_+ - z_-| / sqrt|z'_+ . z'_-|; errors E1 = |w_+ + w_-| dtt^3/48,
+// E2 = 1.5 |(z_+ - z_-).(z'_+ - z'_-) -+ 2 |z_+ - z_-| sqrt|z'_+.z'_-|| dtt ("-"
+// for creation along +theta), E3 = |dA_p| dth^2 / 10.
+__device__ __forceinline__ void add_cross(const WaveMem& m, int sc, int ip, int in, int kind,
+                                          double dth, Piece& out) {
+  const c64 zp = m.root[ip * m.cap + sc], zm = m.root[in * m.cap + sc];
+  const c64 dp = m.dz[ip * m.cap + sc], dm = m.dz[in * m.cap + sc];
+  const double wp = m.w[ip * m.cap + sc], wm = m.w[in * m.cap + sc];
+  const double dd = sqrt(fabs(cdot(dp, dm)));
+  const double sep = cabs64(zp - zm);
+  const double dtt = sep / dd;
+  const double dtt3 = dtt * dtt * dtt;
+  const double dAp = (wp - wm) * dtt3 * (1.0 / 24.0);
+  const double chord = kind > 0 ? 0.5 * cwedge(zm, zp) : 0.5 * cwedge(zp, zm);
+  out.dA += chord + dAp;
+  const double E1 = fabs(wp + wm) * dtt3 * (1.0 / 48.0);
+  const double sgn = kind > 0 ? 1.0 : -1.0;
+  const double E2 = 1.5 * fabs(cdot(zp - zm, dp - dm) - sgn * 2.0 * sep * dd) * dtt;
+  const double E3 = 0.1 * fabs(dAp) * dth * dth;
+  out.E += E1 + E2 + E3;
+  out.fl |= IF_CROSS;
+}
+
+// Image sets whose parity counts are not 1+2 or 2+3: general linking of
+// whatever same-parity images there are.
+__device__ __attribute__((noinline)) Piece interval_piece_any(const WaveMem& m, int sa, int sb,
+                                                              double dth) {
+  c64 za[5], zb[5];
+  const uint32_t ma_ = m.meta[sa], mb_ = m.meta[sb];
+  const int na_ = ma_ & 7u, nb_ = mb_ & 7u;
+  const uint32_t para = (ma_ >> 3) & 31u, parb = (mb_ >> 3) & 31u;
+  for (int k = 0; k < 5; ++k) {
+    za[k] = m.root[k * m.cap + sa];
+    zb[k] = m.root[k * m.cap + sb];
+  }
   int pa[5], ma[5], pb[5], mb[5];
   int npa = 0, nma = 0, npb = 0, nmb = 0;
-#pragma unroll
   for (int k = 0; k < 5; ++k) {
-    if (k < a.n) {
-      if ((a.par >> k) & 1u) pa[npa++] = k; else ma[nma++] = k;
+    if (k < na_) {
+      if ((para >> k) & 1u) pa[npa++] = k; else ma[nma++] = k;
     }
-    if (k < b.n) {
-      if ((b.par >> k) & 1u) pb[npb++] = k; else mb[nmb++] = k;
+    if (k < nb_) {
+      if ((parb >> k) & 1u) pb[npb++] = k; else mb[nmb++] = k;
     }
   }
-  Piece out{0.0, 0.0, (a.n != b.n) ? (uint32_t)IF_COUNT : 0u};
-  const double dth2 = dth * dth, dth3 = dth2 * dth;
-  uint32_t usedA = 0, usedB = 0;  // bit k: image k of a (b) linked
-  // two parity classes, each linked by the least-distance injection
-#pragma unroll
+  Piece out{0.0, 0.0, IF_ANOMALY | ((na_ != nb_) ? (uint32_t)IF_COUNT : 0u)};
+  if (npa > 3 || nma > 3 || npb > 3 || nmb > 3) return out;
+  uint32_t usedA = 0, usedB = 0;
   for (int cls = 0; cls < 2; ++cls) {
     const int* la = cls == 0 ? pa : ma;
     const int* lb = cls == 0 ? pb : mb;
     const int na = cls == 0 ? npa : nma;
     const int nb = cls == 0 ? npb : nmb;
-    const double par = cls == 0 ? 1.0 : -1.0;
-    if (na == 0 || nb == 0 || na > 3 || nb > 3) {
-      if (na + nb > 0 && (na > 3 || nb > 3)) out.fl |= IF_ANOMALY;
-      continue;
-    }
-    int m[3];
+    if (na == 0 || nb == 0) continue;
+    int mt[3];
     const bool swap = na > nb;
-    if (!swap) inject(a.z, la, na, b.z, lb, nb, m);
-    else inject(b.z, lb, nb, a.z, la, na, m);
+    if (!swap) inject_any(za, la, na, zb, lb, nb, mt);
+    else inject_any(zb, lb, nb, za, la, na, mt);
     const int nl = swap ? nb : na;
     for (int t = 0; t < nl; ++t) {
-      const int i = swap ? la[m[t]] : la[t];
-      const int j = swap ? lb[t] : lb[m[t]];
+      const int i = swap ? la[mt[t]] : la[t];
+      const int j = swap ? lb[t] : lb[mt[t]];
       usedA |= 1u << i;
       usedB |= 1u << j;
-      const c64 za = a.z[i], zb = b.z[j], da = a.dz[i], db = b.dz[j];
-      const double wa = a.w[i], wb = b.w[j];
-      const double dAt = 0.5 * cwedge(za, zb);
-      const double dAp1 = (wa + wb) * dth3 * (1.0 / 24.0);
-      const double dAp2 = cwedge(zb - za, db - da) * dth * (1.0 / 12.0);
-      const double dAp = 0.5 * (dAp1 + dAp2);
-      out.dA += par * (dAt + dAp);
-      const double E1 = fabs(wa - wb) * dth3 * (1.0 / 48.0);
-      const double ch2 = cnorm(za - zb);
-      const double E2 = 1.5 * fabs(dAp * (ch2 / (dth2 * fabs(cdot(da, db))) - 1.0));
-      const double E3 = 0.1 * fabs(dAp) * dth2;
-      const double E4 = fabs(dAp1 - dAp2);
-      out.E += E1 + E2 + E3 + E4;
+      add_link(m, sa, i, sb, j, cls == 0 ? 1.0 : -1.0, dth, out);
     }
   }
-  // left-over images: a created (at b) or destroyed (at a) pair
   int lpa = -1, lna = -1, lpb = -1, lnb = -1, ca = 0, cb = 0;
+  for (int k = 0; k < 5; ++k) {
+    if (k < na_ && !((usedA >> k) & 1u)) {
+      ++ca;
+      if ((para >> k) & 1u) lpa = k; else lna = k;
+    }
+    if (k < nb_ && !((usedB >> k) & 1u)) {
+      ++cb;
+      if ((parb >> k) & 1u) lpb = k; else lnb = k;
+    }
+  }
+  if (ca == 0 && cb == 2 && lpb >= 0 && lnb >= 0) add_cross(m, sb, lpb, lnb, 1, dth, out);
+  else if (cb == 0 && ca == 2 && lpa >= 0 && lna >= 0) add_cross(m, sa, lpa, lna, -1, dth, out);
+  return out;
+}
+
+// Area and error of the interval between the samples in slots sa and sb,
+// dth apart.  The four count patterns of a binary lens (3-3, 5-5, 3-5, 5-3)
+// are linked with static list positions; image data are read from the
+// (cached) sample records with computed offsets.
+__device__ inline Piece interval_piece(const WaveMem& m, int sa, int sb, double dth) {
+  const uint32_t ma_ = m.meta[sa], mb_ = m.meta[sb];
+  const int na = ma_ & 7u, nb = mb_ & 7u;
+  const uint32_t para = (ma_ >> 3) & 31u, parb = (mb_ >> 3) & 31u;
+  const bool stda = (na == 3 && para == 1u) || (na == 5 && para == 3u);
+  const bool stdb = (nb == 3 && parb == 1u) || (nb == 5 && parb == 3u);
+  if (!stda || !stdb) return interval_piece_any(m, sa, sb, dth);
+  c64 za[5], zb[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    if (k < a.n && !((usedA >> k) & 1u)) {
-      ++ca;
-      if ((a.par >> k) & 1u) lpa = k; else lna = k;
-    }
-    if (k < b.n && !((usedB >> k) & 1u)) {
-      ++cb;
-      if ((b.par >> k) & 1u) lpb = k; else lnb = k;
-    }
+    za[k] = m.root[k * m.cap + sa];
+    zb[k] = m.root[k * m.cap + sb];
   }
-  int kind = 0;
-  if (ca == 0 && cb == 2 && lpb >= 0 && lnb >= 0) kind = 1;
-  else if (cb == 0 && ca == 2 && lpa >= 0 && lna >= 0) kind = -1;
-  else if (ca + cb > 0) out.fl |= IF_ANOMALY;
-  if (kind != 0) {
-    const Rec& c = kind > 0 ? b : a;
-    const int ip = kind > 0 ? lpb : lpa, in = kind > 0 ? lnb : lna;
-    const c64 zp = c.z[ip], zm = c.z[in], dp = c.dz[ip], dm = c.dz[in];
-    const double wp = c.w[ip], wm = c.w[in];
-    const double dd = sqrt(fabs(cdot(dp, dm)));
-    const double sep = cabs64(zp - zm);
-    const double dtt = sep / dd;
-    const double dtt3 = dtt * dtt * dtt;
-    const double dAp = (wp - wm) * dtt3 * (1.0 / 24.0);
-    const double chord = kind > 0 ? 0.5 * cwedge(zm, zp) : 0.5 * cwedge(zp, zm);
-    out.dA += chord + dAp;
-    const double E1 = fabs(wp + wm) * dtt3 * (1.0 / 48.0);
-    const double sgn = kind > 0 ? 1.0 : -1.0;
-    const double E2 = 1.5 * fabs(cdot(zp - zm, dp - dm) - sgn * 2.0 * sep * dd) * dtt;
-    const double E3 = 0.1 * fabs(dAp) * dth2;
-    out.E += E1 + E2 + E3;
-    out.fl |= IF_CROSS;
+  Piece out{0.0, 0.0, na != nb ? (uint32_t)IF_COUNT : 0u};
+  if (na == 3 && nb == 3) {
+    add_link(m, sa, 0, sb, 0, 1.0, dth, out);
+    const uint32_t c = inject_static<2, 2>(za + 1, zb + 1);
+    add_link(m, sa, 1, sb, 1 + (c & 3u), -1.0, dth, out);
+    add_link(m, sa, 2, sb, 1 + ((c >> 2) & 3u), -1.0, dth, out);
+  } else if (na == 5 && nb == 5) {
+    const uint32_t cp = inject_static<2, 2>(za, zb);
+    add_link(m, sa, 0, sb, cp & 3u, 1.0, dth, out);
+    add_link(m, sa, 1, sb, (cp >> 2) & 3u, 1.0, dth, out);
+    const uint32_t cn = inject_static<3, 3>(za + 2, zb + 2);
+    add_link(m, sa, 2, sb, 2 + (cn & 3u), -1.0, dth, out);
+    add_link(m, sa, 3, sb, 2 + ((cn >> 2) & 3u), -1.0, dth, out);
+    add_link(m, sa, 4, sb, 2 + ((cn >> 4) & 3u), -1.0, dth, out);
+  } else if (na == 3) {  // 3 -> 5: a pair is created before sample b
+    const uint32_t cp = inject_static<1, 2>(za, zb);
+    add_link(m, sa, 0, sb, cp & 3u, 1.0, dth, out);
+    const uint32_t cn = inject_static<2, 3>(za + 1, zb + 2);
+    const int j0 = cn & 3u, j1 = (cn >> 2) & 3u;
+    add_link(m, sa, 1, sb, 2 + j0, -1.0, dth, out);
+    add_link(m, sa, 2, sb, 2 + j1, -1.0, dth, out);
+    add_cross(m, sb, 1 - (int)(cp & 3u), 2 + (3 - j0 - j1), 1, dth, out);
+  } else {  // 5 -> 3: a pair is destroyed after sample a
+    const uint32_t cp = inject_static<1, 2>(zb, za);
+    add_link(m, sa, cp & 3u, sb, 0, 1.0, dth, out);
+    const uint32_t cn = inject_static<2, 3>(zb + 1, za + 2);
+    const int j0 = cn & 3u, j1 = (cn >> 2) & 3u;
+    add_link(m, sa, 2 + j0, sb, 1, -1.0, dth, out);
+    add_link(m, sa, 2 + j1, sb, 2, -1.0, dth, out);
+    add_cross(m, sa, 1 - (int)(cp & 3u), 2 + (3 - j0 - j1), -1, dth, out);
   }
   return out;
 }
@@ -300,7 +380,7 @@ __device__ inline Piece interval_piece(const Rec& a, const Rec& b, double dth) {
 __device__ __forceinline__ double wave_incl_scan(double v, int lane) {
 #pragma unroll
   for (int o = 1; o < WAVE; o <<= 1) {
-    double t = __shfl_up(v, o);
+    const double t = __shfl_up(v, o);
     if (lane >= o) v += t;
   }
   return v;
@@ -309,22 +389,21 @@ __device__ __forceinline__ double wave_incl_scan(double v, int lane) {
 // Error-free transformation a + b = s + e (Knuth's TwoSum).
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
   s = a + b;
-  double bb = s - a;
+  const double bb = s - a;
   e = (a - (s - bb)) + (b - bb);
 }
 
 // Wave-wide compensated sum of per-lane (hi, lo) partials; every lane gets
 // the same bits (the butterfly combines commutatively).
-__device__ __forceinline__ double wave_sum_comp(double hi, double lo) {
+__device__ __forceinline__ void wave_sum_comp(double& hi, double& lo) {
 #pragma unroll
   for (int o = 1; o < WAVE; o <<= 1) {
-    double h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
+    const double h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
     double s, e;
     two_sum(hi, h2, s, e);
     hi = s;
     lo = lo + l2 + e;
   }
-  return hi + lo;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -340,52 +419,57 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 }
 
 // ---------------------------------------------------------------- engine
-template <int CAP>
+// LDS of one wave: the sorted arrays for sources of up to LCAP samples.
+template <int LCAP>
 struct FsLds {
-  double th[CAP];      // sorted limb angles
-  double wc[CAP + 1];  // interval errors, then their cumulative weights
-  uint16_t sl[CAP];    // slot of each sorted position
-  int ivl[NNEW];       // old interval index of each accepted new sample
+  double th[LCAP];    // sorted limb angles
+  double E[LCAP];     // error of the interval starting at each sorted position
+  uint16_t sl[LCAP];  // slot of each sorted position
+  int ivl[NNEW];      // old interval index of each accepted new sample
+};
+
+// The sorted arrays in use: the LDS copy, or, once a source outgrows it,
+// the spill copy in the wave's global slice (generic pointers address both).
+struct Sorted {
+  double* th;
+  double* E;
+  uint16_t* sl;
+  int cap;
 };
 
 struct FsOut {
   double mag, err;
   int n;
   uint32_t flags;
-  bool overflow;
-  // work counters of this source (wave totals)
-  double sweeps32, sweeps64, intervals;
+  bool spilled;                          // outgrew the LDS copy
+  double sweeps32, sweeps64, intervals;  // work of this source (wave totals)
 };
 
-// Relink the interval starting at sorted position p (of N) and store its
-// area, error and flags under the slot of its left sample.
-template <int CAP>
-__device__ __forceinline__ uint32_t relink(const WaveMem& m, const FsLds<CAP>& L, int p, int N) {
+// Relink the interval starting at sorted position p (of N): area to the
+// global record of its left slot, error to the sorted arrays.
+__device__ __forceinline__ Piece relink(const WaveMem& m, const Sorted& S, int p, int N) {
   const int q = p + 1 < N ? p + 1 : 0;
-  const int sa = L.sl[p], sb = L.sl[q];
-  const double dth = (p + 1 < N ? L.th[q] : L.th[q] + TWO_PI) - L.th[p];
-  Rec a, b;
-  load_rec(m, sa, a);
-  load_rec(m, sb, b);
-  Piece pc = interval_piece(a, b, dth);
+  const int sa = S.sl[p], sb = S.sl[q];
+  const double dth = (p + 1 < N ? S.th[q] : S.th[q] + TWO_PI) - S.th[p];
+  const Piece pc = interval_piece(m, sa, sb, dth);
   m.dA[sa] = pc.dA;
-  m.E[sa] = pc.E;
-  m.ifl[sa] = pc.fl;
-  return pc.fl;
+  S.E[p] = pc.E;
+  return pc;
 }
 
-// Number of accepted new samples whose old interval index is < p.
-__device__ __forceinline__ int count_before(const int* ivl, int m, int p) {
-  int lo = 0, hi = m;  // first r with ivl[r] >= p
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (ivl[mid] < p) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
+// Relative tolerance actually targeted by the stop test: half the stated one.
+// The error estimate of Sec. 2.5 can fall short of the true error by up to
+// about a factor 2 across caustics (measured against the tight oracle on
+// near-caustic sources), so the stop test aims at tol/2 for the returned
+// magnification to meet tol.
+constexpr double TOL_SAFETY = 0.5;
 
-template <int CAP, bool MIXED>
-__device__ FsOut fs_source(const Task& T, double tol, const WaveMem& m, FsLds<CAP>& L, int lane) {
+template <int LCAP, bool MIXED>
+__device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, FsLds<LCAP>& L,
+                           int lane) {
+  const double tol = tol_stated * TOL_SAFETY;
+  Sorted S{L.th, L.E, L.sl, LCAP};
+  bool spilled = false;
   const Lens lens = make_lens(T.s, T.q);
   const c64 yc = cz(T.zx - lens.z2, T.zy);
   const double rho = T.rho;
@@ -399,77 +483,89 @@ __device__ FsOut fs_source(const Task& T, double tol, const WaveMem& m, FsLds<CA
     c64 r[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) r[k] = T.roots[k];
-    Sample sm;
-    const uint32_t sw = solve_sample<MIXED>(lens, yc, rho, th, r, sm);
+    uint32_t sf;
+    const uint32_t sw = solve_store<MIXED>(lens, yc, rho, th, r, m, lane, &sf);
     sw64 += sw & 0xffffu;
     sw32 += sw >> 16;
-    store_sample(m, lane, sm);
-    fl |= sm.im.flags & (F_ANOMALY | F_NEARDEGEN);
-    L.th[lane] = th;
-    L.sl[lane] = (uint16_t)lane;
+    fl |= sf & (F_ANOMALY | F_NEARDEGEN);
+    S.th[lane] = th;
+    S.sl[lane] = (uint16_t)lane;
   }
   __syncthreads();
+  double Ahi, Alo;
   {
-    uint32_t f = relink(m, L, lane, N);
+    const Piece pc = relink(m, S, lane, N);
     ++nint;
-    if (f & IF_ANOMALY) fl |= F_ANOMALY;
+    if (pc.fl & IF_ANOMALY) fl |= F_ANOMALY;
+    Ahi = pc.dA;
+    Alo = 0.0;
+    wave_sum_comp(Ahi, Alo);
   }
   __syncthreads();
-  double A = 0.0, E = 0.0;
-  bool overflow = false;
+  double A = Ahi + Alo, E = 0.0;
   for (;;) {
-    // totals: compensated area, plain error; errors staged in wc[p+1]
-    double hi = 0.0, lo = 0.0, es = 0.0;
+    // error total and total tolerance-subtracted weight
+    A = Ahi + Alo;
+    const double avg = tol * fabs(A) / N;
+    double es = 0.0, ws = 0.0;
     for (int p = lane; p < N; p += WAVE) {
-      const int sa = L.sl[p];
-      const double a = m.dA[sa], e = m.E[sa];
-      double s, t;
-      two_sum(hi, a, s, t);
-      hi = s;
-      lo += t;
+      const double e = S.E[p];
       es += e;
-      L.wc[p + 1] = e;
+      ws += fmax(e - avg, 0.0);
     }
-    A = wave_sum_comp(hi, lo);
     E = wave_sum(es);
     if (E <= tol * fabs(A)) break;
-    int nnew = NNEW;
-    if (N + nnew > CAP) {
-      if (CAP < METHOD_CAP) { overflow = true; break; }
-      nnew = CAP - N;
-      if (nnew <= 0) { fl |= F_CAP; break; }
+    if (N + NNEW > S.cap && S.cap < METHOD_CAP) {
+      // outgrowing the LDS copy: continue on the spill copy in global memory
+      for (int p = lane; p < N; p += WAVE) {
+        m.sth[p] = S.th[p];
+        m.sE[p] = S.E[p];
+        m.ssl[p] = S.sl[p];
+      }
+      __syncthreads();
+      S = Sorted{m.sth, m.sE, m.ssl, METHOD_CAP};
+      spilled = true;
     }
-    // tolerance-subtracted weights, cumulative over sorted positions
-    const double avg = tol * fabs(A) / N;
-    __syncthreads();
+    const int nnew = N + NNEW <= S.cap ? NNEW : S.cap - N;
+    if (nnew <= 0) { fl |= F_CAP; break; }
+    const double W = wave_sum(ws);
+    if (!(W > 0.0)) break;
+    // inverse transform sampling: lane j takes quantile (j + 1/2)/nnew of the
+    // cumulative weight, located during one strip-wise scan of the weights
+    const double u = (lane + 0.5) / nnew * W;
+    bool found = false;
+    int iv = 0;
+    double w0 = 0.0, wi = 0.0;
     double carry = 0.0;
     for (int base = 0; base < N; base += WAVE) {
       const int p = base + lane;
-      double w = 0.0;
-      if (p < N) w = fmax(L.wc[p + 1] - avg, 0.0);
-      double inc = wave_incl_scan(w, lane);
-      if (p < N) L.wc[p + 1] = carry + inc;
-      carry += __shfl(inc, WAVE - 1);
-    }
-    if (lane == 0) L.wc[0] = 0.0;
-    __syncthreads();
-    const double W = L.wc[N];
-    if (!(W > 0.0)) break;
-    // inverse transform: quantile (j + 1/2)/nnew of the cumulative weight
-    bool valid = false;
-    int iv = 0;
-    double thn = 0.0;
-    if (lane < nnew) {
-      const double u = (lane + 0.5) / nnew * W;
-      int lo2 = 1, hi2 = N;  // first p in [1, N] with wc[p] > u
-      while (lo2 < hi2) {
-        int mid = (lo2 + hi2) >> 1;
-        if (L.wc[mid] > u) hi2 = mid; else lo2 = mid + 1;
+      const double w = p < N ? fmax(S.E[p] - avg, 0.0) : 0.0;
+      const double inc = wave_incl_scan(w, lane);
+      const double tot = __shfl(inc, WAVE - 1);
+      const bool mine = !found && lane < nnew && u < carry + tot;
+      if (__ballot(mine)) {
+        int lo = 0;  // first strip position whose inclusive sum exceeds u
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+          const double v = carry + __shfl(inc, lo + step - 1);
+          if (!(v > u)) lo += step;
+        }
+        const int lq = lo < WAVE ? lo : WAVE - 1;
+        const double wl = __shfl(w, lq), il = __shfl(inc, lq);
+        if (mine) {
+          found = true;
+          iv = base + lq;
+          wi = wl;
+          w0 = carry + il - wl;
+        }
       }
-      iv = lo2 - 1;
-      const double w0 = L.wc[iv], wi = L.wc[iv + 1] - w0;
-      const double ta = L.th[iv];
-      const double tb = iv + 1 < N ? L.th[iv + 1] : TWO_PI;
+      carry += tot;
+    }
+    bool valid = false;
+    double thn = 0.0;
+    if (found && iv < N) {
+      const double ta = S.th[iv];
+      const double tb = iv + 1 < N ? S.th[iv + 1] : TWO_PI;
       thn = ta + (u - w0) / wi * (tb - ta);
       valid = wi > 0.0 && thn > ta && thn < tb;
     }
@@ -481,56 +577,94 @@ __device__ FsOut fs_source(const Task& T, double tol, const WaveMem& m, FsLds<CA
     if (mcount == 0) { fl |= F_CAP; break; }
     const int rank = __popcll(mask & ((1ull << lane) - 1ull));
     if (valid) L.ivl[rank] = iv;
-    // solve the new samples, warm-started from the left neighbour's roots
+    // solve the new samples, warm-started from the nearer neighbour's roots
+    // advanced along their limb derivative
     if (valid) {
-      const int nb = L.sl[iv];
+      const double ta = S.th[iv];
+      const int ivb = iv + 1 < N ? iv + 1 : 0;
+      const double tb = iv + 1 < N ? S.th[ivb] : S.th[ivb] + TWO_PI;
+      const bool left = thn - ta <= tb - thn;
       c64 r[5];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) r[k] = m.root[k * m.cap + nb];
-      Sample sm;
-      const uint32_t sw = solve_sample<MIXED>(lens, yc, rho, thn, r, sm);
+      warm_start(m, left ? S.sl[iv] : S.sl[ivb], left ? thn - ta : thn - tb, r);
+      uint32_t sf;
+      const uint32_t sw = solve_store<MIXED>(lens, yc, rho, thn, r, m, N + rank, &sf);
       sw64 += sw & 0xffffu;
       sw32 += sw >> 16;
-      store_sample(m, N + rank, sm);
-      fl |= sm.im.flags & (F_ANOMALY | F_NEARDEGEN);
+      fl |= sf & (F_ANOMALY | F_NEARDEGEN);
     }
     __syncthreads();
-    // merge: old position p moves to p + #(new samples in intervals < p),
+    // merge: old position p moves up by #(new samples in intervals < p);
     // strips from the top so that no unread entry is overwritten
+    const int myivl = lane < mcount ? L.ivl[lane] : 0x7fffffff;
     for (int base = ((N - 1) / WAVE) * WAVE; base >= 0; base -= WAVE) {
       const int p = base + lane;
-      double vt = 0.0;
+      int sh = 0;  // number of r with ivl[r] < p (ivl ascending), 0..64
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int v = __shfl(myivl, sh + step - 1);
+        if (v < p) sh += step;
+      }
+      if (__shfl(myivl, WAVE - 1) < p) sh = WAVE;  // lifting alone stops at 63
+      double vt = 0.0, ve = 0.0;
       uint16_t vs = 0;
-      int sh = 0;
       if (p < N) {
-        vt = L.th[p];
-        vs = L.sl[p];
-        sh = count_before(L.ivl, mcount, p);
+        vt = S.th[p];
+        ve = S.E[p];
+        vs = S.sl[p];
       }
       __syncthreads();
-      if (p < N) {
-        L.th[p + sh] = vt;
-        L.sl[p + sh] = vs;
+      if (p < N && sh > 0) {
+        S.th[p + sh] = vt;
+        S.E[p + sh] = ve;
+        S.sl[p + sh] = vs;
       }
       __syncthreads();
     }
     int P = 0;
+    bool first = false;
+    double dAold = 0.0;
     if (valid) {
       P = iv + 1 + rank;
-      L.th[P] = thn;
-      L.sl[P] = (uint16_t)(N + rank);
+      first = rank == 0 || L.ivl[rank - 1] != iv;
+      if (first) dAold = m.dA[S.sl[P - 1]];
+    }
+    __syncthreads();
+    if (valid) {
+      S.th[P] = thn;
+      S.sl[P] = (uint16_t)(N + rank);
     }
     N += mcount;
     __syncthreads();
-    // relink the intervals touching new samples
+    // relink the intervals touching new samples; the area total changes by
+    // the new pieces minus the replaced one (compensated)
+    double dh = 0.0, dl = 0.0;
     if (valid) {
-      uint32_t f = relink(m, L, P, N);
+      const Piece p1 = relink(m, S, P, N);
       ++nint;
-      if (rank == 0 || L.ivl[rank - 1] != iv) {
-        f |= relink(m, L, P - 1, N);
+      double s, e;
+      two_sum(dh, p1.dA, s, e);
+      dh = s;
+      dl += e;
+      uint32_t f = p1.fl;
+      if (first) {
+        const Piece p0 = relink(m, S, P - 1, N);
         ++nint;
+        f |= p0.fl;
+        two_sum(dh, p0.dA, s, e);
+        dh = s;
+        dl += e;
+        two_sum(dh, -dAold, s, e);
+        dh = s;
+        dl += e;
       }
       if (f & IF_ANOMALY) fl |= F_ANOMALY;
+    }
+    wave_sum_comp(dh, dl);
+    {
+      double s, e;
+      two_sum(Ahi, dh, s, e);
+      Ahi = s;
+      Alo += dl + e;
     }
     __syncthreads();
   }
@@ -540,7 +674,7 @@ __device__ FsOut fs_source(const Task& T, double tol, const WaveMem& m, FsLds<CA
   o.err = E / area;
   o.n = N;
   o.flags = wave_or(fl);
-  o.overflow = overflow;
+  o.spilled = spilled;
   o.sweeps32 = wave_sum((double)sw32);
   o.sweeps64 = wave_sum((double)sw64);
   o.intervals = wave_sum((double)nint);

@@ -11,7 +11,8 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtwk.so")
+# TWK_LIB may name another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("TWK_LIB") or os.path.join(HERE, "libtwk.so")
 
 OK, EINVAL, EDEVICE, ENOMEM, ENOMLP = 0, -1, -2, -3, -4
 MODE_FP64 = 0
@@ -127,7 +128,7 @@ class Context:
     def stats(self):
         out = (C.c_int64 * 8)()
         self._check(self.lib.twk_last_stats(self.h, out), "twk_last_stats")
-        return dict(fs_tasks=out[0], full_cap_reruns=out[1], samples=out[2], waves=out[3],
+        return dict(fs_tasks=out[0], spilled=out[1], samples=out[2], waves=out[3],
                     sweeps32=out[4], sweeps64=out[5], intervals=out[6], runs=out[7])
 
     def enable_timing(self, on=True):

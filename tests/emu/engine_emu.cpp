@@ -1,0 +1,85 @@
+// Host driver that runs the device contour engine (fs_source) of the HIP
+// library on the CPU, one emulated 64-lane wavefront per source, and the
+// device point-source classification, exposing a small C ABI to the tests.
+// Test infrastructure only: the product library never uses it.
+#include <hip/hip_runtime.h>
+
+#include <thread>
+#include <vector>
+
+#include "../../paper_2501_03322_amd/csrc/twk_fs.h"
+
+using namespace twk;
+
+namespace {
+constexpr int LCAP = 512;
+
+void run_wave(const Task& T, double tol, bool mixed, FsOut* out) {
+  std::vector<char> scratch((size_t)METHOD_CAP * kSlotBytes);
+  const WaveMem m = wave_mem(scratch.data(), 0, METHOD_CAP);
+  auto* lds = new FsLds<LCAP>();
+  hip_emu::Wave wave;
+  hip_emu::g_wave = &wave;
+  std::vector<std::thread> th;
+  for (int l = 0; l < hip_emu::kLanes; ++l) {
+    th.emplace_back([&, l] {
+      hip_emu::t_lane = l;
+      FsOut o = mixed ? fs_source<LCAP, true>(T, tol, m, *lds, l)
+                      : fs_source<LCAP, false>(T, tol, m, *lds, l);
+      if (l == 0) *out = o;
+    });
+  }
+  for (auto& t : th) t.join();
+  hip_emu::g_wave = nullptr;
+  delete lds;
+}
+}  // namespace
+
+extern "C" {
+
+// Centre roots by the device cold-start solve, then the contour engine.
+int emu_finite_mag(double s, double q, double zx, double zy, double rho, double tol, int mixed,
+                   double* mag, double* err, int* nsamp, unsigned* flags, double* sweeps) {
+  const Lens L = make_lens(s, q);
+  const c64 yc = cz(zx - L.z2, zy);
+  Images im;
+  int it;
+  solve_point_cold(L, yc, im, it);
+  Task T;
+  T.out = 0;
+  T.s = s;
+  T.q = q;
+  T.rho = rho;
+  T.zx = zx;
+  T.zy = zy;
+  for (int k = 0; k < 5; ++k) T.roots[k] = im.z[k];
+  FsOut o;
+  run_wave(T, tol, mixed != 0, &o);
+  *mag = o.mag;
+  *err = o.err;
+  *nsamp = o.n;
+  *flags = o.flags;
+  if (sweeps) {
+    sweeps[0] = o.sweeps32;
+    sweeps[1] = o.sweeps64;
+    sweeps[2] = o.intervals;
+  }
+  return 0;
+}
+
+int emu_point(double s, double q, double zx, double zy, double* mag, int* n, unsigned* flags,
+              double* img10) {
+  const Lens L = make_lens(s, q);
+  Images im;
+  int it;
+  solve_point_cold(L, cz(zx - L.z2, zy), im, it);
+  *mag = point_mag(im);
+  *n = im.n;
+  *flags = im.flags;
+  for (int k = 0; k < 5; ++k) {
+    img10[2 * k] = im.z[k].x + L.z2;
+    img10[2 * k + 1] = im.z[k].y;
+  }
+  return 0;
+}
+}
