@@ -71,7 +71,7 @@ def run_path(ctx, dev, c, mode, steps, warmup, label):
         fs_ms.append(kt["fs_ms"])
         tot_ms.append(kt["total_ms"])
         log(f"[{label}] step {k + 1}/{steps}: {kt['total_ms']:.2f} ms (contour kernel {kt['fs_ms']:.2f} ms,"
-            f" full-cap pass {kt['fs_full_cap_ms']:.2f} ms, point pass {kt['ps_ms']:.2f} ms)")
+            f" point pass {kt['ps_ms']:.2f} ms, rest {kt['rest_ms']:.2f} ms)")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = ctx.stats()

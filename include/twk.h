@@ -98,20 +98,32 @@ int twk_finite_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *ze
  * alpha, rho, each of length nsets) times nepochs epochs tau (device array)
  * on straight trajectories zeta = (tau cos a - u0 sin a) + i (tau sin a +
  * u0 cos a), centre-of-mass frame.  gamma (length nsets, linear limb-
- * darkening coefficient) may be NULL for uniform sources; with gamma the
- * source is split into n_annuli equal-area annuli (n_annuli >= 1).
+ * darkening coefficient of I(r)/<I> = 1 - gamma (1 - 1.5 sqrt(1 - r^2/rho^2)))
+ * may be NULL for uniform sources (then n_annuli must be 1); with gamma the
+ * source is split into n_annuli (1..64) equal-area annuli whose uniform-disk
+ * magnifications are combined with the annulus mean intensities.
  * Outputs (device, length nsets*nepochs, set-major): mag, err, n_samples
  * (summed over annuli), flags.  Point-source-adequate epochs are answered
  * by the point value; all others by contour integration in one persistent
- * launch fed by a device work queue. */
+ * launch per chunk of parameter sets (a chunk holds at most 2^24 contour
+ * tasks) fed by a device work queue. */
 int twk_lightcurves(twk_ctx *ctx, int64_t nsets, const double *s, const double *q,
                     const double *u0, const double *alpha, const double *rho,
                     const double *gamma, int64_t nepochs, const double *tau, int32_t n_annuli,
                     double tol, uint32_t mode, double *mag, double *err, int32_t *n_samples,
                     uint32_t *flags);
 
+/* Magnification map of one lens: uniform disks of radius rho centred on the
+ * pixel centres of an nx x ny grid over the box [xc - width/2, xc + width/2]
+ * x [yc - height/2, yc + height/2] (centre-of-mass frame).  Outputs (device,
+ * length nx*ny, index iy*nx + ix): mag, err, n_samples, flags.  mode as for
+ * twk_finite_mag. */
+int twk_mag_map(twk_ctx *ctx, double s, double q, double rho, double xc, double yc, double width,
+                double height, int32_t nx, int32_t ny, double tol, uint32_t mode, double *mag,
+                double *err, int32_t *n_samples, uint32_t *flags);
+
 /* Work counters of the last finite-source call (host pointer out[8]):
- * out[0] = contour tasks queued, out[1] = tasks whose sorted limb arrays
+ * out[0] = contour tasks run, out[1] = tasks whose sorted limb arrays
  * outgrew LDS (continued in global memory), out[2] = limb samples of the
  * returned results, out[3] = persistent waves launched, out[4] = FP32 root
  * sweeps, out[5] = FP64 root sweeps (one sweep updates all five roots of one
@@ -121,8 +133,8 @@ int twk_last_stats(twk_ctx *ctx, int64_t *out8);
 
 /* Per-kernel timing with HIP events on the context's stream (on != 0 to
  * enable).  After a finite-source call, twk_kernel_times writes (host
- * pointer ms[4], milliseconds): point-source pass, contour kernel, 0 (no
- * third pass), whole call.  Waits for the call to finish.
+ * pointer ms[4], milliseconds): point-source pass and contour kernel of the
+ * first chunk, the rest of the call, whole call.  Waits for the call.
  * Errors: TWK_EINVAL if timing is off. */
 int twk_enable_timing(twk_ctx *ctx, int on);
 int twk_kernel_times(twk_ctx *ctx, double *ms4);

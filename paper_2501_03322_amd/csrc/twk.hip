@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -41,7 +42,8 @@ enum {
   C_SW32 = 5,      // FP32 root sweeps (5 roots each)
   C_SW64 = 6,      // FP64 root sweeps
   C_INTERVALS = 7, // intervals linked
-  C_RUNS = 8,      // FS runs (including those deferred and re-run)
+  C_RUNS = 8,      // contour runs
+  C_NFS = 9,       // limb-darkened epochs sent to the annulus contours
   C_SPARE = 15,
   C_NCOUNTERS = 16
 };
@@ -119,8 +121,12 @@ __device__ inline PsResult point_source_pass(const Lens& L, c64 yc, double rho, 
   return out;
 }
 
-__global__ void k_reset(long long* cnt) {
-  if (threadIdx.x < C_NCOUNTERS) cnt[threadIdx.x] = 0;
+// Clear all counters (start of a call) or only the queue counters (start of
+// a chunk of a call).
+__global__ void k_reset(long long* cnt, int queue_only) {
+  const int i = threadIdx.x;
+  if (i >= C_NCOUNTERS) return;
+  if (!queue_only || i == C_NTASK || i == C_HEAD || i == C_NFS) cnt[i] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_point(double s, double q, int64_t n, const double* zx,
@@ -144,24 +150,30 @@ __global__ __launch_bounds__(256) void k_point(double s, double q, int64_t n, co
   flags[i] = im.flags;
 }
 
-// Append the calling lanes with `push` set to the task queue: one atomic
-// per wave.
-__device__ inline int64_t queue_push(bool push, long long* count) {
+// Append `count` entries per calling lane (0 or a lane-uniform k) to a
+// queue: one atomic per wave; returns this lane's first slot.
+__device__ inline int64_t queue_push(bool push, int count, long long* counter) {
   const uint64_t mask = __ballot(push);
   if (mask == 0) return -1;
   const int lane = threadIdx.x & (WAVE - 1);
   const int leader = __ffsll((unsigned long long)mask) - 1;
   long long base = 0;
-  if (lane == leader) base = atomicAdd((unsigned long long*)count, (unsigned long long)__popcll(mask));
+  if (lane == leader)
+    base = atomicAdd((unsigned long long*)counter, (unsigned long long)(__popcll(mask) * count));
   base = __shfl(base, leader);
   if (!push) return -1;
-  return base + __popcll(mask & ((1ull << lane) - 1ull));
+  return base + (long long)count * __popcll(mask & ((1ull << lane) - 1ull));
 }
 
+// Point-source pass for one source: answer it by the point value when the
+// point-source test passes, else queue its contour task(s).  With na > 1
+// annuli (limb darkening), the source is recorded in fs_epoch[] and na
+// uniform-disk tasks of radii rho sqrt(k/na), k = 1..na, are queued; their
+// results land in the annulus buffers at f*na + k - 1.
 __device__ inline void emit_source(int64_t out, double s, double q, double zx, double zy,
-                                   double rho, double tol, bool all_fs, Task* tasks,
-                                   long long* cnt, double* mag, double* err, int32_t* ns,
-                                   uint32_t* flags, bool active) {
+                                   double rho, double tol, bool all_fs, int na, Task* tasks,
+                                   long long* cnt, int64_t* fs_epoch, double* mag, double* err,
+                                   int32_t* ns, uint32_t* flags, bool active) {
   bool push = false;
   PsResult ps;
   const Lens L = make_lens(s, q);
@@ -184,18 +196,28 @@ __device__ inline void emit_source(int64_t out, double s, double q, double zx, d
       }
     }
   }
-  const int64_t slot = queue_push(push, &cnt[C_NTASK]);
+  int64_t first_out = out;
+  if (na > 1) {
+    const int64_t f = queue_push(push, 1, &cnt[C_NFS]);
+    if (push) {
+      fs_epoch[f] = out;
+      first_out = f * na;
+    }
+  }
+  const int64_t slot = queue_push(push, na, &cnt[C_NTASK]);
   if (push) {
     Task t;
-    t.out = out;
     t.s = s;
     t.q = q;
-    t.rho = rho;
     t.zx = zx;
     t.zy = zy;
 #pragma unroll
     for (int k = 0; k < 5; ++k) t.roots[k] = ps.roots[k];
-    tasks[slot] = t;
+    for (int k = 0; k < na; ++k) {
+      t.out = first_out + k;
+      t.rho = na > 1 ? rho * sqrt((double)(k + 1) / na) : rho;
+      tasks[slot + k] = t;
+    }
   }
 }
 
@@ -206,8 +228,30 @@ __global__ __launch_bounds__(256) void k_prep(double s, double q, int64_t n, con
                                               uint32_t* flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = i < n;
-  emit_source(i, s, q, active ? zx[i] : 0.0, active ? zy[i] : 0.0, rho, tol, all_fs != 0, tasks,
-              cnt, mag, err, ns, flags, active);
+  emit_source(i, s, q, active ? zx[i] : 0.0, active ? zy[i] : 0.0, rho, tol, all_fs != 0, 1, tasks,
+              cnt, nullptr, mag, err, ns, flags, active);
+}
+
+// Magnification map: pixel (ix, iy) of an nx x ny grid over the box
+// [xc - w/2, xc + w/2] x [yc - h/2, yc + h/2], pixel centres, output index
+// iy * nx + ix (rows iy0 .. iy0 + nrows - 1 in this launch).
+__global__ __launch_bounds__(256) void k_map(double s, double q, double rho, double xc, double yc,
+                                             double w, double h, int32_t nx, int32_t ny,
+                                             int64_t iy0, int64_t nrows, double tol, int all_fs,
+                                             Task* tasks, long long* cnt, double* mag,
+                                             double* err, int32_t* ns, uint32_t* flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = i < nrows * (int64_t)nx;
+  double zx = 0.0, zy = 0.0;
+  int64_t out = 0;
+  if (active) {
+    const int64_t iy = iy0 + i / nx, ix = i % nx;
+    zx = xc - 0.5 * w + (ix + 0.5) * (w / nx);
+    zy = yc - 0.5 * h + (iy + 0.5) * (h / ny);
+    out = iy * nx + ix;
+  }
+  emit_source(out, s, q, zx, zy, rho, tol, all_fs != 0, 1, tasks, cnt, nullptr, mag, err, ns,
+              flags, active);
 }
 
 // Light curves: element (set k, epoch j) at index k * nepochs + j.  Source
@@ -215,9 +259,10 @@ __global__ __launch_bounds__(256) void k_prep(double s, double q, int64_t n, con
 __global__ __launch_bounds__(256) void k_lc(int64_t nsets, const double* ps, const double* pq,
                                             const double* pu0, const double* pal,
                                             const double* prho, int64_t nep,
-                                            const double* tau, double tol, int all_fs,
-                                            Task* tasks, long long* cnt, double* mag,
-                                            double* err, int32_t* ns, uint32_t* flags) {
+                                            const double* tau, double tol, int all_fs, int na,
+                                            Task* tasks, long long* cnt, int64_t* fs_epoch,
+                                            double* mag, double* err, int32_t* ns,
+                                            uint32_t* flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = i < nsets * nep;
   double s = 1.0, q = 1.0, zx = 0.0, zy = 0.0, rho = 1.0;
@@ -232,7 +277,44 @@ __global__ __launch_bounds__(256) void k_lc(int64_t nsets, const double* ps, con
     zx = t * ca - u0 * sa;
     zy = t * sa + u0 * ca;
   }
-  emit_source(i, s, q, zx, zy, rho, tol, all_fs != 0, tasks, cnt, mag, err, ns, flags, active);
+  emit_source(i, s, q, zx, zy, rho, tol, all_fs != 0, na, tasks, cnt, fs_epoch, mag, err, ns,
+              flags, active);
+}
+
+// Linear limb darkening over na equal-area annuli (x_k = k/na of the squared
+// radius): I(r)/mean = 1 - G (1 - 1.5 sqrt(1 - r^2/rho^2)); the annulus mean
+// is I_k = 1 - G + G [(1 - x_{k-1})^1.5 - (1 - x_k)^1.5] / (x_k - x_{k-1}).
+// The flux of annulus k is I_k (x_k mu_k - x_{k-1} mu_{k-1}) with mu_k the
+// uniform-disk magnification of the disk of squared radius x_k rho^2.
+__global__ __launch_bounds__(256) void k_ld(const long long* cnt, const int64_t* fs_epoch,
+                                            int na, const double* gamma, int64_t nep,
+                                            const double* amag, const double* aerr,
+                                            const int32_t* ans, const uint32_t* afl, double* mag,
+                                            double* err, int32_t* ns, uint32_t* flags) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= cnt[C_NFS]) return;
+  const int64_t i = fs_epoch[f];
+  const double G = gamma[i / nep];
+  double num = 0.0, den = 0.0, e = 0.0, xp = 0.0, mp = 0.0, ep = 0.0;
+  int32_t nsum = 0;
+  uint32_t fl = 0;
+  for (int k = 1; k <= na; ++k) {
+    const double x = (double)k / na;
+    const double Ik = 1.0 - G + G * (pow(1.0 - xp, 1.5) - pow(1.0 - x, 1.5)) / (x - xp);
+    const double mk = amag[f * na + k - 1], ek = aerr[f * na + k - 1];
+    num += Ik * (x * mk - xp * mp);
+    den += Ik * (x - xp);
+    e += Ik * (x * ek + xp * ep);
+    nsum += ans[f * na + k - 1];
+    fl |= afl[f * na + k - 1];
+    xp = x;
+    mp = mk;
+    ep = ek;
+  }
+  mag[i] = num / den;
+  err[i] = e / den;
+  ns[i] = nsum;
+  flags[i] = fl;
 }
 
 // Persistent finite-source kernel: each wave pops tasks until the queue is
@@ -287,6 +369,11 @@ struct twk_ctx {
   int64_t task_cap = 0;
   long long* cnt = nullptr;
   int waves = 0;
+  // limb darkening: epochs sent to the annulus contours and their results
+  int64_t* fs_epoch = nullptr;
+  size_t fs_epoch_bytes = 0;
+  char* ann = nullptr;  // [mag f64 | err f64 | ns i32 | flags u32] x (nfs * na)
+  size_t ann_bytes = 0;
   bool timing = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
@@ -327,6 +414,9 @@ int occupancy(int* blocks) {
   return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fs<LDS_CAP, MIXED>, 64, 0);
 }
 
+// Task records per chunk of a call: bounds the queue memory (128 B each).
+constexpr int64_t CHUNK_TASKS = (int64_t)1 << 24;
+
 int ensure_fs(twk_ctx* c, int64_t ntask_max) {
   int rc;
   size_t have = (size_t)c->task_cap * sizeof(Task);
@@ -337,19 +427,57 @@ int ensure_fs(twk_ctx* c, int64_t ntask_max) {
   return grow(c, (void**)&c->scratch, &c->scratch_bytes, need);
 }
 
-template <bool MIXED>
-int launch_fs(twk_ctx* c, double tol, double* mag, double* err, int32_t* ns, uint32_t* flags) {
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
-  hipLaunchKernelGGL((k_fs<LDS_CAP, MIXED>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
-                     &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
-                     c->cnt);
+int ensure_ld(twk_ctx* c, int64_t nfs_max, int na) {
+  int rc;
+  if ((rc = grow(c, (void**)&c->fs_epoch, &c->fs_epoch_bytes,
+                 (size_t)std::max<int64_t>(nfs_max, 1) * sizeof(int64_t))))
+    return rc;
+  return grow(c, (void**)&c->ann, &c->ann_bytes, (size_t)std::max<int64_t>(nfs_max, 1) * na * 24);
+}
+
+struct AnnBufs {
+  double* mag;
+  double* err;
+  int32_t* ns;
+  uint32_t* flags;
+};
+
+AnnBufs ann_bufs(twk_ctx* c, int64_t n) {
+  char* p = c->ann;
+  AnnBufs a;
+  a.mag = (double*)p;
+  a.err = (double*)(p + (size_t)n * 8);
+  a.ns = (int32_t*)(p + (size_t)n * 16);
+  a.flags = (uint32_t*)(p + (size_t)n * 20);
+  return a;
+}
+
+int launch_fs(twk_ctx* c, bool mixed, double tol, double* mag, double* err, int32_t* ns,
+              uint32_t* flags) {
+  if (mixed)
+    hipLaunchKernelGGL((k_fs<LDS_CAP, true>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
+                       &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
+                       c->cnt);
+  else
+    hipLaunchKernelGGL((k_fs<LDS_CAP, false>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
+                       &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
+                       c->cnt);
   HIP_TRY(c, hipGetLastError());
-  if (c->timing) {
-    HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-    HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
-  }
   return TWK_OK;
 }
+
+int reset(twk_ctx* c, bool queue_only) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, c->cnt, queue_only ? 1 : 0);
+  HIP_TRY(c, hipGetLastError());
+  return TWK_OK;
+}
+
+int mark(twk_ctx* c, int i, bool on) {
+  if (c->timing && on) HIP_TRY(c, hipEventRecord(c->ev[i], c->stream));
+  return TWK_OK;
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
 
@@ -408,6 +536,8 @@ int twk_destroy(twk_ctx* c) {
   (void)hipFree(c->scratch);
   (void)hipFree(c->tasks);
   (void)hipFree(c->cnt);
+  (void)hipFree(c->fs_epoch);
+  (void)hipFree(c->ann);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   delete c;
@@ -443,44 +573,106 @@ int twk_finite_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, 
   if (mode & ~(TWK_MODE_MIXED | TWK_MODE_ALL_FS)) return TWK_EINVAL;
   if (n == 0) return TWK_OK;
   if (!zx || !zy || !mag || !err || !ns || !flags) return TWK_EINVAL;
-  if (n > (int64_t)1 << 40) return TWK_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
-  int rc = ensure_fs(c, n);
+  const int64_t chunk = std::min<int64_t>(n, CHUNK_TASKS);
+  int rc = ensure_fs(c, chunk);
   if (rc) return rc;
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, c->cnt);
-  HIP_TRY(c, hipGetLastError());
-  const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_prep, dim3((unsigned)blocks), dim3(256), 0, c->stream, s, q, n, zx, zy, rho,
-                     tol, (mode & TWK_MODE_ALL_FS) ? 1 : 0, c->tasks, c->cnt, mag, err, ns, flags);
-  HIP_TRY(c, hipGetLastError());
-  return (mode & TWK_MODE_MIXED) ? launch_fs<true>(c, tol, mag, err, ns, flags)
-                                 : launch_fs<false>(c, tol, mag, err, ns, flags);
+  const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
+  const bool mixed = (mode & TWK_MODE_MIXED) != 0;
+  if ((rc = mark(c, 0, true)) || (rc = reset(c, false))) return rc;
+  for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+    const int64_t m = std::min(chunk, n - i0);
+    if (i0 > 0 && (rc = reset(c, true))) return rc;
+    hipLaunchKernelGGL(k_prep, dim3(blocks_for(m)), dim3(256), 0, c->stream, s, q, m, zx + i0,
+                       zy + i0, rho, tol, all_fs, c->tasks, c->cnt, mag + i0, err + i0, ns + i0,
+                       flags + i0);
+    HIP_TRY(c, hipGetLastError());
+    if ((rc = mark(c, 1, i0 == 0))) return rc;
+    if ((rc = launch_fs(c, mixed, tol, mag + i0, err + i0, ns + i0, flags + i0))) return rc;
+    if ((rc = mark(c, 2, i0 == 0))) return rc;
+  }
+  return mark(c, 3, true);
+}
+
+int twk_mag_map(twk_ctx* c, double s, double q, double rho, double xc, double yc, double width,
+                double height, int32_t nx, int32_t ny, double tol, uint32_t mode, double* mag,
+                double* err, int32_t* ns, uint32_t* flags) {
+  if (!c || !finite_pos(s) || !finite_pos(q) || !finite_pos(rho) || !finite_pos(tol) ||
+      !finite_pos(width) || !finite_pos(height) || nx < 0 || ny < 0 || !std::isfinite(xc) ||
+      !std::isfinite(yc))
+    return TWK_EINVAL;
+  if (mode & ~(TWK_MODE_MIXED | TWK_MODE_ALL_FS)) return TWK_EINVAL;
+  const int64_t n = (int64_t)nx * ny;
+  if (n == 0) return TWK_OK;
+  if (!mag || !err || !ns || !flags) return TWK_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(ny, CHUNK_TASKS / nx));
+  int rc = ensure_fs(c, rows * nx);
+  if (rc) return rc;
+  const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
+  const bool mixed = (mode & TWK_MODE_MIXED) != 0;
+  if ((rc = mark(c, 0, true)) || (rc = reset(c, false))) return rc;
+  for (int64_t y0 = 0; y0 < ny; y0 += rows) {
+    const int64_t nr = std::min<int64_t>(rows, ny - y0);
+    if (y0 > 0 && (rc = reset(c, true))) return rc;
+    hipLaunchKernelGGL(k_map, dim3(blocks_for(nr * nx)), dim3(256), 0, c->stream, s, q, rho, xc, yc,
+                       width, height, nx, ny, y0, nr, tol, all_fs, c->tasks, c->cnt, mag, err, ns,
+                       flags);
+    HIP_TRY(c, hipGetLastError());
+    if ((rc = mark(c, 1, y0 == 0))) return rc;
+    if ((rc = launch_fs(c, mixed, tol, mag, err, ns, flags))) return rc;
+    if ((rc = mark(c, 2, y0 == 0))) return rc;
+  }
+  return mark(c, 3, true);
 }
 
 int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q, const double* u0,
                     const double* alpha, const double* rho, const double* gamma, int64_t nepochs,
                     const double* tau, int32_t n_annuli, double tol, uint32_t mode, double* mag,
                     double* err, int32_t* ns, uint32_t* flags) {
-  if (!c || nsets < 0 || nepochs < 0 || !finite_pos(tol) || n_annuli < 1) return TWK_EINVAL;
+  if (!c || nsets < 0 || nepochs < 0 || !finite_pos(tol) || n_annuli < 1 || n_annuli > 64)
+    return TWK_EINVAL;
   if (mode & ~(TWK_MODE_MIXED | TWK_MODE_ALL_FS)) return TWK_EINVAL;
-  if (gamma != nullptr && n_annuli != 1) return TWK_EINVAL;  // limb darkening: not yet wired
+  if (gamma == nullptr && n_annuli != 1) return TWK_EINVAL;
   const int64_t n = nsets * nepochs;
   if (n == 0) return TWK_OK;
   if (!s || !q || !u0 || !alpha || !rho || !tau || !mag || !err || !ns || !flags) return TWK_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
-  int rc = ensure_fs(c, n);
+  const bool ld = gamma != nullptr;
+  const int na = ld ? n_annuli : 1;
+  const int64_t chunk_sets = std::max<int64_t>(1, CHUNK_TASKS / na / nepochs);
+  const int64_t chunk_n = std::min(nsets, chunk_sets) * nepochs;
+  int rc = ensure_fs(c, chunk_n * na);
   if (rc) return rc;
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, c->cnt);
-  HIP_TRY(c, hipGetLastError());
-  const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_lc, dim3((unsigned)blocks), dim3(256), 0, c->stream, nsets, s, q, u0, alpha,
-                     rho, nepochs, tau, tol, (mode & TWK_MODE_ALL_FS) ? 1 : 0, c->tasks, c->cnt,
-                     mag, err, ns, flags);
-  HIP_TRY(c, hipGetLastError());
-  return (mode & TWK_MODE_MIXED) ? launch_fs<true>(c, tol, mag, err, ns, flags)
-                                 : launch_fs<false>(c, tol, mag, err, ns, flags);
+  if (ld && (rc = ensure_ld(c, chunk_n, na))) return rc;
+  const AnnBufs ab = ld ? ann_bufs(c, chunk_n * na) : AnnBufs{nullptr, nullptr, nullptr, nullptr};
+  const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
+  const bool mixed = (mode & TWK_MODE_MIXED) != 0;
+  // The limb-darkened value is a weighted difference of the annulus values,
+  // which roughly doubles their relative error: annuli run at tol / 2.
+  const double tol_fs = ld ? 0.5 * tol : tol;
+  if ((rc = mark(c, 0, true)) || (rc = reset(c, false))) return rc;
+  for (int64_t k0 = 0; k0 < nsets; k0 += chunk_sets) {
+    const int64_t nk = std::min(chunk_sets, nsets - k0);
+    const int64_t o = k0 * nepochs;
+    if (k0 > 0 && (rc = reset(c, true))) return rc;
+    hipLaunchKernelGGL(k_lc, dim3(blocks_for(nk * nepochs)), dim3(256), 0, c->stream, nk, s + k0,
+                       q + k0, u0 + k0, alpha + k0, rho + k0, nepochs, tau, tol, all_fs, na,
+                       c->tasks, c->cnt, c->fs_epoch, mag + o, err + o, ns + o, flags + o);
+    HIP_TRY(c, hipGetLastError());
+    if ((rc = mark(c, 1, k0 == 0))) return rc;
+    if (ld) rc = launch_fs(c, mixed, tol_fs, ab.mag, ab.err, ab.ns, ab.flags);
+    else rc = launch_fs(c, mixed, tol_fs, mag + o, err + o, ns + o, flags + o);
+    if (rc) return rc;
+    if ((rc = mark(c, 2, k0 == 0))) return rc;
+    if (ld) {
+      hipLaunchKernelGGL(k_ld, dim3(blocks_for(nk * nepochs)), dim3(256), 0, c->stream, c->cnt,
+                         c->fs_epoch, na, gamma + k0, nepochs, ab.mag, ab.err, ab.ns, ab.flags,
+                         mag + o, err + o, ns + o, flags + o);
+      HIP_TRY(c, hipGetLastError());
+    }
+  }
+  return mark(c, 3, true);
 }
 
 int twk_last_stats(twk_ctx* c, int64_t* out8) {
@@ -488,7 +680,7 @@ int twk_last_stats(twk_ctx* c, int64_t* out8) {
   long long h[C_NCOUNTERS];
   HIP_TRY(c, hipMemcpyAsync(h, c->cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  out8[0] = h[C_NTASK];
+  out8[0] = h[C_RUNS];
   out8[1] = h[C_NOVER];
   out8[2] = h[C_SAMPLES];
   out8[3] = c->waves;

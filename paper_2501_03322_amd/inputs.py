@@ -89,7 +89,7 @@ def large_ld_curves(nsets=16384, nepochs=8000, seed=4, n_annuli=10):
 # of the central caustic's x-extent in the centre-of-mass frame, computed
 # once from the caustic of this lens and recorded here.
 MAP_S, MAP_Q, MAP_RHO = 0.9, 1e-4, 1e-3
-MAP_CENTRE = (3.50e-3, 0.0)
+MAP_CENTRE = (3.5013e-3, 0.0)
 MAP_WIDTH = 0.2
 
 

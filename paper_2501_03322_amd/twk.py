@@ -29,7 +29,7 @@ FLAG_NEARDEGEN = 1 << 5
 
 EXPORTS = ("twk_create", "twk_destroy", "twk_sync", "twk_last_hip_error", "twk_strerror",
            "twk_point_mag", "twk_finite_mag", "twk_lightcurves", "twk_last_stats",
-           "twk_enable_timing", "twk_kernel_times")
+           "twk_enable_timing", "twk_kernel_times", "twk_mag_map")
 
 _lib = None
 _vp = C.c_void_p
@@ -61,12 +61,15 @@ def load():
                                  C.c_double, C.c_uint32, _vp, _vp, _vp, _vp]
     L.twk_lightcurves.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int64, _vp,
                                   C.c_int32, C.c_double, C.c_uint32, _vp, _vp, _vp, _vp]
+    L.twk_mag_map.argtypes = [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                              C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_uint32,
+                              _vp, _vp, _vp, _vp]
     L.twk_last_stats.argtypes = [_vp, C.POINTER(C.c_int64)]
     L.twk_enable_timing.argtypes = [_vp, C.c_int]
     L.twk_kernel_times.argtypes = [_vp, C.POINTER(C.c_double)]
     for f in ("twk_create", "twk_destroy", "twk_sync", "twk_last_hip_error", "twk_point_mag",
               "twk_finite_mag", "twk_lightcurves", "twk_last_stats", "twk_enable_timing",
-              "twk_kernel_times"):
+              "twk_kernel_times", "twk_mag_map"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -137,7 +140,7 @@ class Context:
     def kernel_times(self):
         out = (C.c_double * 4)()
         self._check(self.lib.twk_kernel_times(self.h, out), "twk_kernel_times")
-        return dict(ps_ms=out[0], fs_ms=out[1], fs_full_cap_ms=out[2], total_ms=out[3])
+        return dict(ps_ms=out[0], fs_ms=out[1], rest_ms=out[2], total_ms=out[3])
 
     def point_mag(self, s, q, zx, zy):
         zx = _dev(zx, self.device)
@@ -181,4 +184,13 @@ class Context:
                                              _ptr(rho), _ptr(g), nep, _ptr(tau), n_annuli, tol, mode,
                                              _ptr(mag), _ptr(err), _ptr(ns), _ptr(fl)),
                     "twk_lightcurves")
+        return out
+
+    def mag_map(self, s, q, rho, centre, width, height, nx, ny, tol, mode=MODE_FP64, out=None):
+        if out is None:
+            out = self.alloc_out(nx * ny)
+        mag, err, ns, fl = out
+        self._check(self.lib.twk_mag_map(self.h, s, q, rho, centre[0], centre[1], width, height, nx,
+                                         ny, tol, mode, _ptr(mag), _ptr(err), _ptr(ns), _ptr(fl)),
+                    "twk_mag_map")
         return out

@@ -191,3 +191,52 @@ def test_deterministic(ctx):
     b = [_np(t).copy() for t in ctx.finite_mag(s, q, zx, zy, rho, 1e-4, 9)]
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_limb_darkened_lightcurves(ctx, oracle):
+    """Linear limb darkening over 10 equal-area annuli (large limb-darkened
+    batch's parameter ranges): sampled epochs against the oracle's annulus
+    combination of tight-tolerance uniform-disk values."""
+    from paper_2501_03322_amd import inputs
+    c = inputs.large_ld_curves(nsets=48, nepochs=400, seed=4)
+    _log("limb darkened: 48 x 400, 10 annuli")
+    mag, err, ns, fl = ctx.lightcurves(c.s, c.q, c.u0, c.alpha, c.rho, c.tau, 1e-4, 1,
+                                       gamma=c.gamma, n_annuli=10)
+    mag, fl = _np(mag), _np(fl)
+    assert np.all(np.isfinite(mag))
+    fs = np.nonzero((fl & 1) == 0)[0]
+    pt = np.nonzero((fl & 1) != 0)[0]
+    rng = np.random.default_rng(4)
+    pick = np.concatenate([rng.choice(fs, min(40, fs.size), replace=False),
+                           rng.choice(pt, min(20, pt.size), replace=False)])
+    for i in pick:
+        k, j = divmod(int(i), c.nepochs)
+        zx, zy = oracle.trajectory(c.u0[k], c.alpha[k], c.tau[j:j + 1])
+        mu_k = [oracle.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k] * np.sqrt(a / 10), oracle.JUDGE_TOL,
+                                  oracle.judge_cfg())[0][0] for a in range(1, 11)]
+        ref = oracle.ld_combine(c.gamma[k], mu_k)
+        assert abs(mag[i] / ref - 1) <= GATE, (i, k, j, mag[i], ref)
+
+
+def test_magnification_map(ctx, oracle):
+    """Magnification map of the central caustic (s=0.9, q=1e-4, rho=1e-3):
+    a 64 x 64 map checked pixel by pixel on a sample, and the full 2048 x
+    2048 map in the launch configuration of a map run, checked on sampled
+    pixels."""
+    from paper_2501_03322_amd import inputs
+    s, q, rho = inputs.MAP_S, inputs.MAP_Q, inputs.MAP_RHO
+    for n, nsample in [(64, 60), (2048, 60)]:
+        _log(f"map {n} x {n}")
+        mag, err, ns, fl = ctx.mag_map(s, q, rho, inputs.MAP_CENTRE, inputs.MAP_WIDTH,
+                                       inputs.MAP_WIDTH, n, n, 1e-4, 1)
+        mag, fl = _np(mag), _np(fl)
+        assert np.all(np.isfinite(mag))
+        x, y = inputs.map_pixels(n)
+        rng = np.random.default_rng(n)
+        fs = np.nonzero((fl & 1) == 0)[0]
+        pick = np.concatenate([rng.choice(fs, min(nsample, fs.size), replace=False),
+                               rng.choice(mag.size, nsample // 2, replace=False)])
+        for p in pick:
+            iy, ix = divmod(int(p), n)
+            rm = oracle.finite_mag(s, q, [x[ix]], [y[iy]], rho, oracle.JUDGE_TOL, oracle.judge_cfg())[0][0]
+            assert abs(mag[p] / rm - 1) <= GATE, (n, ix, iy, mag[p], rm)
