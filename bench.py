@@ -77,9 +77,13 @@ def run_path(ctx, dev, c, mode, steps, warmup, label):
     st = ctx.stats()
     ctx.enable_timing(False)
     fl = out[3].cpu().numpy()
+    ns = out[2].cpu().numpy()
+    nfs = ns[(fl & 1) == 0]
+    hist = {f"<= {b}": int(np.sum(nfs <= b)) for b in (64, 128, 256, 512, 1024, 2048, 4096)}
     return dict(ms_per_step=1e3 * wall / steps, fs_kernel_ms=float(np.mean(fs_ms)),
                 event_ms=float(np.mean(tot_ms)), stats=st,
-                fs_fraction=float(np.mean((fl & 1) == 0)), mag=out[0])
+                fs_fraction=float(np.mean((fl & 1) == 0)), mag=out[0],
+                samples_hist=hist, samples_max=int(nfs.max()) if nfs.size else 0)
 
 
 def cpu_baseline(c, seconds, seed=11):
@@ -171,7 +175,9 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
                      "kernel": "k_fs<512, mixed>",
                      "flops_per_launch": flops, "kernel_ms": best["fs_kernel_ms"]},
-        "work": {"fs_fraction": best["fs_fraction"], **{k: int(v) for k, v in st.items()}},
+        "work": {"fs_fraction": best["fs_fraction"], **{k: int(v) for k, v in st.items()},
+                 "samples_per_source_cumulative": best["samples_hist"],
+                 "samples_per_source_max": best["samples_max"]},
     }
     if plain is not None:
         pst = plain["stats"]

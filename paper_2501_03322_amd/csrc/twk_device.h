@@ -143,24 +143,28 @@ __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
       horner64(c, x, p, d);
       const c64 ratio = cdiv(p, d);
       c64 rep = cz(0.0, 0.0);
-      const double nr = cnorm(x);
+      const double inr = rcp64(fmax(cnorm(x), 1e-300));
+      double n2min = 1e300;
 #pragma unroll
       for (int j = 1; j < 5; ++j) {
         const c64 dd = x - r[j];
         const double n2 = cnorm(dd);
-        closest = fmin(closest, n2 / fmax(nr, 1e-300));
+        n2min = fmin(n2min, n2);
         const double ir = rcp64(n2);
         rep = rep + cz(dd.x * ir, -dd.y * ir);
       }
+      closest = fmin(closest, n2min * inr);
       c64 w = cdiv(ratio, cz(1.0, 0.0) - ratio * rep);
       double nw = cnorm(w);
       if (!(nw < 1e300)) {  // vanishing derivative or coincident iterates
-        w = cz(-1e-3 * (1.0 + sqrt(nr)), 7e-4 * (1.0 + sqrt(nr)));
+        const double a = 1.0 + sqrt(cnorm(x));
+        w = cz(-1e-3 * a, 7e-4 * a);
         nw = 1.0;
         worst = 1.0;
       }
       const c64 xn = x - w;
-      worst = fmax(worst, nw / fmax(cnorm(xn), 1e-300));
+      // relative size of the correction; only its order of magnitude matters
+      worst = fmax(worst, nw * __builtin_amdgcn_rcp(fmax(cnorm(xn), 1e-300)));
       r[0] = r[1];
       r[1] = r[2];
       r[2] = r[3];
@@ -210,7 +214,7 @@ __device__ inline int aberth32(const c64 c64c[6], c64 r64[5], int maxit) {
         worst = 1.f;
       }
       const c32 xn = x - w;
-      worst = fmaxf(worst, nw / fmaxf(cnorm(xn), 1e-30f));
+      worst = fmaxf(worst, nw * __builtin_amdgcn_rcpf(fmaxf(cnorm(xn), 1e-30f)));
       r[0] = r[1];
       r[1] = r[2];
       r[2] = r[3];

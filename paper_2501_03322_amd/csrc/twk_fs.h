@@ -475,117 +475,110 @@ __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, F
   const double rho = T.rho;
   uint32_t fl = 0;
   uint32_t sw32 = 0, sw64 = 0, nint = 0;  // this lane's work
-  int N = NNEW;
-  // Initial samples: theta_j = 2 pi j / 64, warm-started from the roots at
-  // the source centre.
-  {
-    const double th = TWO_PI * lane / (double)NNEW;
-    c64 r[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) r[k] = T.roots[k];
-    uint32_t sf;
-    const uint32_t sw = solve_store<MIXED>(lens, yc, rho, th, r, m, lane, &sf);
-    sw64 += sw & 0xffffu;
-    sw32 += sw >> 16;
-    fl |= sf & (F_ANOMALY | F_NEARDEGEN);
-    S.th[lane] = th;
-    S.sl[lane] = (uint16_t)lane;
-  }
-  __syncthreads();
-  double Ahi, Alo;
-  {
-    const Piece pc = relink(m, S, lane, N);
-    ++nint;
-    if (pc.fl & IF_ANOMALY) fl |= F_ANOMALY;
-    Ahi = pc.dA;
-    Alo = 0.0;
-    wave_sum_comp(Ahi, Alo);
-  }
-  __syncthreads();
-  double A = Ahi + Alo, E = 0.0;
+  int N = 0;
+  double Ahi = 0.0, Alo = 0.0, A = 0.0, E = 0.0;
+  // One round per iteration.  The first round places the initial samples
+  // theta_j = 2 pi j / 64, warm-started from the roots at the source centre;
+  // later rounds place 64 samples by inverse transform sampling.  Solving,
+  // merging and relinking have one call site each, which keeps the kernel
+  // small enough for the instruction cache.
   for (;;) {
-    // error total and total tolerance-subtracted weight
-    A = Ahi + Alo;
-    const double avg = tol * fabs(A) / N;
-    double es = 0.0, ws = 0.0;
-    for (int p = lane; p < N; p += WAVE) {
-      const double e = S.E[p];
-      es += e;
-      ws += fmax(e - avg, 0.0);
-    }
-    E = wave_sum(es);
-    if (E <= tol * fabs(A)) break;
-    if (N + NNEW > S.cap && S.cap < METHOD_CAP) {
-      // outgrowing the LDS copy: continue on the spill copy in global memory
+    bool valid;
+    int iv = -1, rank, mcount;
+    double thn;
+    if (N == 0) {
+      valid = true;
+      thn = TWO_PI * lane / (double)NNEW;
+      rank = lane;
+      mcount = NNEW;
+    } else {
+      // error total and total tolerance-subtracted weight
+      A = Ahi + Alo;
+      const double avg = tol * fabs(A) / N;
+      double es = 0.0, ws = 0.0;
       for (int p = lane; p < N; p += WAVE) {
-        m.sth[p] = S.th[p];
-        m.sE[p] = S.E[p];
-        m.ssl[p] = S.sl[p];
+        const double e = S.E[p];
+        es += e;
+        ws += fmax(e - avg, 0.0);
       }
-      __syncthreads();
-      S = Sorted{m.sth, m.sE, m.ssl, METHOD_CAP};
-      spilled = true;
-    }
-    const int nnew = N + NNEW <= S.cap ? NNEW : S.cap - N;
-    if (nnew <= 0) { fl |= F_CAP; break; }
-    const double W = wave_sum(ws);
-    if (!(W > 0.0)) break;
-    // inverse transform sampling: lane j takes quantile (j + 1/2)/nnew of the
-    // cumulative weight, located during one strip-wise scan of the weights
-    const double u = (lane + 0.5) / nnew * W;
-    bool found = false;
-    int iv = 0;
-    double w0 = 0.0, wi = 0.0;
-    double carry = 0.0;
-    for (int base = 0; base < N; base += WAVE) {
-      const int p = base + lane;
-      const double w = p < N ? fmax(S.E[p] - avg, 0.0) : 0.0;
-      const double inc = wave_incl_scan(w, lane);
-      const double tot = __shfl(inc, WAVE - 1);
-      const bool mine = !found && lane < nnew && u < carry + tot;
-      if (__ballot(mine)) {
-        int lo = 0;  // first strip position whose inclusive sum exceeds u
+      E = wave_sum(es);
+      if (E <= tol * fabs(A)) break;
+      if (N + NNEW > S.cap && S.cap < METHOD_CAP) {
+        // outgrowing the LDS copy: continue on the spill copy in global memory
+        for (int p = lane; p < N; p += WAVE) {
+          m.sth[p] = S.th[p];
+          m.sE[p] = S.E[p];
+          m.ssl[p] = S.sl[p];
+        }
+        __syncthreads();
+        S = Sorted{m.sth, m.sE, m.ssl, METHOD_CAP};
+        spilled = true;
+      }
+      const int nnew = N + NNEW <= S.cap ? NNEW : S.cap - N;
+      if (nnew <= 0) { fl |= F_CAP; break; }
+      const double W = wave_sum(ws);
+      if (!(W > 0.0)) break;
+      // inverse transform sampling: lane j takes quantile (j + 1/2)/nnew of
+      // the cumulative weight, located during one strip-wise scan
+      const double u = (lane + 0.5) / nnew * W;
+      bool found = false;
+      double w0 = 0.0, wi = 0.0;
+      double carry = 0.0;
+      for (int base = 0; base < N; base += WAVE) {
+        const int p = base + lane;
+        const double w = p < N ? fmax(S.E[p] - avg, 0.0) : 0.0;
+        const double inc = wave_incl_scan(w, lane);
+        const double tot = __shfl(inc, WAVE - 1);
+        const bool mine = !found && lane < nnew && u < carry + tot;
+        if (__ballot(mine)) {
+          int lo = 0;  // first strip position whose inclusive sum exceeds u
 #pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-          const double v = carry + __shfl(inc, lo + step - 1);
-          if (!(v > u)) lo += step;
+          for (int step = 32; step >= 1; step >>= 1) {
+            const double v = carry + __shfl(inc, lo + step - 1);
+            if (!(v > u)) lo += step;
+          }
+          const int lq = lo < WAVE ? lo : WAVE - 1;
+          const double wl = __shfl(w, lq), il = __shfl(inc, lq);
+          if (mine) {
+            found = true;
+            iv = base + lq;
+            wi = wl;
+            w0 = carry + il - wl;
+          }
         }
-        const int lq = lo < WAVE ? lo : WAVE - 1;
-        const double wl = __shfl(w, lq), il = __shfl(inc, lq);
-        if (mine) {
-          found = true;
-          iv = base + lq;
-          wi = wl;
-          w0 = carry + il - wl;
-        }
+        carry += tot;
       }
-      carry += tot;
+      valid = false;
+      thn = 0.0;
+      if (found && iv < N) {
+        const double ta = S.th[iv];
+        const double tb = iv + 1 < N ? S.th[iv + 1] : TWO_PI;
+        thn = ta + (u - w0) / wi * (tb - ta);
+        valid = wi > 0.0 && thn > ta && thn < tb;
+      }
+      const int piv = __shfl_up(iv, 1);
+      const double pth = __shfl_up(thn, 1);
+      if (lane > 0 && valid && piv == iv && !(thn > pth)) valid = false;
+      const uint64_t mask = __ballot(valid);
+      mcount = __popcll(mask);
+      if (mcount == 0) { fl |= F_CAP; break; }
+      rank = __popcll(mask & ((1ull << lane) - 1ull));
+      if (valid) L.ivl[rank] = iv;
     }
-    bool valid = false;
-    double thn = 0.0;
-    if (found && iv < N) {
-      const double ta = S.th[iv];
-      const double tb = iv + 1 < N ? S.th[iv + 1] : TWO_PI;
-      thn = ta + (u - w0) / wi * (tb - ta);
-      valid = wi > 0.0 && thn > ta && thn < tb;
-    }
-    const int piv = __shfl_up(iv, 1);
-    const double pth = __shfl_up(thn, 1);
-    if (lane > 0 && valid && piv == iv && !(thn > pth)) valid = false;
-    const uint64_t mask = __ballot(valid);
-    const int mcount = __popcll(mask);
-    if (mcount == 0) { fl |= F_CAP; break; }
-    const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-    if (valid) L.ivl[rank] = iv;
-    // solve the new samples, warm-started from the nearer neighbour's roots
-    // advanced along their limb derivative
+    // solve the new samples: the centre roots start the first round, later
+    // samples start from the nearer neighbour's roots advanced along z'
     if (valid) {
-      const double ta = S.th[iv];
-      const int ivb = iv + 1 < N ? iv + 1 : 0;
-      const double tb = iv + 1 < N ? S.th[ivb] : S.th[ivb] + TWO_PI;
-      const bool left = thn - ta <= tb - thn;
       c64 r[5];
-      warm_start(m, left ? S.sl[iv] : S.sl[ivb], left ? thn - ta : thn - tb, r);
+      if (N == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) r[k] = T.roots[k];
+      } else {
+        const double ta = S.th[iv];
+        const int ivb = iv + 1 < N ? iv + 1 : 0;
+        const double tb = iv + 1 < N ? S.th[ivb] : S.th[ivb] + TWO_PI;
+        const bool left = thn - ta <= tb - thn;
+        warm_start(m, left ? S.sl[iv] : S.sl[ivb], left ? thn - ta : thn - tb, r);
+      }
       uint32_t sf;
       const uint32_t sw = solve_store<MIXED>(lens, yc, rho, thn, r, m, N + rank, &sf);
       sw64 += sw & 0xffffu;
@@ -595,37 +588,39 @@ __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, F
     __syncthreads();
     // merge: old position p moves up by #(new samples in intervals < p);
     // strips from the top so that no unread entry is overwritten
-    const int myivl = lane < mcount ? L.ivl[lane] : 0x7fffffff;
-    for (int base = ((N - 1) / WAVE) * WAVE; base >= 0; base -= WAVE) {
-      const int p = base + lane;
-      int sh = 0;  // number of r with ivl[r] < p (ivl ascending), 0..64
+    if (N > 0) {
+      const int myivl = lane < mcount ? L.ivl[lane] : 0x7fffffff;
+      for (int base = ((N - 1) / WAVE) * WAVE; base >= 0; base -= WAVE) {
+        const int p = base + lane;
+        int sh = 0;  // number of r with ivl[r] < p (ivl ascending), 0..64
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
-        const int v = __shfl(myivl, sh + step - 1);
-        if (v < p) sh += step;
+        for (int step = 32; step >= 1; step >>= 1) {
+          const int v = __shfl(myivl, sh + step - 1);
+          if (v < p) sh += step;
+        }
+        if (__shfl(myivl, WAVE - 1) < p) sh = WAVE;  // lifting alone stops at 63
+        double vt = 0.0, ve = 0.0;
+        uint16_t vs = 0;
+        if (p < N) {
+          vt = S.th[p];
+          ve = S.E[p];
+          vs = S.sl[p];
+        }
+        __syncthreads();
+        if (p < N && sh > 0) {
+          S.th[p + sh] = vt;
+          S.E[p + sh] = ve;
+          S.sl[p + sh] = vs;
+        }
+        __syncthreads();
       }
-      if (__shfl(myivl, WAVE - 1) < p) sh = WAVE;  // lifting alone stops at 63
-      double vt = 0.0, ve = 0.0;
-      uint16_t vs = 0;
-      if (p < N) {
-        vt = S.th[p];
-        ve = S.E[p];
-        vs = S.sl[p];
-      }
-      __syncthreads();
-      if (p < N && sh > 0) {
-        S.th[p + sh] = vt;
-        S.E[p + sh] = ve;
-        S.sl[p + sh] = vs;
-      }
-      __syncthreads();
     }
     int P = 0;
     bool first = false;
     double dAold = 0.0;
     if (valid) {
-      P = iv + 1 + rank;
-      first = rank == 0 || L.ivl[rank - 1] != iv;
+      P = N == 0 ? lane : iv + 1 + rank;
+      first = N > 0 && (rank == 0 || L.ivl[rank - 1] != iv);
       if (first) dAold = m.dA[S.sl[P - 1]];
     }
     __syncthreads();
@@ -635,36 +630,35 @@ __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, F
     }
     N += mcount;
     __syncthreads();
-    // relink the intervals touching new samples; the area total changes by
-    // the new pieces minus the replaced one (compensated)
+    // relink the intervals touching new samples: the one starting at the
+    // new sample, and for the first new sample of a split interval the one
+    // ending there; the area total changes by the new pieces minus the
+    // replaced one (compensated)
     double dh = 0.0, dl = 0.0;
-    if (valid) {
-      const Piece p1 = relink(m, S, P, N);
-      ++nint;
-      double s, e;
-      two_sum(dh, p1.dA, s, e);
-      dh = s;
-      dl += e;
-      uint32_t f = p1.fl;
-      if (first) {
-        const Piece p0 = relink(m, S, P - 1, N);
+#pragma unroll 1
+    for (int j = 0; j < 2; ++j) {
+      if (valid && (j == 0 || first)) {
+        const Piece pc = relink(m, S, j == 0 ? P : P - 1, N);
         ++nint;
-        f |= p0.fl;
-        two_sum(dh, p0.dA, s, e);
-        dh = s;
-        dl += e;
-        two_sum(dh, -dAold, s, e);
-        dh = s;
-        dl += e;
+        double s1, e1;
+        two_sum(dh, pc.dA, s1, e1);
+        dh = s1;
+        dl += e1;
+        if (pc.fl & IF_ANOMALY) fl |= F_ANOMALY;
       }
-      if (f & IF_ANOMALY) fl |= F_ANOMALY;
+    }
+    if (first) {
+      double s1, e1;
+      two_sum(dh, -dAold, s1, e1);
+      dh = s1;
+      dl += e1;
     }
     wave_sum_comp(dh, dl);
     {
-      double s, e;
-      two_sum(Ahi, dh, s, e);
-      Ahi = s;
-      Alo += dl + e;
+      double s1, e1;
+      two_sum(Ahi, dh, s1, e1);
+      Ahi = s1;
+      Alo += dl + e1;
     }
     __syncthreads();
   }
