@@ -61,10 +61,12 @@ def lib():
         L.twk_ref_ld_combine.argtypes = [C.c_double, C.c_int32, _dp, _dp]
         L.twk_ref_ps_adequate.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
                                           C.c_double, C.c_double, _ip, _dp]
+        L.twk_ref_features.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, C.c_double, C.POINTER(C.c_float), _dp, _ip]
         for name in ("twk_ref_coeffs", "twk_ref_coeffs_conventional", "twk_ref_roots",
                      "twk_ref_images", "twk_ref_point_mag", "twk_ref_limb_derivs",
                      "twk_ref_finite_mag", "twk_ref_finite_trace", "twk_ref_trajectory",
-                     "twk_ref_ld_combine", "twk_ref_ps_adequate"):
+                     "twk_ref_ld_combine", "twk_ref_ps_adequate", "twk_ref_features"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -196,3 +198,14 @@ def ps_adequate(s, q, zeta, rho, tol):
     _check(lib().twk_ref_ps_adequate(s, q, float(np.real(zeta)), float(np.imag(zeta)), rho, tol,
                                      C.byref(ok), C.byref(mu)))
     return bool(ok.value), mu.value
+
+
+def features(s, q, zeta, rho, tol):
+    """The eight float32 features of one epoch, mu_ps and the adequacy flag."""
+    f = np.zeros(8, dtype=np.float32)
+    ok = C.c_int32()
+    mu = C.c_double()
+    _check(lib().twk_ref_features(s, q, float(np.real(zeta)), float(np.imag(zeta)), rho, tol,
+                                  f.ctypes.data_as(C.POINTER(C.c_float)), C.byref(mu),
+                                  C.byref(ok)))
+    return f, mu.value, bool(ok.value)

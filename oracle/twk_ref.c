@@ -1019,28 +1019,93 @@ int twk_ref_ld_combine(double gamma, int32_t na, const double *mu_k,
 #define PS_CQ 20.0
 #define PS_CG 8.0
 
+/* The five point-source solves of the adequacy test: the centre zeta_c and
+ * the four points zeta_c +- rho, zeta_c +- i rho, in that order. */
+typedef struct {
+  double mu[5];
+  int adequate;
+  int n0;          /* image count at the centre                         */
+  double ghost0;   /* min over the centre's ghosts of |f''| |R|^2         */
+  double pair0;    /* 5 images: min over opposite-parity real pairs of
+                      |f''(midpoint)| |z+ - z-|^2 / 4                     */
+} ps_probe_t;
+
+static void ps_probe(const lens_t *L, cplx yc, double rho, double tol,
+                     ps_probe_t *pp) {
+  cplx pts[5] = {yc, yc + rho, yc + CMPLX(0.0, rho), yc - rho,
+                 yc - CMPLX(0.0, rho)};
+  int ok = 1;
+  pp->ghost0 = INFINITY;
+  pp->pair0 = INFINITY;
+  for (int k = 0; k < 5; ++k) {
+    images_t im;
+    solve_point(L, pts[k], 100.0, &im);
+    pp->mu[k] = mu_point(&im);
+    if (im.n != 3) ok = 0;
+    for (int g = im.n; g < 5; ++g) {
+      double d = cabs(fsecond(L, im.z[g])) * creal(im.R[g] * conj(im.R[g]));
+      if (!(d > PS_CG * rho)) ok = 0;
+      if (k == 0 && d < pp->ghost0) pp->ghost0 = d;
+    }
+    if (k == 0) {
+      pp->n0 = im.n;
+      for (int a = 0; a < im.n; ++a)
+        for (int b = 0; b < im.n; ++b) {
+          if (!(im.par[a] > 0 && im.par[b] < 0)) continue;
+          cplx dz = im.z[a] - im.z[b];
+          double x = cabs(fsecond(L, 0.5 * (im.z[a] + im.z[b]))) *
+                     creal(dz * conj(dz)) / 4.0;
+          if (x < pp->pair0) pp->pair0 = x;
+        }
+    }
+  }
+  double dq = 0.5 * (0.25 * (pp->mu[1] + pp->mu[2] + pp->mu[3] + pp->mu[4]) -
+                     pp->mu[0]);
+  if (!(PS_CQ * fabs(dq) < tol * pp->mu[0])) ok = 0;
+  pp->adequate = ok;
+}
+
 int twk_ref_ps_adequate(double s, double q, double zx, double zy, double rho,
                         double tol, int32_t *adequate, double *mu_ps) {
   if (!lens_ok(s, q) || !(rho > 0.0) || !(tol > 0.0) || !adequate || !mu_ps)
     return TWK_REF_EINVAL;
   lens_t L = lens_make(s, q);
-  cplx yc = CMPLX(zx - L.z2, zy);
-  cplx pts[5] = {yc, yc + rho, yc + CMPLX(0.0, rho), yc - rho, yc - CMPLX(0.0, rho)};
-  double mu[5];
-  int ok = 1;
-  for (int k = 0; k < 5; ++k) {
-    images_t im;
-    solve_point(&L, pts[k], 100.0, &im);
-    mu[k] = mu_point(&im);
-    if (im.n != 3) ok = 0;
-    for (int g = im.n; g < 5; ++g) {
-      double d = cabs(fsecond(&L, im.z[g])) * creal(im.R[g] * conj(im.R[g]));
-      if (!(d > PS_CG * rho)) ok = 0;
-    }
-  }
-  double dq = 0.5 * (0.25 * (mu[1] + mu[2] + mu[3] + mu[4]) - mu[0]);
-  if (!(PS_CQ * fabs(dq) < tol * mu[0])) ok = 0;
-  *adequate = ok;
-  *mu_ps = mu[0];
+  ps_probe_t pp;
+  ps_probe(&L, CMPLX(zx - L.z2, zy), rho, tol, &pp);
+  *adequate = pp.adequate;
+  *mu_ps = pp.mu[0];
+  return TWK_REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Features of one epoch for the learned sample budget and FS predictor  */
+/* (not in the paper; inputs of the learned part).  READING, in order:   */
+/*  f0 s, f1 log10 q, f2 Re zeta, f3 Im zeta (centre-of-mass frame),      */
+/*  f4 log10 rho, f5 log10 mu_ps(zeta_c),                                 */
+/*  f6 caustic proximity: +log10(1 + X/rho) with three images, X the     */
+/*     centre's ghost statistic; -log10(1 + X/rho) with five, X the       */
+/*     closest opposite-parity pair statistic (both estimate the source- */
+/*     plane distance to the nearest fold),                               */
+/*  f7 log10(rho |grad mu_ps| / mu_ps) from central differences over the  */
+/*     four probe points, the argument floored at 1e-30.                  */
+/* ------------------------------------------------------------------ */
+int twk_ref_features(double s, double q, double zx, double zy, double rho,
+                     double tol, float *feat, double *mu_ps,
+                     int32_t *adequate) {
+  if (!lens_ok(s, q) || !(rho > 0.0) || !(tol > 0.0) || !feat || !mu_ps ||
+      !adequate)
+    return TWK_REF_EINVAL;
+  lens_t L = lens_make(s, q);
+  ps_probe_t pp;
+  ps_probe(&L, CMPLX(zx - L.z2, zy), rho, tol, &pp);
+  double gx = pp.mu[1] - pp.mu[3], gy = pp.mu[2] - pp.mu[4];
+  double grad = 0.5 * sqrt(gx * gx + gy * gy); /* rho |grad mu| */
+  double prox = pp.n0 == 3 ? log10(1.0 + pp.ghost0 / rho)
+                           : -log10(1.0 + pp.pair0 / rho);
+  double f[8] = {s, log10(q), zx, zy, log10(rho), log10(pp.mu[0]), prox,
+                 log10(fmax(grad / pp.mu[0], 1e-30))};
+  for (int k = 0; k < 8; ++k) feat[k] = (float)f[k];
+  *mu_ps = pp.mu[0];
+  *adequate = pp.adequate;
   return TWK_REF_OK;
 }

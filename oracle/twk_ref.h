@@ -133,6 +133,14 @@ int twk_ref_ps_adequate(double s, double q, double zeta_x, double zeta_y,
                         double rho, double tol, int32_t *adequate,
                         double *mu_ps);
 
+/* Eight features of one epoch for the learned budget / FS predictor, as
+ * float32 (order: s, log10 q, Re zeta, Im zeta, log10 rho, log10 mu_ps,
+ * signed caustic proximity, log10 of the relative gradient of mu_ps over
+ * the probe radius), plus mu_ps and the adequacy decision. */
+int twk_ref_features(double s, double q, double zeta_x, double zeta_y,
+                     double rho, double tol, float *feat, double *mu_ps,
+                     int32_t *adequate);
+
 #ifdef __cplusplus
 }
 #endif
