@@ -562,6 +562,14 @@ static void link_samples(const sample_t *a, const sample_t *b, links_t *lk) {
   lk->kind = 0;
   lk->cp = lk->cn = -1;
   lk->anomaly = 0;
+  /* A binary lens has at most two positive and three negative real images
+   * (parity sum -1, Sec. 2.3); more than three of one parity only arise
+   * from a misjudged ghost pair.  Such an interval is anomalous and linked
+   * no further. */
+  if (npa > 3 || nma > 3 || npb > 3 || nmb > 3) {
+    lk->anomaly = 1;
+    return;
+  }
   int xa[3], xb[3], nm;
   /* positive parity class */
   assign(a->im.z, pa, npa, b->im.z, pb, npb, xa, xb, &nm);
