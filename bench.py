@@ -9,10 +9,14 @@ point-source test for every epoch, contour integration for the rest in one
 persistent launch.  A step is one such call over the whole batch; inputs
 are resident in device memory before timing starts.
 
-Prints one JSON line (rank 0) with the value, the roofline of the dominant
-kernel (the persistent contour kernel, VALU-bound), the plain FP64 path
-beside it, and the CPU oracle timed on a bounded sample of the same
-workload.
+Paths timed (same call, mode bits differ): plain FP64 (no learned budget),
++ mixed precision (FP32 bulk root iterations), + learned budget (the MLP's
+starting grid and longest-first queue).  The headline value is the learned
++ mixed path; the others are reported beside it.
+
+Prints one JSON line with the value, the roofline of the dominant kernel
+(the persistent contour kernel, VALU-bound), and the CPU oracle timed on a
+bounded sample of the same workload.
 """
 import argparse
 import json
@@ -25,7 +29,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
-METRIC = "finite-source magnifications/sec at <=1e-4 rel. err, learned-batched vs plain GPU"
+METRIC = "finite-source magnifications/sec at \u22641e-4 rel. err, learned-batched vs plain GPU"
 
 # Algorithmic floating-point work of the contour kernel, counted by hand
 # from the device code (FMA = 2 flops, add/mul/rcp/sqrt = 1).  Units: one
@@ -63,6 +67,7 @@ def run_path(ctx, dev, c, mode, steps, warmup, label):
         log(f"[{label}] warmup {w + 1}/{warmup} done")
     fs_ms = []
     tot_ms = []
+    mlp_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -70,8 +75,10 @@ def run_path(ctx, dev, c, mode, steps, warmup, label):
         kt = ctx.kernel_times()  # waits for this step
         fs_ms.append(kt["fs_ms"])
         tot_ms.append(kt["total_ms"])
+        mlp_ms.append(kt["mlp_ms"])
         log(f"[{label}] step {k + 1}/{steps}: {kt['total_ms']:.2f} ms (contour kernel {kt['fs_ms']:.2f} ms,"
-            f" point pass {kt['ps_ms']:.2f} ms, rest {kt['rest_ms']:.2f} ms)")
+            f" point pass {kt['ps_ms']:.2f} ms, learned stage {kt['mlp_ms']:.2f} ms,"
+            f" rest {kt['rest_ms']:.2f} ms)")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = ctx.stats()
@@ -81,7 +88,7 @@ def run_path(ctx, dev, c, mode, steps, warmup, label):
     nfs = ns[(fl & 1) == 0]
     hist = {f"<= {b}": int(np.sum(nfs <= b)) for b in (64, 128, 256, 512, 1024, 2048, 4096)}
     return dict(ms_per_step=1e3 * wall / steps, fs_kernel_ms=float(np.mean(fs_ms)),
-                event_ms=float(np.mean(tot_ms)), stats=st,
+                event_ms=float(np.mean(tot_ms)), mlp_ms=float(np.mean(mlp_ms)), stats=st,
                 fs_fraction=float(np.mean((fl & 1) == 0)), mag=out[0],
                 samples_hist=hist, samples_max=int(nfs.max()) if nfs.size else 0)
 
@@ -111,6 +118,40 @@ def cpu_baseline(c, seconds, seed=11):
                        f"{dt:.1f} s")
 
 
+WEIGHTS = os.path.join(HERE, "paper_2501_03322_amd", "weights", "mlp_budget.bin")
+TRAFFIC = os.path.join(HERE, "profiles", "k_fs_traffic.json")
+
+
+def lib_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(lib_path):
+    """HBM bytes per launch of the contour kernel from the committed counter
+    runs (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
+    valid only for the library build they were taken on."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    with open(TRAFFIC) as f:
+        t = json.load(f)
+    if t.get("lib_sha256") != lib_digest(lib_path):
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def path_summary(n, r):
+    st = r["stats"]
+    fs_s = r["fs_kernel_ms"] * 1e-3
+    return {"value": n / (r["ms_per_step"] * 1e-3), "ms_per_step": r["ms_per_step"],
+            "fs_kernel_ms": r["fs_kernel_ms"], "learned_stage_ms": r["mlp_ms"],
+            "contour_mags_per_s": st["fs_tasks"] / fs_s,
+            "limb_solves_per_s": st["samples"] / fs_s,
+            "achieved_tflops": flops_of(st) / fs_s / 1e12,
+            "samples": int(st["samples"]), "fs_tasks": int(st["fs_tasks"])}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,7 +159,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="time only the headline path (for profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -131,16 +173,25 @@ def main():
 
     dev = torch.device("cuda", 0)
     ctx = twk.Context(0)
+    if not os.path.exists(WEIGHTS):
+        log(f"{WEIGHTS} missing: training the learned budget first")
+        from paper_2501_03322_amd import train_mlp
+        train_mlp.train(WEIGHTS, log=log)
+    ctx.mlp_load(WEIGHTS)
     c = inputs.batched_curves()
     n = c.nsets * c.nepochs
     log(f"workload: {c.nsets} sets x {c.nepochs} epochs = {n} magnifications, tol {c.tol}")
 
-    best = run_path(ctx, dev, c, twk.MODE_MIXED, args.steps, args.warmup, "mixed")
-    plain = None
+    best = run_path(ctx, dev, c, twk.MODE_MLP | twk.MODE_MIXED, args.steps, args.warmup,
+                    "learned+mixed")
+    others = {}
     if not args.no_plain:
-        plain = run_path(ctx, dev, c, twk.MODE_FP64, args.steps, args.warmup, "fp64")
-        rel = (best["mag"] / plain["mag"] - 1).abs().max().item()
-        log(f"max relative difference mixed vs fp64 over the batch: {rel:.3g}")
+        others["mixed"] = run_path(ctx, dev, c, twk.MODE_MIXED, args.steps, args.warmup, "mixed")
+        others["plain_fp64"] = run_path(ctx, dev, c, twk.MODE_FP64, args.steps, args.warmup, "fp64")
+        for k, r in others.items():
+            rel = (best["mag"] / r["mag"] - 1).abs().max().item()
+            log(f"max relative difference learned+mixed vs {k} over the batch: {rel:.3g}")
+            r["max_rel_diff_vs_headline"] = rel
 
     if args.copy_probe:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -170,23 +221,22 @@ def main():
         "config": {"workload": "batched light curves: 1024 parameter sets x 2000 epochs, uniform source, "
                                "tol 1e-4, one persistent launch (seed 1)",
                    "nsets": c.nsets, "nepochs": c.nepochs, "tol": c.tol,
-                   "path": "batched persistent + mixed precision (learned budget not yet in the path)"},
+                   "path": "learned budget + batched persistent + mixed precision"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                     "traffic": measured_traffic(twk.LIB_PATH),
                      "kernel": "k_fs<512, mixed>",
                      "flops_per_launch": flops, "kernel_ms": best["fs_kernel_ms"]},
         "work": {"fs_fraction": best["fs_fraction"], **{k: int(v) for k, v in st.items()},
                  "samples_per_source_cumulative": best["samples_hist"],
                  "samples_per_source_max": best["samples_max"]},
+        "paths": {"learned+mixed": path_summary(n, best)},
     }
-    if plain is not None:
-        pst = plain["stats"]
-        pf = flops_of(pst)
-        out["plain_fp64"] = {"value": n / (plain["ms_per_step"] * 1e-3),
-                             "ms_per_step": plain["ms_per_step"],
-                             "fs_kernel_ms": plain["fs_kernel_ms"],
-                             "achieved_tflops": pf / (plain["fs_kernel_ms"] * 1e-3) / 1e12,
-                             "speedup_of_value": plain["ms_per_step"] / best["ms_per_step"]}
+    for k, r in others.items():
+        out["paths"][k] = path_summary(n, r)
+        out["paths"][k]["max_rel_diff_vs_headline"] = r["max_rel_diff_vs_headline"]
+    if "plain_fp64" in others:
+        out["speedup_vs_plain_fp64"] = others["plain_fp64"]["ms_per_step"] / best["ms_per_step"]
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle for about {args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds)

@@ -87,9 +87,14 @@ int twk_point_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *zet
  * Outputs (device, length n): mag = area/(pi rho^2); err = error estimate
  * in the same units; n_samples = limb samples used; flags.
  * mode: TWK_MODE_FP64 or TWK_MODE_MIXED; without TWK_MODE_ALL_FS the
- * point-source test may return the point value (flag bit 0).
+ * point-source test may return the point value (flag bit 0).  With
+ * TWK_MODE_MLP the learned budget (weights from twk_mlp_set/load/train)
+ * sets each contour's starting grid (a multiple of 64, at most 512 uniform
+ * samples) and the queue runs sources longest first; the stop rule and the
+ * tolerance are unchanged.
  * Errors: TWK_EINVAL for s, q, rho, tol <= 0 or non-finite, n < 0, NULL
- * pointers or unknown mode bits; TWK_ENOMEM / TWK_EDEVICE. */
+ * pointers or unknown mode bits; TWK_ENOMLP for TWK_MODE_MLP without
+ * weights; TWK_ENOMEM / TWK_EDEVICE. */
 int twk_finite_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *zeta_x,
                    const double *zeta_y, double rho, double tol, uint32_t mode, double *mag,
                    double *err, int32_t *n_samples, uint32_t *flags);
@@ -133,11 +138,117 @@ int twk_last_stats(twk_ctx *ctx, int64_t *out8);
 
 /* Per-kernel timing with HIP events on the context's stream (on != 0 to
  * enable).  After a finite-source call, twk_kernel_times writes (host
- * pointer ms[4], milliseconds): point-source pass and contour kernel of the
- * first chunk, the rest of the call, whole call.  Waits for the call.
+ * pointer ms[5], milliseconds): for the first chunk the point-source pass,
+ * the learned stage (0 without TWK_MODE_MLP) and the contour kernel; then
+ * the rest of the call and the whole call.  Waits for the call.
  * Errors: TWK_EINVAL if timing is off. */
 int twk_enable_timing(twk_ctx *ctx, int on);
-int twk_kernel_times(twk_ctx *ctx, double *ms4);
+int twk_kernel_times(twk_ctx *ctx, double *ms5);
+
+/* ------------------------------------------------------------------------
+ * Launch tuning of the contour stage and graph replay.  None of these
+ * change the arithmetic of a source except budget_shift (which moves the
+ * learned starting grid; results stay within the tolerance).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t waves_per_cu; /* resident contour waves per CU: the persistent grid is
+                           waves_per_cu x CUs; 1 .. the occupancy limit of lds_cap */
+  int32_t lds_cap;      /* limb samples a source keeps in LDS before continuing in
+                           global memory: 256, 512 or 1024 */
+  float budget_shift;   /* learned path: starting grid from 2^(predicted log2 N -
+                           budget_shift), in [-2, 4] */
+  int32_t graphs;       /* 1: capture each call's launch sequence in a hipGraph and
+                           replay it when an identical call (same arguments and
+                           pointers) repeats; needs a created (non-null) stream */
+} twk_tuning;
+
+/* Current tuning (defaults: the occupancy limit at lds_cap 512, shift 1, no
+ * graphs). */
+int twk_get_tuning(twk_ctx *ctx, twk_tuning *out);
+/* Set the tuning; synchronises the stream and drops captured graphs.
+ * TWK_EINVAL for values out of range (graphs on a null stream included). */
+int twk_set_tuning(twk_ctx *ctx, const twk_tuning *t);
+/* Autotuner: times twk_lightcurves on this batch (a representative sample
+ * of the workload; arguments as for twk_lightcurves) for every LDS capacity
+ * and four persistent grid sizes, then, with TWK_MODE_MLP, six budget
+ * shifts, taking the fastest of `trials` (1..100) calls per candidate; the
+ * best tuning is left in the context (graphs setting unchanged) and copied
+ * to *best (may be NULL).  Synchronous; allocates its own output buffers. */
+int twk_autotune(twk_ctx *ctx, int64_t nsets, const double *s, const double *q,
+                 const double *u0, const double *alpha, const double *rho,
+                 const double *gamma, int64_t nepochs, const double *tau, int32_t n_annuli,
+                 double tol, uint32_t mode, int32_t trials, twk_tuning *best);
+
+/* ------------------------------------------------------------------------
+ * Learned sample budget and finite-source predictor.  Not part of the
+ * paper's method; an addition that only chooses where contour integration
+ * starts.  Model: perceptron 8 -> 128 -> 128 -> 128 -> 2 with erf-GELU
+ * activations x Phi(x), bf16 matrix-core products with float32
+ * accumulation.  Parameters: one float32 vector of TWK_MLP_NPARAM entries,
+ *   mean[8], std[8]   (features are standardised as (f - mean) / std),
+ *   W0[8][128], b0[128], W1[128][128], b1[128], W2[128][128], b2[128],
+ *   W3[128][2], b3[2]   (row-major, input index first).
+ * Outputs per row: [0] log2 of the limb-sample count the contour needs,
+ * [1] logit of "the point-source value misses the tolerance".
+ * ---------------------------------------------------------------------- */
+#define TWK_MLP_NPARAM 34450
+#define TWK_MLP_GRAD_MAX_ROWS 65536
+
+/* Per-epoch features of light-curve batches (same arguments as
+ * twk_lightcurves for the geometry): feat (device, [nsets*nepochs][8]
+ * float32) = s, log10 q, Re zeta, Im zeta, log10 rho, log10 mu_ps, signed
+ * caustic proximity (+log10(1 + X/rho) with 3 images, X = min over ghosts of
+ * |f''| |R|^2; -log10(1 + X/rho) with 5, X = min over opposite-parity real
+ * pairs of |f''(midpoint)| |z+ - z-|^2 / 4), log10 of rho |grad mu_ps| / mu_ps
+ * (central differences at zeta +- rho, zeta +- i rho, floored at 1e-30);
+ * mu_ps (device, f64) the point value; adequate (device, i32) the
+ * point-source test's decision at tolerance tol.  Non-finite centres give
+ * NaN features.  Errors: TWK_EINVAL for negative sizes, tol <= 0, NULL. */
+int twk_features(twk_ctx *ctx, int64_t nsets, const double *s, const double *q,
+                 const double *u0, const double *alpha, const double *rho, int64_t nepochs,
+                 const double *tau, double tol, float *feat, double *mu_ps, int32_t *adequate);
+
+/* Install parameters from a host vector of n = TWK_MLP_NPARAM floats
+ * (copied; synchronous).  TWK_EINVAL for a wrong n, non-finite entries or
+ * std <= 0. */
+int twk_mlp_set(twk_ctx *ctx, const float *host_params, int64_t n);
+/* Copy the current parameters to a host vector (synchronous); TWK_ENOMLP if none. */
+int twk_mlp_get(twk_ctx *ctx, float *host_params, int64_t n);
+/* Weight file: 8 bytes "TWKMLP01", int32 count (= TWK_MLP_NPARAM), then the
+ * float32 parameter vector, little-endian.  TWK_EINVAL for unreadable or
+ * malformed files (the context keeps its previous weights). */
+int twk_mlp_save(twk_ctx *ctx, const char *path);
+int twk_mlp_load(twk_ctx *ctx, const char *path);
+
+/* Inference on n rows: feat (device, [n][8] raw features) -> out (device,
+ * [n][2] float32).  Asynchronous.  TWK_ENOMLP without weights. */
+int twk_mlp_infer(twk_ctx *ctx, int64_t n, const float *feat, float *out);
+
+/* Loss and gradient on one batch of n (1..TWK_MLP_GRAD_MAX_ROWS) rows:
+ * loss = mean Huber(out0 - y_budget; delta) + mean BCE-with-logits(out1,
+ * y_fs).  grad (device, TWK_MLP_NPARAM floats, same layout as the
+ * parameters; the 16 standardisation entries are set to 0); *loss (host).
+ * Synchronous.  The device work area is shared with twk_mlp_train. */
+int twk_mlp_grad(twk_ctx *ctx, int64_t n, const float *feat, const float *y_budget,
+                 const float *y_fs, float huber_delta, float *grad, double *loss);
+
+typedef struct {
+  int32_t epochs;      /* passes over the rows                              */
+  int32_t batch;       /* rows per Adam step, 32 .. TWK_MLP_GRAD_MAX_ROWS    */
+  float lr, lr_end;    /* Adam step size, decayed linearly to lr_end         */
+  float beta1, beta2, eps;
+  float huber_delta;
+  int32_t init;        /* 1: standardise from these rows and draw fresh       */
+                       /*    He-normal weights; 0: continue from the current  */
+  uint64_t seed;       /* initialisation and shuffles (splitmix64)           */
+} twk_train_cfg;
+
+/* Minibatch Adam training on n rows (device: feat [n][8], y_budget [n],
+ * y_fs [n] in {0,1}); every epoch visits the rows in a fresh shuffled order
+ * and drops the last n mod batch.  loss_hist (host, may be NULL) receives
+ * the mean loss of each epoch.  Synchronous; deterministic for a seed. */
+int twk_mlp_train(twk_ctx *ctx, int64_t n, const float *feat, const float *y_budget,
+                  const float *y_fs, const twk_train_cfg *cfg, float *loss_hist);
 
 #ifdef __cplusplus
 }

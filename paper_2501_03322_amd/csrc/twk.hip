@@ -20,17 +20,23 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "../../include/twk.h"
 #include "twk_device.h"
 #include "twk_fs.h"
+#include "twk_mlp.h"
 
 using namespace twk;
 
 namespace {
 
-constexpr int LDS_CAP = 512;  // limb samples a source keeps in LDS before spilling
+// Limb samples a source keeps in LDS before spilling to global memory: one
+// persistent-kernel instantiation per choice; the tuning picks one.
+constexpr int LDS_CAPS[3] = {256, 512, 1024};
+constexpr int BUDGET_MAX = 512;  // largest learned starting grid
 
 // Counters in device memory (int64 each).
 enum {
@@ -44,9 +50,11 @@ enum {
   C_INTERVALS = 7, // intervals linked
   C_RUNS = 8,      // contour runs
   C_NFS = 9,       // limb-darkened epochs sent to the annulus contours
-  C_SPARE = 15,
-  C_NCOUNTERS = 16
+  C_BUCKET = 16,   // learned path: tasks per budget class (7 classes)
+  C_CURSOR = 24,   // learned path: fill cursors of the classes
+  C_NCOUNTERS = 32
 };
+constexpr int NBUCKET = 7;  // predicted sample counts 2^6 .. >= 2^12
 
 // Point-source adequacy test.  The paper (Sec. 2.3) applies the quadrupole
 // test and the ghost-image test before any contour work but gives no
@@ -74,10 +82,31 @@ struct PsResult {
   uint32_t flags;
   bool adequate;
   c64 roots[5];
+  double gx, gy;  // mu(zeta_c + rho) - mu(zeta_c - rho), same along i rho
+  double ghost0;  // three images at the centre: min ghost statistic
+  double pair0;   // five images at the centre: min opposite-parity pair statistic
 };
 
+// |f''(midpoint)| |z+ - z-|^2 / 4 minimised over opposite-parity real pairs:
+// like the ghost statistic, an estimate of the source's distance to the
+// fold that created the pair.
+__device__ inline double pair_stat(const Lens& L, const Images& im) {
+  const int npos = __popc(im.par);
+  double best = INFINITY;
+  for (int a = 0; a < npos; ++a)
+    for (int b = npos; b < im.n; ++b) {
+      const c64 mid = 0.5 * (im.z[a] + im.z[b]);
+      const c64 a1 = mid + L.s;
+      const c64 f2 = -2.0 * (L.m1 * cinv(a1 * a1 * a1) + L.m2 * cinv(mid * mid * mid));
+      best = fmin(best, 0.25 * cabs64(f2) * cnorm(im.z[a] - im.z[b]));
+    }
+  return best;
+}
+
+// probe: solve the four stencil points (needed by the test and by the
+// learned features); test: decide adequacy.
 __device__ inline PsResult point_source_pass(const Lens& L, c64 yc, double rho, double tol,
-                                             bool test) {
+                                             bool probe, bool test) {
   PsResult out;
   c64 c[6], r[5];
   coefficients(L, yc, c);
@@ -88,19 +117,31 @@ __device__ inline PsResult point_source_pass(const Lens& L, c64 yc, double rho, 
   out.mu = point_mag(im);
   out.n = im.n;
   out.flags = im.flags;
+  out.adequate = false;
+  out.ghost0 = INFINITY;
+  out.pair0 = INFINITY;
 #pragma unroll
   for (int k = 0; k < 5; ++k) out.roots[k] = im.z[k];
-  if (!test) {
-    out.adequate = false;
-    return out;
-  }
+  if (!probe) return out;
   bool ok = im.n == 3;
-  for (int g = 3; g < 5; ++g)
-    if (!(ghost_stat(L, yc, im.z[g]) > PS_CG * rho)) ok = false;
+  if (im.n == 3) {
+    for (int g = 3; g < 5; ++g) {
+      const double gs = ghost_stat(L, yc, im.z[g]);
+      out.ghost0 = fmin(out.ghost0, gs);
+      if (!(gs > PS_CG * rho)) ok = false;
+    }
+  } else {
+    out.pair0 = pair_stat(L, im);
+  }
   double mus = 0.0;
-  const c64 off[4] = {cz(rho, 0.0), cz(0.0, rho), cz(-rho, 0.0), cz(0.0, -rho)};
+  out.gx = 0.0;
+  out.gy = 0.0;
+#pragma unroll 1
   for (int k = 0; k < 4; ++k) {
-    const c64 y = yc + off[k];
+    // stencil point k: zeta_c + rho, + i rho, - rho, - i rho
+    const double sx = k == 0 ? rho : (k == 2 ? -rho : 0.0);
+    const double sy = k == 1 ? rho : (k == 3 ? -rho : 0.0);
+    const c64 y = yc + cz(sx, sy);
     coefficients(L, y, c);
 #pragma unroll
     for (int j = 0; j < 5; ++j) r[j] = out.roots[j];
@@ -110,15 +151,39 @@ __device__ inline PsResult point_source_pass(const Lens& L, c64 yc, double rho, 
     }
     Images ik;
     finish_images(L, y, r, ik);
-    mus += point_mag(ik);
+    const double mk = point_mag(ik);
+    mus += mk;
+    const double sg = k < 2 ? 1.0 : -1.0;
+    if (k & 1) out.gy += sg * mk;
+    else out.gx += sg * mk;
     if (ik.n != 3) ok = false;
     for (int g = 3; g < 5; ++g)
       if (!(ghost_stat(L, y, ik.z[g]) > PS_CG * rho)) ok = false;
   }
   const double dq = 0.5 * (0.25 * mus - out.mu);
   if (!(PS_CQ * fabs(dq) < tol * out.mu)) ok = false;
-  out.adequate = ok;
+  out.adequate = test && ok;
   return out;
+}
+
+// The eight inputs of the learned budget (centre-of-mass frame):
+// s, log10 q, Re zeta, Im zeta, log10 rho, log10 mu_ps, the signed caustic
+// proximity +-log10(1 + X / rho) (+ with three images and X the ghost
+// statistic, - with five and X the pair statistic), and log10 of
+// rho |grad mu_ps| / mu_ps from central differences over the stencil,
+// floored at 1e-30.
+__device__ inline void ps_features(double s, double q, double zx, double zy, double rho,
+                                   const PsResult& ps, float* f) {
+  const double grad = 0.5 * sqrt(ps.gx * ps.gx + ps.gy * ps.gy);
+  const double prox = ps.n == 3 ? log10(1.0 + ps.ghost0 / rho) : -log10(1.0 + ps.pair0 / rho);
+  f[0] = (float)s;
+  f[1] = (float)log10(q);
+  f[2] = (float)zx;
+  f[3] = (float)zy;
+  f[4] = (float)log10(rho);
+  f[5] = (float)log10(ps.mu);
+  f[6] = (float)prox;
+  f[7] = (float)log10(fmax(grad / ps.mu, 1e-30));
 }
 
 // Clear all counters (start of a call) or only the queue counters (start of
@@ -126,7 +191,7 @@ __device__ inline PsResult point_source_pass(const Lens& L, c64 yc, double rho, 
 __global__ void k_reset(long long* cnt, int queue_only) {
   const int i = threadIdx.x;
   if (i >= C_NCOUNTERS) return;
-  if (!queue_only || i == C_NTASK || i == C_HEAD || i == C_NFS) cnt[i] = 0;
+  if (!queue_only || i == C_NTASK || i == C_HEAD || i == C_NFS || i >= C_BUCKET) cnt[i] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_point(double s, double q, int64_t n, const double* zx,
@@ -173,7 +238,7 @@ __device__ inline int64_t queue_push(bool push, int count, long long* counter) {
 __device__ inline void emit_source(int64_t out, double s, double q, double zx, double zy,
                                    double rho, double tol, bool all_fs, int na, Task* tasks,
                                    long long* cnt, int64_t* fs_epoch, double* mag, double* err,
-                                   int32_t* ns, uint32_t* flags, bool active) {
+                                   int32_t* ns, uint32_t* flags, bool active, float* tfeat) {
   bool push = false;
   PsResult ps;
   const Lens L = make_lens(s, q);
@@ -185,7 +250,7 @@ __device__ inline void emit_source(int64_t out, double s, double q, double zx, d
       ns[out] = 0;
       flags[out] = F_NONFINITE;
     } else {
-      ps = point_source_pass(L, cz(zx - L.z2, zy), rho, tol, !all_fs);
+      ps = point_source_pass(L, cz(zx - L.z2, zy), rho, tol, !all_fs || tfeat, !all_fs);
       if (ps.adequate) {
         mag[out] = ps.mu;
         err[out] = 0.0;
@@ -218,6 +283,14 @@ __device__ inline void emit_source(int64_t out, double s, double q, double zx, d
       t.rho = na > 1 ? rho * sqrt((double)(k + 1) / na) : rho;
       tasks[slot + k] = t;
     }
+    if (tfeat) {
+      // every annulus of a limb-darkened epoch shares the epoch's features
+      float f[8];
+      ps_features(s, q, zx, zy, rho, ps, f);
+      for (int k = 0; k < na; ++k)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) tfeat[(slot + k) * 8 + j] = f[j];
+    }
   }
 }
 
@@ -225,11 +298,11 @@ __global__ __launch_bounds__(256) void k_prep(double s, double q, int64_t n, con
                                               const double* zy, double rho, double tol,
                                               int all_fs, Task* tasks, long long* cnt,
                                               double* mag, double* err, int32_t* ns,
-                                              uint32_t* flags) {
+                                              uint32_t* flags, float* tfeat) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = i < n;
   emit_source(i, s, q, active ? zx[i] : 0.0, active ? zy[i] : 0.0, rho, tol, all_fs != 0, 1, tasks,
-              cnt, nullptr, mag, err, ns, flags, active);
+              cnt, nullptr, mag, err, ns, flags, active, tfeat);
 }
 
 // Magnification map: pixel (ix, iy) of an nx x ny grid over the box
@@ -239,7 +312,8 @@ __global__ __launch_bounds__(256) void k_map(double s, double q, double rho, dou
                                              double w, double h, int32_t nx, int32_t ny,
                                              int64_t iy0, int64_t nrows, double tol, int all_fs,
                                              Task* tasks, long long* cnt, double* mag,
-                                             double* err, int32_t* ns, uint32_t* flags) {
+                                             double* err, int32_t* ns, uint32_t* flags,
+                                             float* tfeat) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = i < nrows * (int64_t)nx;
   double zx = 0.0, zy = 0.0;
@@ -251,7 +325,7 @@ __global__ __launch_bounds__(256) void k_map(double s, double q, double rho, dou
     out = iy * nx + ix;
   }
   emit_source(out, s, q, zx, zy, rho, tol, all_fs != 0, 1, tasks, cnt, nullptr, mag, err, ns,
-              flags, active);
+              flags, active, tfeat);
 }
 
 // Light curves: element (set k, epoch j) at index k * nepochs + j.  Source
@@ -262,7 +336,7 @@ __global__ __launch_bounds__(256) void k_lc(int64_t nsets, const double* ps, con
                                             const double* tau, double tol, int all_fs, int na,
                                             Task* tasks, long long* cnt, int64_t* fs_epoch,
                                             double* mag, double* err, int32_t* ns,
-                                            uint32_t* flags) {
+                                            uint32_t* flags, float* tfeat) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = i < nsets * nep;
   double s = 1.0, q = 1.0, zx = 0.0, zy = 0.0, rho = 1.0;
@@ -278,7 +352,7 @@ __global__ __launch_bounds__(256) void k_lc(int64_t nsets, const double* ps, con
     zy = t * sa + u0 * ca;
   }
   emit_source(i, s, q, zx, zy, rho, tol, all_fs != 0, na, tasks, cnt, fs_epoch, mag, err, ns,
-              flags, active);
+              flags, active, tfeat);
 }
 
 // Linear limb darkening over na equal-area annuli (x_k = k/na of the squared
@@ -317,6 +391,94 @@ __global__ __launch_bounds__(256) void k_ld(const long long* cnt, const int64_t*
   flags[i] = fl;
 }
 
+// Features of every epoch of a light-curve batch (inputs of the learned
+// budget), with the point value and the adequacy decision.
+__global__ __launch_bounds__(256) void k_feat(int64_t nsets, const double* ps, const double* pq,
+                                              const double* pu0, const double* pal,
+                                              const double* prho, int64_t nep,
+                                              const double* tau, double tol, float* feat,
+                                              double* mu, int32_t* adequate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsets * nep) return;
+  const int64_t k = i / nep, j = i - k * nep;
+  double sa, ca;
+  sincos(pal[k], &sa, &ca);
+  const double t = tau[j], u0 = pu0[k];
+  const double zx = t * ca - u0 * sa, zy = t * sa + u0 * ca;
+  const Lens L = make_lens(ps[k], pq[k]);
+  if (!isfinite(zx) || !isfinite(zy)) {
+#pragma unroll
+    for (int f = 0; f < 8; ++f) feat[i * 8 + f] = __builtin_nanf("");
+    mu[i] = __builtin_nan("");
+    adequate[i] = 0;
+    return;
+  }
+  const PsResult r = point_source_pass(L, cz(zx - L.z2, zy), prho[k], tol, true, true);
+  float f[8];
+  ps_features(ps[k], pq[k], zx, zy, prho[k], r, f);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) feat[i * 8 + c] = f[c];
+  mu[i] = r.mu;
+  adequate[i] = r.adequate ? 1 : 0;
+}
+
+// Learned budget of each queued task from the predicted log2 sample count
+// (lowered by `shift` so that the uniform start rarely overshoots): the
+// starting grid n0 is the largest multiple of 64 not above 2^(l2 - shift),
+// within [64, BUDGET_MAX]; tasks are also counted into classes
+// floor(l2) - 6.  Counts are gathered per block in LDS and added to the
+// global class counters with one atomic per class and block.
+__device__ inline int budget_class(float l2) {
+  return min(max((int)floorf(l2) - 6, 0), NBUCKET - 1);
+}
+
+__global__ __launch_bounds__(256) void k_budget(long long* cnt, const float* out, int32_t* tn0,
+                                                float shift) {
+  __shared__ int hist[NBUCKET];
+  if (threadIdx.x < NBUCKET) hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt[C_NTASK]) {
+    const float l2 = out[2 * i];
+    const float want = exp2f(fminf(fmaxf(l2 - shift, 6.0f), 9.0f));
+    tn0[i] = min(max(((int)want / 64) * 64, 64), BUDGET_MAX);
+    atomicAdd(&hist[budget_class(l2)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < NBUCKET && hist[threadIdx.x] > 0)
+    atomicAdd((unsigned long long*)&cnt[C_BUCKET + threadIdx.x],
+              (unsigned long long)hist[threadIdx.x]);
+}
+
+// Longest first: class 6 (largest predicted count) leads the queue order.
+// Each block reserves one range per class (one global atomic per class)
+// and places its tasks at LDS-assigned ranks inside it.
+__global__ __launch_bounds__(256) void k_place(long long* cnt, const float* out, int32_t* order) {
+  __shared__ int hist[NBUCKET];
+  __shared__ long long base[NBUCKET];
+  if (threadIdx.x < NBUCKET) hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool on = i < cnt[C_NTASK];
+  int b = 0, rank = 0;
+  if (on) {
+    b = budget_class(out[2 * i]);
+    rank = atomicAdd(&hist[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < NBUCKET) {
+    long long start = 0;
+    for (int c = NBUCKET - 1; c > (int)threadIdx.x; --c) start += cnt[C_BUCKET + c];
+    base[threadIdx.x] =
+        start + (hist[threadIdx.x] > 0
+                     ? (long long)atomicAdd((unsigned long long*)&cnt[C_CURSOR + threadIdx.x],
+                                            (unsigned long long)hist[threadIdx.x])
+                     : 0ll);
+  }
+  __syncthreads();
+  if (on) order[base[b] + rank] = (int32_t)i;
+}
+
 // Persistent finite-source kernel: each wave pops tasks until the queue is
 // drained (every wave reaches the exit: the queue length is fixed before
 // launch and each pop advances the head).
@@ -327,7 +489,8 @@ template <int LCAP, bool MIXED>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES_PER_EU))) void k_fs(const Task* tasks, const long long* ntask,
                                            long long* head, double tol, char* scratch,
                                            double* mag, double* err, int32_t* ns,
-                                           uint32_t* flags, long long* cnt) {
+                                           uint32_t* flags, long long* cnt,
+                                           const int32_t* order, const int32_t* tn0) {
   __shared__ FsLds<LCAP> lds;
   const int lane = threadIdx.x;
   const WaveMem m = wave_mem(scratch, blockIdx.x, METHOD_CAP);
@@ -337,8 +500,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES
     if (lane == 0) t = atomicAdd((unsigned long long*)head, 1ull);
     t = __shfl(t, 0);
     if (t >= n) break;
+    if (order) t = order[t];
     const Task task = tasks[t];
-    const FsOut o = fs_source<LCAP, MIXED>(task, tol, m, lds, lane);
+    const int n0 = tn0 ? min(tn0[t], LCAP) : NNEW;
+    const FsOut o = fs_source<LCAP, MIXED>(task, tol, m, lds, lane, n0);
     if (lane == 0) {
       mag[task.out] = o.mag;
       err[task.out] = o.err;
@@ -375,7 +540,31 @@ struct twk_ctx {
   char* ann = nullptr;  // [mag f64 | err f64 | ns i32 | flags u32] x (nfs * na)
   size_t ann_bytes = 0;
   bool timing = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // launch tuning of the contour stage, and graph replay
+  twk_tuning tune{0, 512, 1.0f, 0};
+  int max_wpc[3] = {0, 0, 0};  // waves per CU the hardware allows, per LDS_CAPS entry
+  // captured launch sequences (replayed when a call repeats)
+  struct Graph {
+    uint64_t key[24];
+    hipGraphExec_t exec;
+  } graphs[4];
+  int n_graphs = 0, graph_next = 0;
+  // learned budget
+  float* mlp_p = nullptr;           // float32 master parameters
+  mlp::bf16x8* mlp_frag = nullptr;  // packed inference operands
+  bool mlp_ready = false;
+  char* lt = nullptr;               // per task: features, outputs, n0, order
+  size_t lt_bytes = 0;
+  int64_t lt_cap = 0;
+  // training
+  char* tr = nullptr;
+  size_t tr_bytes = 0;
+  float* opt = nullptr;             // gradient, first and second moments
+  int32_t* perm = nullptr;
+  size_t perm_bytes = 0;
+  double* dsum = nullptr;           // per-step losses of an epoch
+  size_t dsum_bytes = 0;
 };
 
 namespace {
@@ -391,8 +580,17 @@ int hip_fail(twk_ctx* c, hipError_t e) {
     if (e_ != hipSuccess) return hip_fail(c, e_); \
   } while (0)
 
+void drop_graphs(twk_ctx* c) {
+  for (int i = 0; i < c->n_graphs; ++i) (void)hipGraphExecDestroy(c->graphs[i].exec);
+  c->n_graphs = 0;
+  c->graph_next = 0;
+}
+
+// Grow a context buffer.  Captured launch sequences hold buffer addresses,
+// so any reallocation drops them.
 int grow(twk_ctx* c, void** p, size_t* have, size_t need) {
   if (*have >= need) return TWK_OK;
+  drop_graphs(c);
   if (*p) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e);
@@ -409,10 +607,22 @@ int grow(twk_ctx* c, void** p, size_t* have, size_t need) {
   return TWK_OK;
 }
 
-template <bool MIXED>
-int occupancy(int* blocks) {
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_fs<LDS_CAP, MIXED>, 64, 0);
+template <int LCAP>
+hipError_t occupancy(int* blocks) {
+  int b1 = 0, b2 = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fs<LCAP, false>, 64, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fs<LCAP, true>, 64, 0);
+  *blocks = std::max(1, std::min(b1, b2));
+  return e;
 }
+
+int cap_index(int lds_cap) {
+  for (int i = 0; i < 3; ++i)
+    if (LDS_CAPS[i] == lds_cap) return i;
+  return -1;
+}
+
+int fs_waves(const twk_ctx* c) { return c->tune.waves_per_cu * c->n_cu; }
 
 // Task records per chunk of a call: bounds the queue memory (128 B each).
 constexpr int64_t CHUNK_TASKS = (int64_t)1 << 24;
@@ -423,6 +633,7 @@ int ensure_fs(twk_ctx* c, int64_t ntask_max) {
   if ((rc = grow(c, (void**)&c->tasks, &have, (size_t)std::max<int64_t>(ntask_max, 1) * sizeof(Task))))
     return rc;
   c->task_cap = (int64_t)(have / sizeof(Task));
+  c->waves = fs_waves(c);
   const size_t need = (size_t)c->waves * METHOD_CAP * kSlotBytes;
   return grow(c, (void**)&c->scratch, &c->scratch_bytes, need);
 }
@@ -452,16 +663,72 @@ AnnBufs ann_bufs(twk_ctx* c, int64_t n) {
   return a;
 }
 
-int launch_fs(twk_ctx* c, bool mixed, double tol, double* mag, double* err, int32_t* ns,
-              uint32_t* flags) {
+// Per-task buffers of the learned path, carved from one allocation.
+struct LearnBufs {
+  float* feat;    // [cap x 8]
+  float* out;     // [cap x 2]
+  int32_t* n0;    // [cap]
+  int32_t* order; // [cap]
+};
+
+LearnBufs learn_bufs(twk_ctx* c) {
+  LearnBufs b;
+  b.feat = (float*)c->lt;
+  b.out = b.feat + 8 * c->lt_cap;
+  b.n0 = (int32_t*)(b.out + 2 * c->lt_cap);
+  b.order = b.n0 + c->lt_cap;
+  return b;
+}
+
+int ensure_learn(twk_ctx* c, int64_t ntask_max) {
+  const int64_t cap = std::max<int64_t>(ntask_max, 1);
+  if (c->lt_cap >= cap) return TWK_OK;
+  int rc = grow(c, (void**)&c->lt, &c->lt_bytes, (size_t)cap * 48);
+  if (rc) return rc;
+  c->lt_cap = cap;
+  return TWK_OK;
+}
+
+// Learned stage between the point-source pass and the contour kernel:
+// predict every queued task's sample count, set its starting grid, and
+// order the queue longest first.  Grids cover the chunk's task capacity;
+// threads beyond the device-side task count return at once.
+int learned_stage(twk_ctx* c, int64_t ntask_max) {
+  const LearnBufs b = learn_bufs(c);
+  hipLaunchKernelGGL(mlp::k_infer, dim3(c->n_cu), dim3(64 * mlp::INFER_WAVES), 0, c->stream,
+                     c->mlp_p, c->mlp_frag, (int64_t)0, &c->cnt[C_NTASK], b.feat, b.out);
+  HIP_TRY(c, hipGetLastError());
+  const unsigned g = (unsigned)((ntask_max + 255) / 256);
+  hipLaunchKernelGGL(k_budget, dim3(g), dim3(256), 0, c->stream, c->cnt, b.out, b.n0,
+                     c->tune.budget_shift);
+  HIP_TRY(c, hipGetLastError());
+  hipLaunchKernelGGL(k_place, dim3(g), dim3(256), 0, c->stream, c->cnt, b.out, b.order);
+  HIP_TRY(c, hipGetLastError());
+  return TWK_OK;
+}
+
+template <int LCAP>
+void launch_fs_cap(twk_ctx* c, bool mixed, double tol, double* mag, double* err, int32_t* ns,
+                   uint32_t* flags, const int32_t* order, const int32_t* n0) {
   if (mixed)
-    hipLaunchKernelGGL((k_fs<LDS_CAP, true>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
+    hipLaunchKernelGGL((k_fs<LCAP, true>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
                        &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
-                       c->cnt);
+                       c->cnt, order, n0);
   else
-    hipLaunchKernelGGL((k_fs<LDS_CAP, false>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
+    hipLaunchKernelGGL((k_fs<LCAP, false>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
                        &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
-                       c->cnt);
+                       c->cnt, order, n0);
+}
+
+int launch_fs(twk_ctx* c, bool mixed, bool learned, double tol, double* mag, double* err,
+              int32_t* ns, uint32_t* flags) {
+  const int32_t* order = learned ? learn_bufs(c).order : nullptr;
+  const int32_t* n0 = learned ? learn_bufs(c).n0 : nullptr;
+  switch (c->tune.lds_cap) {
+    case 256: launch_fs_cap<256>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
+    case 1024: launch_fs_cap<1024>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
+    default: launch_fs_cap<512>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
+  }
   HIP_TRY(c, hipGetLastError());
   return TWK_OK;
 }
@@ -515,12 +782,13 @@ int twk_create(twk_ctx** out, int device, void* stream) {
     return TWK_EDEVICE;
   }
   c->n_cu = prop.multiProcessorCount;
-  int b1 = 0, b2 = 0;
-  if (occupancy<false>(&b1) != hipSuccess || occupancy<true>(&b2) != hipSuccess) {
+  if (occupancy<256>(&c->max_wpc[0]) != hipSuccess || occupancy<512>(&c->max_wpc[1]) != hipSuccess ||
+      occupancy<1024>(&c->max_wpc[2]) != hipSuccess) {
     delete c;
     return TWK_EDEVICE;
   }
-  c->waves = std::max(1, std::min(b1, b2)) * c->n_cu;
+  c->tune.waves_per_cu = c->max_wpc[1];
+  c->waves = fs_waves(c);
   if (hipMalloc((void**)&c->cnt, C_NCOUNTERS * sizeof(long long)) != hipSuccess) {
     delete c;
     return TWK_ENOMEM;
@@ -538,8 +806,16 @@ int twk_destroy(twk_ctx* c) {
   (void)hipFree(c->cnt);
   (void)hipFree(c->fs_epoch);
   (void)hipFree(c->ann);
-  for (int i = 0; i < 4; ++i)
+  drop_graphs(c);
+  for (int i = 0; i < 5; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  (void)hipFree(c->mlp_p);
+  (void)hipFree(c->mlp_frag);
+  (void)hipFree(c->lt);
+  (void)hipFree(c->tr);
+  (void)hipFree(c->opt);
+  (void)hipFree(c->perm);
+  (void)hipFree(c->dsum);
   delete c;
   return TWK_OK;
 }
@@ -565,33 +841,131 @@ int twk_point_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, c
   return TWK_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+constexpr uint32_t KNOWN_MODES = TWK_MODE_MIXED | TWK_MODE_MLP | TWK_MODE_ALL_FS;
+
+// Identity of a call for graph replay: entry point, scalar arguments (as
+// bits), device pointers, tuning and timing state.
+struct CallKey {
+  uint64_t w[24] = {};
+  int n = 0;
+  CallKey& u(uint64_t v) {
+    w[n++] = v;
+    return *this;
+  }
+  CallKey& d(double v) {
+    uint64_t b;
+    std::memcpy(&b, &v, 8);
+    return u(b);
+  }
+  CallKey& p(const void* v) { return u((uint64_t)(uintptr_t)v); }
+};
+
+CallKey& tuning_key(CallKey& k, const twk_ctx* c) {
+  uint32_t sh;
+  std::memcpy(&sh, &c->tune.budget_shift, 4);
+  return k.u((uint64_t)c->tune.waves_per_cu | ((uint64_t)c->tune.lds_cap << 20) |
+             ((uint64_t)sh << 32)).u(c->timing ? 1 : 0);
+}
+
+// Issue the launch sequence of a call, or, with graph replay on, replay
+// the captured sequence of an identical earlier call (capturing it the
+// first time).  Nothing inside `issue` may allocate or synchronise.
+template <class F>
+int run_captured(twk_ctx* c, const CallKey& key, F&& issue) {
+  if (!c->tune.graphs) return issue();
+  for (int i = 0; i < c->n_graphs; ++i)
+    if (std::memcmp(c->graphs[i].key, key.w, sizeof(key.w)) == 0) {
+      HIP_TRY(c, hipGraphLaunch(c->graphs[i].exec, c->stream));
+      return TWK_OK;
+    }
+  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  const int rc = issue();
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (rc || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : hip_fail(c, e);
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return hip_fail(c, ei);
+  int slot;
+  if (c->n_graphs < 4) {
+    slot = c->n_graphs++;
+  } else {
+    slot = c->graph_next;
+    c->graph_next = (c->graph_next + 1) % 4;
+    (void)hipGraphExecDestroy(c->graphs[slot].exec);
+  }
+  std::memcpy(c->graphs[slot].key, key.w, sizeof(key.w));
+  c->graphs[slot].exec = ex;
+  HIP_TRY(c, hipGraphLaunch(ex, c->stream));
+  return TWK_OK;
+}
+
+// Mode bits: unknown bits are rejected; the learned budget needs weights.
+int check_mode(twk_ctx* c, uint32_t mode) {
+  if (mode & ~KNOWN_MODES) return TWK_EINVAL;
+  if ((mode & TWK_MODE_MLP) && !c->mlp_ready) return TWK_ENOMLP;
+  return TWK_OK;
+}
+
+// After the point-source pass of one chunk: learned stage (if any), then
+// the contour kernel.  Events 1..3 bracket the first chunk's stages.
+int contour_stage(twk_ctx* c, bool first, bool mixed, bool learned, int64_t ntask_max,
+                  double tol, double* mag, double* err, int32_t* ns, uint32_t* flags) {
+  int rc;
+  if ((rc = mark(c, 1, first))) return rc;
+  if (learned && (rc = learned_stage(c, ntask_max))) return rc;
+  if ((rc = mark(c, 2, first))) return rc;
+  if ((rc = launch_fs(c, mixed, learned, tol, mag, err, ns, flags))) return rc;
+  return mark(c, 3, first);
+}
+
+}  // namespace
+
+extern "C" {
+
 int twk_finite_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, const double* zy,
                    double rho, double tol, uint32_t mode, double* mag, double* err, int32_t* ns,
                    uint32_t* flags) {
   if (!c || !finite_pos(s) || !finite_pos(q) || !finite_pos(rho) || !finite_pos(tol) || n < 0)
     return TWK_EINVAL;
-  if (mode & ~(TWK_MODE_MIXED | TWK_MODE_ALL_FS)) return TWK_EINVAL;
+  int rc = check_mode(c, mode);
+  if (rc) return rc;
   if (n == 0) return TWK_OK;
   if (!zx || !zy || !mag || !err || !ns || !flags) return TWK_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
   const int64_t chunk = std::min<int64_t>(n, CHUNK_TASKS);
-  int rc = ensure_fs(c, chunk);
-  if (rc) return rc;
+  const bool learned = (mode & TWK_MODE_MLP) != 0;
+  if ((rc = ensure_fs(c, chunk))) return rc;
+  if (learned && (rc = ensure_learn(c, chunk))) return rc;
   const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
   const bool mixed = (mode & TWK_MODE_MIXED) != 0;
-  if ((rc = mark(c, 0, true)) || (rc = reset(c, false))) return rc;
-  for (int64_t i0 = 0; i0 < n; i0 += chunk) {
-    const int64_t m = std::min(chunk, n - i0);
-    if (i0 > 0 && (rc = reset(c, true))) return rc;
-    hipLaunchKernelGGL(k_prep, dim3(blocks_for(m)), dim3(256), 0, c->stream, s, q, m, zx + i0,
-                       zy + i0, rho, tol, all_fs, c->tasks, c->cnt, mag + i0, err + i0, ns + i0,
-                       flags + i0);
-    HIP_TRY(c, hipGetLastError());
-    if ((rc = mark(c, 1, i0 == 0))) return rc;
-    if ((rc = launch_fs(c, mixed, tol, mag + i0, err + i0, ns + i0, flags + i0))) return rc;
-    if ((rc = mark(c, 2, i0 == 0))) return rc;
-  }
-  return mark(c, 3, true);
+  float* tfeat = learned ? learn_bufs(c).feat : nullptr;
+  CallKey key;
+  key.u(1).d(s).d(q).u((uint64_t)n).p(zx).p(zy).d(rho).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
+  return run_captured(c, tuning_key(key, c), [&]() -> int {
+    int r;
+    if ((r = mark(c, 0, true)) || (r = reset(c, false))) return r;
+    for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+      const int64_t m = std::min(chunk, n - i0);
+      if (i0 > 0 && (r = reset(c, true))) return r;
+      hipLaunchKernelGGL(k_prep, dim3(blocks_for(m)), dim3(256), 0, c->stream, s, q, m, zx + i0,
+                         zy + i0, rho, tol, all_fs, c->tasks, c->cnt, mag + i0, err + i0, ns + i0,
+                         flags + i0, tfeat);
+      HIP_TRY(c, hipGetLastError());
+      if ((r = contour_stage(c, i0 == 0, mixed, learned, m, tol, mag + i0, err + i0, ns + i0,
+                             flags + i0)))
+        return r;
+    }
+    return mark(c, 4, true);
+  });
 }
 
 int twk_mag_map(twk_ctx* c, double s, double q, double rho, double xc, double yc, double width,
@@ -601,29 +975,37 @@ int twk_mag_map(twk_ctx* c, double s, double q, double rho, double xc, double yc
       !finite_pos(width) || !finite_pos(height) || nx < 0 || ny < 0 || !std::isfinite(xc) ||
       !std::isfinite(yc))
     return TWK_EINVAL;
-  if (mode & ~(TWK_MODE_MIXED | TWK_MODE_ALL_FS)) return TWK_EINVAL;
+  int rc = check_mode(c, mode);
+  if (rc) return rc;
   const int64_t n = (int64_t)nx * ny;
   if (n == 0) return TWK_OK;
   if (!mag || !err || !ns || !flags) return TWK_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
   const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(ny, CHUNK_TASKS / nx));
-  int rc = ensure_fs(c, rows * nx);
-  if (rc) return rc;
+  const bool learned = (mode & TWK_MODE_MLP) != 0;
+  if ((rc = ensure_fs(c, rows * nx))) return rc;
+  if (learned && (rc = ensure_learn(c, rows * nx))) return rc;
   const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
   const bool mixed = (mode & TWK_MODE_MIXED) != 0;
-  if ((rc = mark(c, 0, true)) || (rc = reset(c, false))) return rc;
-  for (int64_t y0 = 0; y0 < ny; y0 += rows) {
-    const int64_t nr = std::min<int64_t>(rows, ny - y0);
-    if (y0 > 0 && (rc = reset(c, true))) return rc;
-    hipLaunchKernelGGL(k_map, dim3(blocks_for(nr * nx)), dim3(256), 0, c->stream, s, q, rho, xc, yc,
-                       width, height, nx, ny, y0, nr, tol, all_fs, c->tasks, c->cnt, mag, err, ns,
-                       flags);
-    HIP_TRY(c, hipGetLastError());
-    if ((rc = mark(c, 1, y0 == 0))) return rc;
-    if ((rc = launch_fs(c, mixed, tol, mag, err, ns, flags))) return rc;
-    if ((rc = mark(c, 2, y0 == 0))) return rc;
-  }
-  return mark(c, 3, true);
+  float* tfeat = learned ? learn_bufs(c).feat : nullptr;
+  CallKey key;
+  key.u(2).d(s).d(q).d(rho).d(xc).d(yc).d(width).d(height).u((uint64_t)nx).u((uint64_t)ny).d(tol)
+      .u(mode).p(mag).p(err).p(ns).p(flags);
+  return run_captured(c, tuning_key(key, c), [&]() -> int {
+    int r;
+    if ((r = mark(c, 0, true)) || (r = reset(c, false))) return r;
+    for (int64_t y0 = 0; y0 < ny; y0 += rows) {
+      const int64_t nr = std::min<int64_t>(rows, ny - y0);
+      if (y0 > 0 && (r = reset(c, true))) return r;
+      hipLaunchKernelGGL(k_map, dim3(blocks_for(nr * nx)), dim3(256), 0, c->stream, s, q, rho, xc,
+                         yc, width, height, nx, ny, y0, nr, tol, all_fs, c->tasks, c->cnt, mag, err,
+                         ns, flags, tfeat);
+      HIP_TRY(c, hipGetLastError());
+      if ((r = contour_stage(c, y0 == 0, mixed, learned, nr * nx, tol, mag, err, ns, flags)))
+        return r;
+    }
+    return mark(c, 4, true);
+  });
 }
 
 int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q, const double* u0,
@@ -632,7 +1014,8 @@ int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q,
                     double* err, int32_t* ns, uint32_t* flags) {
   if (!c || nsets < 0 || nepochs < 0 || !finite_pos(tol) || n_annuli < 1 || n_annuli > 64)
     return TWK_EINVAL;
-  if (mode & ~(TWK_MODE_MIXED | TWK_MODE_ALL_FS)) return TWK_EINVAL;
+  int rc = check_mode(c, mode);
+  if (rc) return rc;
   if (gamma == nullptr && n_annuli != 1) return TWK_EINVAL;
   const int64_t n = nsets * nepochs;
   if (n == 0) return TWK_OK;
@@ -642,37 +1025,46 @@ int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q,
   const int na = ld ? n_annuli : 1;
   const int64_t chunk_sets = std::max<int64_t>(1, CHUNK_TASKS / na / nepochs);
   const int64_t chunk_n = std::min(nsets, chunk_sets) * nepochs;
-  int rc = ensure_fs(c, chunk_n * na);
-  if (rc) return rc;
+  const bool learned = (mode & TWK_MODE_MLP) != 0;
+  if ((rc = ensure_fs(c, chunk_n * na))) return rc;
+  if (learned && (rc = ensure_learn(c, chunk_n * na))) return rc;
   if (ld && (rc = ensure_ld(c, chunk_n, na))) return rc;
   const AnnBufs ab = ld ? ann_bufs(c, chunk_n * na) : AnnBufs{nullptr, nullptr, nullptr, nullptr};
   const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
   const bool mixed = (mode & TWK_MODE_MIXED) != 0;
+  float* tfeat = learned ? learn_bufs(c).feat : nullptr;
   // The limb-darkened value is a weighted difference of the annulus values,
   // which roughly doubles their relative error: annuli run at tol / 2.
   const double tol_fs = ld ? 0.5 * tol : tol;
-  if ((rc = mark(c, 0, true)) || (rc = reset(c, false))) return rc;
-  for (int64_t k0 = 0; k0 < nsets; k0 += chunk_sets) {
-    const int64_t nk = std::min(chunk_sets, nsets - k0);
-    const int64_t o = k0 * nepochs;
-    if (k0 > 0 && (rc = reset(c, true))) return rc;
-    hipLaunchKernelGGL(k_lc, dim3(blocks_for(nk * nepochs)), dim3(256), 0, c->stream, nk, s + k0,
-                       q + k0, u0 + k0, alpha + k0, rho + k0, nepochs, tau, tol, all_fs, na,
-                       c->tasks, c->cnt, c->fs_epoch, mag + o, err + o, ns + o, flags + o);
-    HIP_TRY(c, hipGetLastError());
-    if ((rc = mark(c, 1, k0 == 0))) return rc;
-    if (ld) rc = launch_fs(c, mixed, tol_fs, ab.mag, ab.err, ab.ns, ab.flags);
-    else rc = launch_fs(c, mixed, tol_fs, mag + o, err + o, ns + o, flags + o);
-    if (rc) return rc;
-    if ((rc = mark(c, 2, k0 == 0))) return rc;
-    if (ld) {
-      hipLaunchKernelGGL(k_ld, dim3(blocks_for(nk * nepochs)), dim3(256), 0, c->stream, c->cnt,
-                         c->fs_epoch, na, gamma + k0, nepochs, ab.mag, ab.err, ab.ns, ab.flags,
-                         mag + o, err + o, ns + o, flags + o);
+  CallKey key;
+  key.u(3).u((uint64_t)nsets).p(s).p(q).p(u0).p(alpha).p(rho).p(gamma).u((uint64_t)nepochs).p(tau)
+      .u((uint64_t)n_annuli).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
+  return run_captured(c, tuning_key(key, c), [&]() -> int {
+    int r;
+    if ((r = mark(c, 0, true)) || (r = reset(c, false))) return r;
+    for (int64_t k0 = 0; k0 < nsets; k0 += chunk_sets) {
+      const int64_t nk = std::min(chunk_sets, nsets - k0);
+      const int64_t o = k0 * nepochs;
+      if (k0 > 0 && (r = reset(c, true))) return r;
+      hipLaunchKernelGGL(k_lc, dim3(blocks_for(nk * nepochs)), dim3(256), 0, c->stream, nk,
+                         s + k0, q + k0, u0 + k0, alpha + k0, rho + k0, nepochs, tau, tol, all_fs,
+                         na, c->tasks, c->cnt, c->fs_epoch, mag + o, err + o, ns + o, flags + o,
+                         tfeat);
       HIP_TRY(c, hipGetLastError());
+      if (ld) r = contour_stage(c, k0 == 0, mixed, learned, nk * nepochs * na, tol_fs, ab.mag,
+                                ab.err, ab.ns, ab.flags);
+      else r = contour_stage(c, k0 == 0, mixed, learned, nk * nepochs, tol_fs, mag + o, err + o,
+                             ns + o, flags + o);
+      if (r) return r;
+      if (ld) {
+        hipLaunchKernelGGL(k_ld, dim3(blocks_for(nk * nepochs)), dim3(256), 0, c->stream, c->cnt,
+                           c->fs_epoch, na, gamma + k0, nepochs, ab.mag, ab.err, ab.ns, ab.flags,
+                           mag + o, err + o, ns + o, flags + o);
+        HIP_TRY(c, hipGetLastError());
+      }
     }
-  }
-  return mark(c, 3, true);
+    return mark(c, 4, true);
+  });
 }
 
 int twk_last_stats(twk_ctx* c, int64_t* out8) {
@@ -695,24 +1087,530 @@ int twk_enable_timing(twk_ctx* c, int on) {
   if (!c) return TWK_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
   if (on && !c->ev[0])
-    for (int i = 0; i < 4; ++i) HIP_TRY(c, hipEventCreate(&c->ev[i]));
+    for (int i = 0; i < 5; ++i) HIP_TRY(c, hipEventCreate(&c->ev[i]));
   c->timing = on != 0;
   return TWK_OK;
 }
 
-int twk_kernel_times(twk_ctx* c, double* ms4) {
-  if (!c || !ms4 || !c->timing) return TWK_EINVAL;
-  HIP_TRY(c, hipEventSynchronize(c->ev[3]));
-  float a = 0.f, b = 0.f, d = 0.f, t = 0.f;
-  HIP_TRY(c, hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
-  HIP_TRY(c, hipEventElapsedTime(&b, c->ev[1], c->ev[2]));
-  HIP_TRY(c, hipEventElapsedTime(&d, c->ev[2], c->ev[3]));
-  HIP_TRY(c, hipEventElapsedTime(&t, c->ev[0], c->ev[3]));
-  ms4[0] = a;
-  ms4[1] = b;
-  ms4[2] = d;
-  ms4[3] = t;
+int twk_kernel_times(twk_ctx* c, double* ms5) {
+  if (!c || !ms5 || !c->timing) return TWK_EINVAL;
+  HIP_TRY(c, hipEventSynchronize(c->ev[4]));
+  float v[4], t = 0.f;
+  for (int i = 0; i < 4; ++i) HIP_TRY(c, hipEventElapsedTime(&v[i], c->ev[i], c->ev[i + 1]));
+  HIP_TRY(c, hipEventElapsedTime(&t, c->ev[0], c->ev[4]));
+  for (int i = 0; i < 4; ++i) ms5[i] = v[i];
+  ms5[4] = t;
   return TWK_OK;
+}
+
+int twk_features(twk_ctx* c, int64_t nsets, const double* s, const double* q, const double* u0,
+                 const double* alpha, const double* rho, int64_t nepochs, const double* tau,
+                 double tol, float* feat, double* mu_ps, int32_t* adequate) {
+  if (!c || nsets < 0 || nepochs < 0 || !finite_pos(tol)) return TWK_EINVAL;
+  const int64_t n = nsets * nepochs;
+  if (n == 0) return TWK_OK;
+  if (!s || !q || !u0 || !alpha || !rho || !tau || !feat || !mu_ps || !adequate) return TWK_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipLaunchKernelGGL(k_feat, dim3(blocks_for(n)), dim3(256), 0, c->stream, nsets, s, q, u0, alpha,
+                     rho, nepochs, tau, tol, feat, mu_ps, adequate);
+  HIP_TRY(c, hipGetLastError());
+  return TWK_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ learned part (host)
+namespace {
+
+using mlp::NPARAM;
+
+int mlp_alloc(twk_ctx* c) {
+  if (c->mlp_p) return TWK_OK;
+  if (hipMalloc((void**)&c->mlp_p, NPARAM * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&c->mlp_frag, mlp::NFRAG * 64 * sizeof(mlp::bf16x8)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(c->mlp_p);
+    (void)hipFree(c->mlp_frag);
+    c->mlp_p = nullptr;
+    c->mlp_frag = nullptr;
+    return TWK_ENOMEM;
+  }
+  return TWK_OK;
+}
+
+int mlp_pack(twk_ctx* c) {
+  hipLaunchKernelGGL(mlp::k_pack, dim3(mlp::NFRAG), dim3(64), 0, c->stream, c->mlp_p, c->mlp_frag);
+  HIP_TRY(c, hipGetLastError());
+  c->mlp_ready = true;
+  return TWK_OK;
+}
+
+bool params_valid(const float* h) {
+  for (int i = 0; i < NPARAM; ++i)
+    if (!std::isfinite(h[i])) return false;
+  for (int j = 0; j < mlp::NF; ++j)
+    if (!(h[mlp::OFF_STD + j] > 0.0f)) return false;
+  return true;
+}
+
+// splitmix64 (Steele, Lea & Flood 2014): the generator behind weight
+// initialisation and minibatch shuffles.
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t& x) { return ((splitmix64(x) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+// Box-Muller transform of two uniforms.
+double normal(uint64_t& x) {
+  const double u1 = uniform01(x), u2 = uniform01(x);
+  return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+// Training workspace for minibatches of B rows (float32 unless noted).
+struct TrainBufs {
+  float *X, *yb, *yf, *Z[3], *H[3], *O, *dO, *dA, *dB, *lrow, *work;
+};
+constexpr int KSPLIT_MAX = 16;
+
+size_t train_floats(int64_t B) {
+  return (size_t)B * (8 + 1 + 1 + 6 * mlp::HID + 2 + 2 + 2 * mlp::HID + 1) +
+         (size_t)KSPLIT_MAX * mlp::HID * mlp::HID;
+}
+
+TrainBufs train_bufs(float* base, int64_t B) {
+  TrainBufs t;
+  float* p = base;
+  auto take = [&](size_t n) { float* r = p; p += n; return r; };
+  t.X = take(B * 8);
+  t.yb = take(B);
+  t.yf = take(B);
+  for (int l = 0; l < 3; ++l) {
+    t.Z[l] = take(B * mlp::HID);
+    t.H[l] = take(B * mlp::HID);
+  }
+  t.O = take(B * 2);
+  t.dO = take(B * 2);
+  t.dA = take(B * mlp::HID);
+  t.dB = take(B * mlp::HID);
+  t.lrow = take(B);
+  t.work = take((size_t)KSPLIT_MAX * mlp::HID * mlp::HID);
+  return t;
+}
+
+int ensure_train(twk_ctx* c, int64_t B, int64_t nperm, int64_t nsteps) {
+  int rc;
+  if ((rc = grow(c, (void**)&c->tr, &c->tr_bytes, train_floats(B) * sizeof(float)))) return rc;
+  size_t have = c->opt ? (size_t)3 * NPARAM * sizeof(float) : 0;
+  if ((rc = grow(c, (void**)&c->opt, &have, (size_t)3 * NPARAM * sizeof(float)))) return rc;
+  if ((rc = grow(c, (void**)&c->perm, &c->perm_bytes,
+                 (size_t)std::max<int64_t>(nperm, 1) * sizeof(int32_t))))
+    return rc;
+  return grow(c, (void**)&c->dsum, &c->dsum_bytes, (size_t)std::max<int64_t>(nsteps, 1) * 8);
+}
+
+unsigned ew_blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// C = A B on the matrix cores (layout strides as in mlp::Gemm); K is split
+// for the weight gradients, whose contraction runs over the batch.
+int gemm(twk_ctx* c, const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk,
+         int64_t sbn, float* C, int64_t scm, int64_t scn, int M, int N, int K, float* work) {
+  mlp::Gemm g{A, sam, sak, B, sbk, sbn, C, scm, scn, M, N, K, 1, work};
+  if (K >= 512) g.ksplit = std::min(KSPLIT_MAX, K / 256);
+  dim3 grid((M + 31) / 32, (N + 31) / 32, g.ksplit);
+  hipLaunchKernelGGL(mlp::k_gemm, grid, dim3(64), 0, c->stream, g);
+  HIP_TRY(c, hipGetLastError());
+  if (g.ksplit > 1) {
+    hipLaunchKernelGGL(mlp::k_split_sum, dim3(ew_blocks((int64_t)M * N)), dim3(256), 0, c->stream,
+                       work, g.ksplit, M, N, C, scm, scn);
+    HIP_TRY(c, hipGetLastError());
+  }
+  return TWK_OK;
+}
+
+// Forward and backward pass of one standardised minibatch already in t.X,
+// t.yb, t.yf: gradient of the mean loss into G (flat parameter layout; the
+// standardisation entries are left alone), batch loss sum into *lsum.
+int forward_backward(twk_ctx* c, const TrainBufs& t, int64_t rows, float delta, float* G,
+                     double* lsum) {
+  using namespace mlp;
+  const float* P = c->mlp_p;
+  const int R = (int)rows;
+  int rc;
+  const int64_t offW[4] = {OFF_W0, OFF_W1, OFF_W2, OFF_W3};
+  const int64_t offB[4] = {OFF_B0, OFF_B1, OFF_B2, OFF_B3};
+  // forward
+  const float* in = t.X;
+  int64_t kin = NF;
+  for (int l = 0; l < 3; ++l) {
+    if ((rc = gemm(c, in, kin, 1, P + offW[l], HID, 1, t.Z[l], HID, 1, R, HID, (int)kin, t.work)))
+      return rc;
+    hipLaunchKernelGGL(k_bias_act, dim3(ew_blocks(rows * HID)), dim3(256), 0, c->stream, t.Z[l],
+                       P + offB[l], t.H[l], rows, HID);
+    HIP_TRY(c, hipGetLastError());
+    in = t.H[l];
+    kin = HID;
+  }
+  if ((rc = gemm(c, t.H[2], HID, 1, P + OFF_W3, NO, 1, t.O, NO, 1, R, NO, HID, t.work))) return rc;
+  hipLaunchKernelGGL(k_bias_act, dim3(ew_blocks(rows * NO)), dim3(256), 0, c->stream, t.O,
+                     P + OFF_B3, (float*)nullptr, rows, NO);
+  HIP_TRY(c, hipGetLastError());
+  hipLaunchKernelGGL(k_loss, dim3(ew_blocks(rows)), dim3(256), 0, c->stream, t.O, t.yb, t.yf,
+                     delta, rows, t.dO, t.lrow);
+  HIP_TRY(c, hipGetLastError());
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, c->stream, t.lrow, rows, lsum);
+  HIP_TRY(c, hipGetLastError());
+  // backward: dZ of layer l lives in dz (width w); its input activation is
+  // H[l-1] (X for layer 0)
+  const float* dz = t.dO;
+  int w = NO;
+  float* spare[2] = {t.dA, t.dB};
+  for (int l = 3; l >= 0; --l) {
+    const float* a = l > 0 ? t.H[l - 1] : t.X;
+    const int ka = l > 0 ? HID : NF;
+    // dW_l = a^T dz  (ka x w), contraction over the batch
+    if ((rc = gemm(c, a, 1, ka, dz, w, 1, G + offW[l], w, 1, ka, w, R, t.work))) return rc;
+    hipLaunchKernelGGL(k_colsum, dim3((w + 127) / 128), dim3(128), 0, c->stream, dz, rows, w,
+                       G + offB[l]);
+    HIP_TRY(c, hipGetLastError());
+    if (l == 0) break;
+    // dH_{l-1} = dz W_l^T, then dZ_{l-1} = dH_{l-1} gelu'(Z_{l-1})
+    float* dh = spare[l & 1];
+    if ((rc = gemm(c, dz, w, 1, P + offW[l], 1, w, dh, HID, 1, R, HID, w, t.work))) return rc;
+    hipLaunchKernelGGL(k_gelu_bwd, dim3(ew_blocks(rows * HID)), dim3(256), 0, c->stream, dh,
+                       t.Z[l - 1], rows * HID);
+    HIP_TRY(c, hipGetLastError());
+    dz = dh;
+    w = HID;
+  }
+  return TWK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int twk_mlp_set(twk_ctx* c, const float* host, int64_t n) {
+  if (!c || !host || n != NPARAM || !params_valid(host)) return TWK_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  int rc = mlp_alloc(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipMemcpyAsync(c->mlp_p, host, NPARAM * sizeof(float), hipMemcpyHostToDevice,
+                            c->stream));
+  if ((rc = mlp_pack(c))) return rc;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TWK_OK;
+}
+
+int twk_mlp_get(twk_ctx* c, float* host, int64_t n) {
+  if (!c || !host || n != NPARAM) return TWK_EINVAL;
+  if (!c->mlp_ready) return TWK_ENOMLP;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(host, c->mlp_p, NPARAM * sizeof(float), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TWK_OK;
+}
+
+static const char kMagic[8] = {'T', 'W', 'K', 'M', 'L', 'P', '0', '1'};
+
+int twk_mlp_save(twk_ctx* c, const char* path) {
+  if (!c || !path) return TWK_EINVAL;
+  float* h = (float*)std::malloc(NPARAM * sizeof(float));
+  if (!h) return TWK_ENOMEM;
+  int rc = twk_mlp_get(c, h, NPARAM);
+  if (rc == TWK_OK) {
+    FILE* f = std::fopen(path, "wb");
+    const int32_t n = NPARAM;
+    if (!f) rc = TWK_EINVAL;
+    else {
+      if (std::fwrite(kMagic, 1, 8, f) != 8 || std::fwrite(&n, 4, 1, f) != 1 ||
+          std::fwrite(h, sizeof(float), NPARAM, f) != (size_t)NPARAM)
+        rc = TWK_EINVAL;
+      if (std::fclose(f) != 0) rc = TWK_EINVAL;
+    }
+  }
+  std::free(h);
+  return rc;
+}
+
+int twk_mlp_load(twk_ctx* c, const char* path) {
+  if (!c || !path) return TWK_EINVAL;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return TWK_EINVAL;
+  char magic[8];
+  int32_t n = 0;
+  float* h = (float*)std::malloc(NPARAM * sizeof(float));
+  int rc = TWK_OK;
+  if (!h) rc = TWK_ENOMEM;
+  else if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, kMagic, 8) != 0 ||
+           std::fread(&n, 4, 1, f) != 1 || n != NPARAM ||
+           std::fread(h, sizeof(float), NPARAM, f) != (size_t)NPARAM)
+    rc = TWK_EINVAL;
+  std::fclose(f);
+  if (rc == TWK_OK) rc = twk_mlp_set(c, h, NPARAM);
+  std::free(h);
+  return rc;
+}
+
+int twk_mlp_infer(twk_ctx* c, int64_t n, const float* feat, float* out) {
+  if (!c || n < 0) return TWK_EINVAL;
+  if (!c->mlp_ready) return TWK_ENOMLP;
+  if (n == 0) return TWK_OK;
+  if (!feat || !out) return TWK_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  const int64_t tiles = (n + 31) / 32;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(c->n_cu * 2, (tiles + 3) / 4));
+  hipLaunchKernelGGL(mlp::k_infer, dim3((unsigned)blocks), dim3(64 * mlp::INFER_WAVES), 0,
+                     c->stream, c->mlp_p, c->mlp_frag, n, (const long long*)nullptr, feat, out);
+  HIP_TRY(c, hipGetLastError());
+  return TWK_OK;
+}
+
+int twk_mlp_grad(twk_ctx* c, int64_t n, const float* feat, const float* yb, const float* yf,
+                 float huber_delta, float* grad, double* loss) {
+  if (!c || n < 1 || n > TWK_MLP_GRAD_MAX_ROWS || !feat || !yb || !yf || !grad || !loss ||
+      !(huber_delta > 0.0f))
+    return TWK_EINVAL;
+  if (!c->mlp_ready) return TWK_ENOMLP;
+  HIP_TRY(c, hipSetDevice(c->device));
+  int rc = ensure_train(c, n, 1, 1);
+  if (rc) return rc;
+  const TrainBufs t = train_bufs((float*)c->tr, n);
+  hipLaunchKernelGGL(mlp::k_gather, dim3(ew_blocks(n)), dim3(256), 0, c->stream, feat, yb, yf,
+                     (const int32_t*)nullptr, n, c->mlp_p, t.X, t.yb, t.yf);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipMemsetAsync(grad, 0, 16 * sizeof(float), c->stream));
+  if ((rc = forward_backward(c, t, n, huber_delta, grad, c->dsum))) return rc;
+  double s = 0.0;
+  HIP_TRY(c, hipMemcpyAsync(&s, c->dsum, 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *loss = s / (double)n;
+  return TWK_OK;
+}
+
+int twk_mlp_train(twk_ctx* c, int64_t n, const float* feat, const float* yb, const float* yf,
+                  const twk_train_cfg* cfg, float* loss_hist) {
+  if (!c || !cfg || !feat || !yb || !yf || cfg->epochs < 1 || cfg->batch < 32 ||
+      cfg->batch > TWK_MLP_GRAD_MAX_ROWS || n < cfg->batch || !(cfg->lr > 0.0f) ||
+      !(cfg->lr_end >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+      !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f) ||
+      !(cfg->huber_delta > 0.0f) || n > (int64_t)INT32_MAX)
+    return TWK_EINVAL;
+  if (!cfg->init && !c->mlp_ready) return TWK_ENOMLP;
+  HIP_TRY(c, hipSetDevice(c->device));
+  int rc = mlp_alloc(c);
+  if (rc) return rc;
+  const int64_t B = cfg->batch;
+  const int64_t steps = n / B;
+  if ((rc = ensure_train(c, B, n, steps))) return rc;
+  uint64_t rng = cfg->seed;
+  float* G = c->opt;
+  float* m1 = c->opt + NPARAM;
+  float* m2 = c->opt + 2 * NPARAM;
+  if (cfg->init) {
+    // standardisation from the data (double sums per block, added in order)
+    const int nb = 256;
+    double* part = nullptr;
+    if (hipMalloc((void**)&part, nb * 16 * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return TWK_ENOMEM;
+    }
+    hipLaunchKernelGGL(mlp::k_feat_stats, dim3(nb), dim3(256), 0, c->stream, feat, n, part);
+    std::vector<double> hp((size_t)nb * 16);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(part);
+    if (e != hipSuccess) return hip_fail(c, e);
+    std::vector<float> h(NPARAM, 0.0f);
+    for (int j = 0; j < mlp::NF; ++j) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int b = 0; b < nb; ++b) {
+        s1 += hp[b * 16 + j];
+        s2 += hp[b * 16 + 8 + j];
+      }
+      const double mean = s1 / n, var = std::max(s2 / n - mean * mean, 0.0);
+      h[mlp::OFF_MEAN + j] = (float)mean;
+      h[mlp::OFF_STD + j] = (float)std::max(std::sqrt(var), 1e-6);
+    }
+    // He-normal weights, zero biases
+    const int64_t offW[4] = {mlp::OFF_W0, mlp::OFF_W1, mlp::OFF_W2, mlp::OFF_W3};
+    const int fan[4] = {mlp::NF, mlp::HID, mlp::HID, mlp::HID};
+    const int width[4] = {mlp::HID, mlp::HID, mlp::HID, mlp::NO};
+    for (int l = 0; l < 4; ++l) {
+      const double sd = std::sqrt(2.0 / fan[l]);
+      for (int64_t i = 0; i < (int64_t)fan[l] * width[l]; ++i)
+        h[offW[l] + i] = (float)(sd * normal(rng));
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->mlp_p, h.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  HIP_TRY(c, hipMemsetAsync(c->opt, 0, (size_t)3 * NPARAM * sizeof(float), c->stream));
+  const TrainBufs t = train_bufs((float*)c->tr, B);
+  std::vector<int32_t> perm((size_t)n);
+  std::vector<double> ls((size_t)steps);
+  const int64_t total = (int64_t)cfg->epochs * steps;
+  int64_t it = 0;
+  for (int ep = 0; ep < cfg->epochs; ++ep) {
+    // Fisher-Yates shuffle of the rows
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+    for (int64_t i = n - 1; i > 0; --i) {
+      const int64_t j = (int64_t)(uniform01(rng) * (double)(i + 1));
+      std::swap(perm[i], perm[std::min(j, i)]);
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->perm, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice,
+                              c->stream));
+    for (int64_t st = 0; st < steps; ++st, ++it) {
+      hipLaunchKernelGGL(mlp::k_gather, dim3(ew_blocks(B)), dim3(256), 0, c->stream, feat, yb, yf,
+                         c->perm + st * B, B, c->mlp_p, t.X, t.yb, t.yf);
+      HIP_TRY(c, hipGetLastError());
+      if ((rc = forward_backward(c, t, B, cfg->huber_delta, G, c->dsum + st))) return rc;
+      const double frac = total > 1 ? (double)it / (double)(total - 1) : 0.0;
+      const float lr = (float)(cfg->lr + (cfg->lr_end - cfg->lr) * frac);
+      const double k = (double)(it + 1);
+      const float c1 = (float)(1.0 - std::pow((double)cfg->beta1, k));
+      const float c2 = (float)(1.0 - std::pow((double)cfg->beta2, k));
+      hipLaunchKernelGGL(mlp::k_adam, dim3(ew_blocks(NPARAM - 16)), dim3(256), 0, c->stream,
+                         c->mlp_p, G, m1, m2, (int64_t)16, (int64_t)NPARAM, lr, cfg->beta1,
+                         cfg->beta2, cfg->eps, c1, c2);
+      HIP_TRY(c, hipGetLastError());
+    }
+    HIP_TRY(c, hipMemcpyAsync(ls.data(), c->dsum, (size_t)steps * 8, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (loss_hist) {
+      double s = 0.0;
+      for (int64_t st = 0; st < steps; ++st) s += ls[st];
+      loss_hist[ep] = (float)(s / (double)(steps * B));
+    }
+  }
+  if ((rc = mlp_pack(c))) return rc;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TWK_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ tuning
+extern "C" {
+
+int twk_get_tuning(twk_ctx* c, twk_tuning* out) {
+  if (!c || !out) return TWK_EINVAL;
+  *out = c->tune;
+  return TWK_OK;
+}
+
+int twk_set_tuning(twk_ctx* c, const twk_tuning* t) {
+  if (!c || !t) return TWK_EINVAL;
+  const int ci = cap_index(t->lds_cap);
+  if (ci < 0 || t->waves_per_cu < 1 || t->waves_per_cu > c->max_wpc[ci] ||
+      !(t->budget_shift >= -2.0f && t->budget_shift <= 4.0f) || (t->graphs != 0 && t->graphs != 1))
+    return TWK_EINVAL;
+  // capture needs a created stream (the legacy null stream cannot be captured)
+  if (t->graphs && c->stream == nullptr) return TWK_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  c->tune = *t;
+  return TWK_OK;
+}
+
+int twk_autotune(twk_ctx* c, int64_t nsets, const double* s, const double* q, const double* u0,
+                 const double* alpha, const double* rho, const double* gamma, int64_t nepochs,
+                 const double* tau, int32_t n_annuli, double tol, uint32_t mode, int32_t trials,
+                 twk_tuning* best) {
+  if (!c || trials < 1 || trials > 100 || nsets < 1 || nepochs < 1) return TWK_EINVAL;
+  int rc = check_mode(c, mode);
+  if (rc) return rc;
+  HIP_TRY(c, hipSetDevice(c->device));
+  const int64_t n = nsets * nepochs;
+  char* out = nullptr;
+  if (hipMalloc((void**)&out, (size_t)n * 24) != hipSuccess) {
+    (void)hipGetLastError();
+    return TWK_ENOMEM;
+  }
+  double* mag = (double*)out;
+  double* err = (double*)(out + (size_t)n * 8);
+  int32_t* ns = (int32_t*)(out + (size_t)n * 16);
+  uint32_t* fl = (uint32_t*)(out + (size_t)n * 20);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const twk_tuning start = c->tune;
+  const bool timing = c->timing;
+  c->timing = false;
+  twk_tuning cur = start, top = start;
+  cur.graphs = 0;
+  double best_ms = 1e300;
+  auto measure = [&](const twk_tuning& t, double* ms) -> int {
+    int r;
+    if ((r = twk_set_tuning(c, &t))) return r;
+    // the first call sizes the buffers; then the fastest of `trials` calls
+    if ((r = twk_lightcurves(c, nsets, s, q, u0, alpha, rho, gamma, nepochs, tau, n_annuli, tol,
+                             mode, mag, err, ns, fl)))
+      return r;
+    double m = 1e300;
+    for (int k = 0; k < trials; ++k) {
+      HIP_TRY(c, hipEventRecord(e0, c->stream));
+      if ((r = twk_lightcurves(c, nsets, s, q, u0, alpha, rho, gamma, nepochs, tau, n_annuli, tol,
+                               mode, mag, err, ns, fl)))
+        return r;
+      HIP_TRY(c, hipEventRecord(e1, c->stream));
+      HIP_TRY(c, hipEventSynchronize(e1));
+      float f = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&f, e0, e1));
+      m = std::min(m, (double)f);
+    }
+    *ms = m;
+    return TWK_OK;
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = hip_fail(c, hipGetLastError());
+  } else {
+    // persistent grid and LDS capacity, then (learned path) the budget shift
+    for (int ci = 0; ci < 3 && rc == TWK_OK; ++ci) {
+      const int mx = c->max_wpc[ci];
+      int last = 0;
+      for (int f = 1; f <= 4 && rc == TWK_OK; ++f) {
+        const int w = std::max(1, (mx * f) / 4);
+        if (w == last) continue;
+        last = w;
+        cur.lds_cap = LDS_CAPS[ci];
+        cur.waves_per_cu = w;
+        double ms;
+        if ((rc = measure(cur, &ms)) == TWK_OK && ms < best_ms) {
+          best_ms = ms;
+          top = cur;
+        }
+      }
+    }
+    if (rc == TWK_OK && (mode & TWK_MODE_MLP)) {
+      const float shifts[6] = {0.0f, 0.5f, 1.0f, 1.5f, 2.0f, 3.0f};
+      cur = top;
+      for (int i = 0; i < 6 && rc == TWK_OK; ++i) {
+        cur.budget_shift = shifts[i];
+        double ms;
+        if ((rc = measure(cur, &ms)) == TWK_OK && ms < best_ms) {
+          best_ms = ms;
+          top = cur;
+        }
+      }
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  c->timing = timing;
+  top.graphs = start.graphs;
+  if (rc == TWK_OK) rc = twk_set_tuning(c, &top);
+  else (void)twk_set_tuning(c, &start);
+  if (rc == TWK_OK && best) *best = top;
+  return rc;
 }
 
 }  // extern "C"

@@ -83,6 +83,19 @@ __device__ __forceinline__ WaveMem wave_mem(char* base, int wave, int cap) {
 // Interval flag bits
 enum : uint32_t { IF_CROSS = 1u, IF_ANOMALY = 2u, IF_COUNT = 4u };
 
+// Sample meta word: n (bits 0-2) | parity mask (3-7) | sample flags (8-15) |
+// demoted (16) | demoted + image (17-19) | demoted - image (20-22) |
+// suspect (23).
+enum : uint32_t { M_DEMOTED = 1u << 16, M_SUSPECT = 1u << 23 };
+
+// Slope detector (Sec. 2.4.2).  A five-image sample whose ghost-pair
+// margin is above SUSPECT (yet below the residual detector's gap) may hold
+// a ghost pair taken for real; only such samples are examined, and a pair
+// whose difference is shorter than PAIR_FLOOR (1 + |z|) is below the
+// resolution of the test and counts as a genuine crossing.
+constexpr double SUSPECT = 8.0;
+constexpr double PAIR_FLOOR = 1e-7;
+
 // ---------------------------------------------------------------- sample
 // Solve the limb point at theta from the start r[] (warm: a neighbouring
 // sample's roots advanced along their derivative; or the centre roots) and
@@ -117,8 +130,9 @@ __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double
     m.w[k * m.cap + slot] = w;
   }
   m.th[slot] = theta;
-  m.meta[slot] = (uint32_t)im.n | (im.par << 3) | (im.flags << 8);
-  *fl = im.flags;
+  const bool suspect = im.n == 5 && im.par == 3u && im.margin > SUSPECT;
+  m.meta[slot] = (uint32_t)im.n | (im.par << 3) | (im.flags << 8) | (suspect ? M_SUSPECT : 0u);
+  *fl = im.flags | (suspect ? M_SUSPECT : 0u);
   return (uint32_t)s64 | ((uint32_t)s32 << 16);
 }
 
@@ -457,6 +471,214 @@ __device__ __forceinline__ Piece relink(const WaveMem& m, const Sorted& S, int p
   return pc;
 }
 
+// ---------------------------------------------------------------- slope detector
+// Demotion rewrites a five-image record (+ + - - -) as a three-image one
+// whose ghost slots hold the demoted pair: [other +, remaining - (in order),
+// demoted +, demoted -], remembering the pair so that the rewrite can be
+// undone (records are re-examined from scratch every round, as the samples
+// around a crossing change).
+__device__ inline void permute_record(const WaveMem& m, int slot, const int* from) {
+  c64 z[5], d[5];
+  double w[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    z[k] = m.root[k * m.cap + slot];
+    d[k] = m.dz[k * m.cap + slot];
+    w[k] = m.w[k * m.cap + slot];
+  }
+  for (int k = 0; k < 5; ++k) {
+    m.root[k * m.cap + slot] = z[from[k]];
+    m.dz[k * m.cap + slot] = d[from[k]];
+    m.w[k * m.cap + slot] = w[from[k]];
+  }
+}
+
+__device__ inline void demote(const WaveMem& m, int slot, int cp, int cn) {
+  int from[5] = {1 - cp, 0, 0, cp, cn};
+  int t = 1;
+  for (int k = 2; k < 5; ++k)
+    if (k != cn) from[t++] = k;
+  permute_record(m, slot, from);
+  const uint32_t mt = m.meta[slot];
+  m.meta[slot] = 3u | (1u << 3) | (mt & 0xFF00u) | M_DEMOTED | ((uint32_t)cp << 17) |
+                 ((uint32_t)cn << 20) | (mt & M_SUSPECT);
+}
+
+__device__ inline void undo_demotion(const WaveMem& m, int slot) {
+  const uint32_t mt = m.meta[slot];
+  if (!(mt & M_DEMOTED)) return;
+  const int cp = (mt >> 17) & 7u, cn = (mt >> 20) & 7u;
+  // current position of each original image
+  int from[5];
+  from[1 - cp] = 0;
+  from[cp] = 3;
+  from[cn] = 4;
+  int t = 1;
+  for (int k = 2; k < 5; ++k)
+    if (k != cn) from[k] = t++;
+  permute_record(m, slot, from);
+  m.meta[slot] = 5u | (3u << 3) | (mt & 0xFF00u) | (mt & M_SUSPECT);
+}
+
+__device__ __forceinline__ bool standard5(uint32_t mt) {
+  return (mt & 7u) == 5u && ((mt >> 3) & 31u) == 3u;
+}
+__device__ __forceinline__ bool standard3(uint32_t mt) {
+  return (mt & 7u) == 3u && ((mt >> 3) & 31u) == 1u;
+}
+
+// Count change between adjacent samples a -> b: +1 if a pair is created at
+// b (3 -> 5), -1 if destroyed after a (5 -> 3), 0 otherwise; (cp, cn) are the
+// record positions of the unmatched + and - images at the five-image
+// sample, by the same least-distance linking as the area pieces.
+__device__ inline int pair_link(const WaveMem& m, int sa, int sb, int& cp, int& cn) {
+  const uint32_t ma = m.meta[sa], mb = m.meta[sb];
+  c64 za[5], zb[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    za[k] = m.root[k * m.cap + sa];
+    zb[k] = m.root[k * m.cap + sb];
+  }
+  if (standard3(ma) && standard5(mb)) {
+    const uint32_t p = inject_static<1, 2>(za, zb);
+    const uint32_t n = inject_static<2, 3>(za + 1, zb + 2);
+    cp = 1 - (int)(p & 3u);
+    cn = 2 + (3 - (int)(n & 3u) - (int)((n >> 2) & 3u));
+    return 1;
+  }
+  if (standard5(ma) && standard3(mb)) {
+    const uint32_t p = inject_static<1, 2>(zb, za);
+    const uint32_t n = inject_static<2, 3>(zb + 1, za + 2);
+    cp = 1 - (int)(p & 3u);
+    cn = 2 + (3 - (int)(n & 3u) - (int)((n >> 2) & 3u));
+    return -1;
+  }
+  return 0;
+}
+
+// Follow the pair (cp, cn) of five-image sample s0 to five-image sample s1.
+__device__ inline bool follow_pair(const WaveMem& m, int s0, int s1, int& cp, int& cn) {
+  if (!standard5(m.meta[s0]) || !standard5(m.meta[s1])) return false;
+  c64 z0[5], z1[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    z0[k] = m.root[k * m.cap + s0];
+    z1[k] = m.root[k * m.cap + s1];
+  }
+  const uint32_t p = inject_static<2, 2>(z0, z1);
+  const uint32_t n = inject_static<3, 3>(z0 + 2, z1 + 2);
+  cp = (int)((p >> (2 * cp)) & 3u);
+  cn = 2 + (int)((n >> (2 * (cn - 2))) & 3u);
+  return true;
+}
+
+// Genuine crossing test: the new pair's difference D and the ghost pair's
+// difference G at the neighbouring three-image sample are close to
+// perpendicular, |D . G| <= cos(pi/4) |D| |G|.
+__device__ inline bool perp_enough(c64 D, c64 G, c64 zref) {
+  const double fl = PAIR_FLOOR * (1.0 + cabs64(zref));
+  const double a = cabs64(D), b = cabs64(G);
+  if (a < fl || b < fl) return true;
+  return fabs(cdot(D, G)) <= 0.70710678118654752 * a * b;
+}
+
+__device__ __forceinline__ c64 root_at(const WaveMem& m, int slot, int k) {
+  return m.root[k * m.cap + slot];
+}
+
+// From the three-image sample at sorted position kb, test the crossing into
+// the run of len five-image samples starting at sorted position `first`
+// (entered at its start or its end); if the pair is not perpendicular
+// enough, walk into the run demoting suspect samples until consecutive
+// pair differences turn perpendicular (or the whole run is walked: the
+// piece is deleted).  Returns the number of samples demoted.
+__device__ inline int walk_run(const WaveMem& m, const Sorted& S, int N, int kb, int first, int len,
+                               bool from_start) {
+  const int j0 = from_start ? 0 : len - 1, dj = from_start ? 1 : -1;
+  const int sb = S.sl[kb];
+  const int sc = S.sl[(first + j0) % N];
+  const uint32_t mc = m.meta[sc];
+  if (!(mc & M_SUSPECT) || (mc & M_DEMOTED)) return 0;
+  int cp = 0, cn = 2;
+  const int kind = from_start ? pair_link(m, sb, sc, cp, cn) : pair_link(m, sc, sb, cp, cn);
+  if (kind != (from_start ? 1 : -1)) return 0;
+  if (perp_enough(root_at(m, sc, cp) - root_at(m, sc, cn), root_at(m, sb, 3) - root_at(m, sb, 4),
+                  root_at(m, sc, cp)))
+    return 0;
+  int demoted = 0;
+  for (int j = j0; j >= 0 && j < len; j += dj) {
+    const int sj = S.sl[(first + j) % N];
+    if (m.meta[sj] & M_DEMOTED) break;
+    bool more = false;
+    int np = cp, nn = cn;
+    const int jn = j + dj;
+    if (jn >= 0 && jn < len) {
+      const int sn = S.sl[(first + jn) % N];
+      const uint32_t mn = m.meta[sn];
+      if ((mn & M_SUSPECT) && !(mn & M_DEMOTED) && follow_pair(m, sj, sn, np, nn))
+        more = !perp_enough(root_at(m, sj, cp) - root_at(m, sj, cn),
+                            root_at(m, sn, np) - root_at(m, sn, nn), root_at(m, sj, cp));
+    }
+    demote(m, sj, cp, cn);
+    ++demoted;
+    if (!more) break;
+    cp = np;
+    cn = nn;
+  }
+  return demoted;
+}
+
+__device__ __forceinline__ int orig_n(uint32_t mt) { return (mt & M_DEMOTED) ? 5 : (int)(mt & 7u); }
+
+// Runs of five-image samples between three-image ones, each examined from
+// both ends (serial; sources with suspect samples are rare).
+__device__ inline int detect_runs(const WaveMem& m, const Sorted& S, int N) {
+  int anchor = -1;
+  for (int i = 0; i < N; ++i)
+    if (orig_n(m.meta[S.sl[i]]) == 3) { anchor = i; break; }
+  if (anchor < 0) return 0;
+  int changed = 0;
+  int i = 0;
+  while (i < N) {
+    if (orig_n(m.meta[S.sl[(anchor + i) % N]]) != 5) { ++i; continue; }
+    const int start = i;
+    int len = 0;
+    while (i < N && orig_n(m.meta[S.sl[(anchor + i) % N]]) == 5) { ++len; ++i; }
+    const int first = (anchor + start) % N;
+    changed += walk_run(m, S, N, (anchor + start - 1 + N) % N, first, len, true);
+    changed += walk_run(m, S, N, (anchor + start + len) % N, first, len, false);
+  }
+  return changed;
+}
+
+// Full slope-detector pass of one source: undo last round's demotions,
+// re-examine every run, relink every interval and recompute the area total
+// (compensated).  Returns true if any sample is demoted.
+__device__ __attribute__((noinline)) bool slope_pass(const WaveMem& m, const Sorted& S, int N,
+                                                     int lane, double* Ahi, double* Alo,
+                                                     uint32_t* nint) {
+  for (int p = lane; p < N; p += WAVE) undo_demotion(m, p);
+  __syncthreads();
+  int changed = 0;
+  if (lane == 0) changed = detect_runs(m, S, N);
+  changed = __shfl(changed, 0);
+  __syncthreads();
+  double h = 0.0, l = 0.0;
+  for (int p = lane; p < N; p += WAVE) {
+    const Piece pc = relink(m, S, p, N);
+    double s1, e1;
+    two_sum(h, pc.dA, s1, e1);
+    h = s1;
+    l += e1;
+    ++*nint;
+  }
+  wave_sum_comp(h, l);
+  *Ahi = h;
+  *Alo = l;
+  __syncthreads();
+  return changed > 0;
+}
+
 // Relative tolerance actually targeted by the stop test: half the stated one.
 // The error estimate of Sec. 2.5 can fall short of the true error by up to
 // about a factor 2 across caustics (measured against the tight oracle on
@@ -466,7 +688,7 @@ constexpr double TOL_SAFETY = 0.5;
 
 template <int LCAP, bool MIXED>
 __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, FsLds<LCAP>& L,
-                           int lane) {
+                           int lane, int n0) {
   const double tol = tol_stated * TOL_SAFETY;
   Sorted S{L.th, L.E, L.sl, LCAP};
   bool spilled = false;
@@ -477,20 +699,29 @@ __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, F
   uint32_t sw32 = 0, sw64 = 0, nint = 0;  // this lane's work
   int N = 0;
   double Ahi = 0.0, Alo = 0.0, A = 0.0, E = 0.0;
-  // One round per iteration.  The first round places the initial samples
-  // theta_j = 2 pi j / 64, warm-started from the roots at the source centre;
-  // later rounds place 64 samples by inverse transform sampling.  Solving,
-  // merging and relinking have one call site each, which keeps the kernel
-  // small enough for the instruction cache.
+  bool suspects = false;  // some sample may hold a misjudged ghost pair
+  // One round per iteration.  The first n0 samples form the uniform grid
+  // theta = 2 pi i / n0, laid down 64 at a time: round r adds the phase
+  // offset r / (n0 / 64) of the base grid theta_j = 2 pi j / 64 (whose
+  // first round starts from the roots at the source centre) and is not
+  // followed by a stop test.  Later rounds place 64 samples by inverse
+  // transform sampling.  Solving, merging and relinking have one call site
+  // each, which keeps the kernel small.
   for (;;) {
     bool valid;
     int iv = -1, rank, mcount;
     double thn;
-    if (N == 0) {
+    if (N < n0) {
+      const int r = N / NNEW, m = n0 / NNEW;
       valid = true;
-      thn = TWO_PI * lane / (double)NNEW;
+      thn = TWO_PI * (lane + (double)r / m) / NNEW;
       rank = lane;
       mcount = NNEW;
+      if (N > 0) {
+        // the new sample follows the r samples of base interval j
+        iv = lane * r + r - 1;
+        L.ivl[rank] = iv;
+      }
     } else {
       // error total and total tolerance-subtracted weight
       A = Ahi + Alo;
@@ -584,7 +815,9 @@ __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, F
       sw64 += sw & 0xffffu;
       sw32 += sw >> 16;
       fl |= sf & (F_ANOMALY | F_NEARDEGEN);
+      if (sf & M_SUSPECT) suspects = true;
     }
+    suspects = __ballot(suspects) != 0;
     __syncthreads();
     // merge: old position p moves up by #(new samples in intervals < p);
     // strips from the top so that no unread entry is overwritten
@@ -661,6 +894,7 @@ __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, F
       Alo += dl + e1;
     }
     __syncthreads();
+    if (suspects && slope_pass(m, S, N, lane, &Ahi, &Alo, &nint)) fl |= F_SLOPE;
   }
   FsOut o;
   const double area = PI_64 * rho * rho;

@@ -29,7 +29,31 @@ FLAG_NEARDEGEN = 1 << 5
 
 EXPORTS = ("twk_create", "twk_destroy", "twk_sync", "twk_last_hip_error", "twk_strerror",
            "twk_point_mag", "twk_finite_mag", "twk_lightcurves", "twk_last_stats",
-           "twk_enable_timing", "twk_kernel_times", "twk_mag_map")
+           "twk_enable_timing", "twk_kernel_times", "twk_mag_map", "twk_features",
+           "twk_mlp_set", "twk_mlp_get", "twk_mlp_save", "twk_mlp_load", "twk_mlp_infer",
+           "twk_mlp_grad", "twk_mlp_train", "twk_get_tuning", "twk_set_tuning", "twk_autotune")
+
+MLP_NPARAM = 34450
+MLP_GRAD_MAX_ROWS = 65536
+
+
+class TrainCfg(C.Structure):
+    """twk_train_cfg."""
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("lr_end", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("huber_delta", C.c_float), ("init", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+
+class Tuning(C.Structure):
+    """twk_tuning."""
+    _fields_ = [("waves_per_cu", C.c_int32), ("lds_cap", C.c_int32), ("budget_shift", C.c_float),
+                ("graphs", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
 
 _lib = None
 _vp = C.c_void_p
@@ -67,10 +91,24 @@ def load():
     L.twk_last_stats.argtypes = [_vp, C.POINTER(C.c_int64)]
     L.twk_enable_timing.argtypes = [_vp, C.c_int]
     L.twk_kernel_times.argtypes = [_vp, C.POINTER(C.c_double)]
-    for f in ("twk_create", "twk_destroy", "twk_sync", "twk_last_hip_error", "twk_point_mag",
-              "twk_finite_mag", "twk_lightcurves", "twk_last_stats", "twk_enable_timing",
-              "twk_kernel_times", "twk_mag_map"):
-        getattr(L, f).restype = C.c_int
+    L.twk_features.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_int64, _vp,
+                               C.c_double, _vp, _vp, _vp]
+    L.twk_mlp_set.argtypes = [_vp, C.POINTER(C.c_float), C.c_int64]
+    L.twk_mlp_get.argtypes = [_vp, C.POINTER(C.c_float), C.c_int64]
+    L.twk_mlp_save.argtypes = [_vp, C.c_char_p]
+    L.twk_mlp_load.argtypes = [_vp, C.c_char_p]
+    L.twk_mlp_infer.argtypes = [_vp, C.c_int64, _vp, _vp]
+    L.twk_mlp_grad.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, C.c_float, _vp,
+                               C.POINTER(C.c_double)]
+    L.twk_mlp_train.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, C.POINTER(TrainCfg),
+                                C.POINTER(C.c_float)]
+    L.twk_get_tuning.argtypes = [_vp, C.POINTER(Tuning)]
+    L.twk_set_tuning.argtypes = [_vp, C.POINTER(Tuning)]
+    L.twk_autotune.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int64, _vp,
+                               C.c_int32, C.c_double, C.c_uint32, C.c_int32, C.POINTER(Tuning)]
+    for f in EXPORTS:
+        if f != "twk_strerror":
+            getattr(L, f).restype = C.c_int
     _lib = L
     return L
 
@@ -138,9 +176,9 @@ class Context:
         self._check(self.lib.twk_enable_timing(self.h, 1 if on else 0), "twk_enable_timing")
 
     def kernel_times(self):
-        out = (C.c_double * 4)()
+        out = (C.c_double * 5)()
         self._check(self.lib.twk_kernel_times(self.h, out), "twk_kernel_times")
-        return dict(ps_ms=out[0], fs_ms=out[1], rest_ms=out[2], total_ms=out[3])
+        return dict(ps_ms=out[0], mlp_ms=out[1], fs_ms=out[2], rest_ms=out[3], total_ms=out[4])
 
     def point_mag(self, s, q, zx, zy):
         zx = _dev(zx, self.device)
@@ -194,3 +232,92 @@ class Context:
                                          ny, tol, mode, _ptr(mag), _ptr(err), _ptr(ns), _ptr(fl)),
                     "twk_mag_map")
         return out
+
+    # ------------------------------------------------------------ learned part
+    def features(self, s, q, u0, alpha, rho, tau, tol):
+        """Per-epoch features [nsets*nepochs, 8] (float32), mu_ps, adequacy."""
+        s, q, u0, alpha, rho = (_dev(a, self.device) for a in (s, q, u0, alpha, rho))
+        tau = _dev(tau, self.device)
+        n = s.numel() * tau.numel()
+        feat = torch.empty((n, 8), dtype=torch.float32, device=self.device)
+        mu = torch.empty(n, dtype=torch.float64, device=self.device)
+        ok = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._check(self.lib.twk_features(self.h, s.numel(), _ptr(s), _ptr(q), _ptr(u0),
+                                          _ptr(alpha), _ptr(rho), tau.numel(), _ptr(tau), tol,
+                                          _ptr(feat), _ptr(mu), _ptr(ok)), "twk_features")
+        return feat, mu, ok
+
+    def mlp_set(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.twk_mlp_set(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size),
+                    "twk_mlp_set")
+
+    def mlp_get(self):
+        import numpy as np
+        p = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(self.lib.twk_mlp_get(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size),
+                    "twk_mlp_get")
+        return p
+
+    def mlp_save(self, path):
+        self._check(self.lib.twk_mlp_save(self.h, os.fsencode(path)), "twk_mlp_save")
+
+    def mlp_load(self, path):
+        self._check(self.lib.twk_mlp_load(self.h, os.fsencode(path)), "twk_mlp_load")
+
+    def mlp_infer(self, feat, out=None):
+        feat = _dev(feat, self.device, torch.float32)
+        n = feat.shape[0]
+        if out is None:
+            out = torch.empty((n, 2), dtype=torch.float32, device=self.device)
+        self._check(self.lib.twk_mlp_infer(self.h, n, _ptr(feat), _ptr(out)), "twk_mlp_infer")
+        return out
+
+    def mlp_grad(self, feat, y_budget, y_fs, huber_delta=1.0):
+        feat = _dev(feat, self.device, torch.float32)
+        yb = _dev(y_budget, self.device, torch.float32)
+        yf = _dev(y_fs, self.device, torch.float32)
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=self.device)
+        loss = C.c_double()
+        self._check(self.lib.twk_mlp_grad(self.h, feat.shape[0], _ptr(feat), _ptr(yb), _ptr(yf),
+                                          huber_delta, _ptr(g), C.byref(loss)), "twk_mlp_grad")
+        return loss.value, g
+
+    def mlp_train(self, feat, y_budget, y_fs, epochs=8, batch=4096, lr=2e-3, lr_end=1e-4,
+                  huber_delta=1.0, init=True, seed=1):
+        import numpy as np
+        feat = _dev(feat, self.device, torch.float32)
+        yb = _dev(y_budget, self.device, torch.float32)
+        yf = _dev(y_fs, self.device, torch.float32)
+        cfg = TrainCfg(epochs=epochs, batch=batch, lr=lr, lr_end=lr_end, beta1=0.9, beta2=0.999,
+                       eps=1e-8, huber_delta=huber_delta, init=1 if init else 0, seed=seed)
+        hist = np.zeros(epochs, dtype=np.float32)
+        self._check(self.lib.twk_mlp_train(self.h, feat.shape[0], _ptr(feat), _ptr(yb), _ptr(yf),
+                                           C.byref(cfg), hist.ctypes.data_as(C.POINTER(C.c_float))),
+                    "twk_mlp_train")
+        return hist
+
+    # ------------------------------------------------------------ tuning
+    def get_tuning(self):
+        t = Tuning()
+        self._check(self.lib.twk_get_tuning(self.h, C.byref(t)), "twk_get_tuning")
+        return t
+
+    def set_tuning(self, **kw):
+        t = self.get_tuning()
+        for k, v in kw.items():
+            setattr(t, k, v)
+        self._check(self.lib.twk_set_tuning(self.h, C.byref(t)), "twk_set_tuning")
+        return t
+
+    def autotune(self, s, q, u0, alpha, rho, tau, tol, mode=MODE_FP64, gamma=None, n_annuli=1,
+                 trials=2):
+        s, q, u0, alpha, rho = (_dev(a, self.device) for a in (s, q, u0, alpha, rho))
+        tau = _dev(tau, self.device)
+        g = None if gamma is None else _dev(gamma, self.device)
+        best = Tuning()
+        self._check(self.lib.twk_autotune(self.h, s.numel(), _ptr(s), _ptr(q), _ptr(u0), _ptr(alpha),
+                                          _ptr(rho), _ptr(g), tau.numel(), _ptr(tau), n_annuli, tol,
+                                          mode, trials, C.byref(best)), "twk_autotune")
+        return best

@@ -9,14 +9,18 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libengine_emu.so")
 
 
-def build() -> str:
+def build(kgap=None) -> str:
+    """kgap: override of the residual detector's gap factor (a blinded
+    detector exercises the slope detector)."""
     os.makedirs(OUT_DIR, exist_ok=True)
+    lib = LIB if kgap is None else os.path.join(OUT_DIR, f"libengine_emu_kgap{kgap:g}.so")
+    defs = [] if kgap is None else [f"-DTWK_KGAP={kgap!r}"]
     cmd = ["g++", "-std=c++20", "-O2", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
-           "-I", os.path.join(HERE, "include"), "-o", LIB + ".tmp",
-           os.path.join(HERE, "engine_emu.cpp")]
+           "-I", os.path.join(HERE, "include")] + defs + ["-o", lib + ".tmp",
+                                                        os.path.join(HERE, "engine_emu.cpp")]
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

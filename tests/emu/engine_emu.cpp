@@ -14,7 +14,7 @@ using namespace twk;
 namespace {
 constexpr int LCAP = 512;
 
-void run_wave(const Task& T, double tol, bool mixed, FsOut* out) {
+void run_wave(const Task& T, double tol, bool mixed, int n0, FsOut* out) {
   std::vector<char> scratch((size_t)METHOD_CAP * kSlotBytes);
   const WaveMem m = wave_mem(scratch.data(), 0, METHOD_CAP);
   auto* lds = new FsLds<LCAP>();
@@ -24,8 +24,8 @@ void run_wave(const Task& T, double tol, bool mixed, FsOut* out) {
   for (int l = 0; l < hip_emu::kLanes; ++l) {
     th.emplace_back([&, l] {
       hip_emu::t_lane = l;
-      FsOut o = mixed ? fs_source<LCAP, true>(T, tol, m, *lds, l)
-                      : fs_source<LCAP, false>(T, tol, m, *lds, l);
+      FsOut o = mixed ? fs_source<LCAP, true>(T, tol, m, *lds, l, n0)
+                      : fs_source<LCAP, false>(T, tol, m, *lds, l, n0);
       if (l == 0) *out = o;
     });
   }
@@ -37,9 +37,10 @@ void run_wave(const Task& T, double tol, bool mixed, FsOut* out) {
 
 extern "C" {
 
-// Centre roots by the device cold-start solve, then the contour engine.
+// Centre roots by the device cold-start solve, then the contour engine
+// starting from a uniform grid of n0 samples (a multiple of 64, <= 512).
 int emu_finite_mag(double s, double q, double zx, double zy, double rho, double tol, int mixed,
-                   double* mag, double* err, int* nsamp, unsigned* flags, double* sweeps) {
+                   int n0, double* mag, double* err, int* nsamp, unsigned* flags, double* sweeps) {
   const Lens L = make_lens(s, q);
   const c64 yc = cz(zx - L.z2, zy);
   Images im;
@@ -54,7 +55,8 @@ int emu_finite_mag(double s, double q, double zx, double zy, double rho, double 
   T.zy = zy;
   for (int k = 0; k < 5; ++k) T.roots[k] = im.z[k];
   FsOut o;
-  run_wave(T, tol, mixed != 0, &o);
+  if (n0 < 64 || n0 > LCAP || n0 % 64) return -1;
+  run_wave(T, tol, mixed != 0, n0, &o);
   *mag = o.mag;
   *err = o.err;
   *nsamp = o.n;

@@ -10,20 +10,20 @@ import pytest
 GATE = 1e-4
 
 
-@pytest.fixture(scope="module")
-def emu():
+def _load(kgap=None):
     from emu import build_emu
-    lib = C.CDLL(build_emu.build())
+    lib = C.CDLL(build_emu.build(kgap))
     dp = C.POINTER(C.c_double)
-    lib.emu_finite_mag.argtypes = [C.c_double] * 6 + [C.c_int, dp, dp, C.POINTER(C.c_int),
+    lib.emu_finite_mag.argtypes = [C.c_double] * 6 + [C.c_int, C.c_int, dp, dp, C.POINTER(C.c_int),
                                                       C.POINTER(C.c_uint), dp]
     lib.emu_point.argtypes = [C.c_double] * 4 + [dp, C.POINTER(C.c_int), C.POINTER(C.c_uint), dp]
 
-    def finite(s, q, x, y, rho, tol, mixed=0):
+    def finite(s, q, x, y, rho, tol, mixed=0, n0=64):
         m, e, n, f = C.c_double(), C.c_double(), C.c_int(), C.c_uint()
         sw = (C.c_double * 3)()
-        lib.emu_finite_mag(s, q, x, y, rho, tol, mixed, C.byref(m), C.byref(e), C.byref(n),
-                           C.byref(f), sw)
+        rc = lib.emu_finite_mag(s, q, x, y, rho, tol, mixed, n0, C.byref(m), C.byref(e), C.byref(n),
+                                C.byref(f), sw)
+        assert rc == 0
         return m.value, e.value, n.value, f.value
 
     def point(s, q, x, y):
@@ -33,6 +33,19 @@ def emu():
         return m.value, n.value, f.value
 
     return dict(finite=finite, point=point)
+
+
+@pytest.fixture(scope="module")
+def emu():
+    return _load()
+
+
+@pytest.fixture(scope="module")
+def emu_blind():
+    """The engine with the residual detector blinded (gap factor 1e9):
+    near-caustic ghost pairs are taken for real, and only the slope
+    detector can repair the contour."""
+    return _load(1e9)
 
 
 CASES = [
@@ -104,3 +117,67 @@ def test_point_classification_against_oracle(emu, oracle):
             continue
         assert n == rn[0]
         assert abs(m / rm[0] - 1) < 1e-10
+
+
+@pytest.mark.parametrize("n0", [128, 320, 512])
+def test_engine_initial_budget(emu, oracle, n0):
+    """A learned budget only changes the starting grid (theta = 2 pi i / n0):
+    the result still meets the gate, uses at least n0 samples, and follows
+    the serial sampler started from the same grid."""
+    for (s, q, z, rho) in CASES[:4]:
+        m, e, n, f = emu["finite"](s, q, z.real, z.imag, rho, 1e-4, 1, n0)
+        r = oracle.finite_mag(s, q, [z.real], [z.imag], rho, oracle.JUDGE_TOL, oracle.judge_cfg())[0][0]
+        assert abs(m / r - 1) <= GATE, (s, q, z, rho, n0, m, r)
+        assert n >= n0
+    s, q, z, rho = CASES[3]
+    m, e, n, f = emu["finite"](s, q, z.real, z.imag, rho, 1e-4, 0, n0)
+    rm, re_, rn, rf = oracle.finite_mag(s, q, [z.real], [z.imag], rho, 5e-5, oracle.cfg(5e-5, n0=n0))
+    assert abs(m / rm[0] - 1) < 1e-9
+    assert n == rn[0]
+
+
+def test_slope_detector_repairs_blinded_engine(emu_blind, oracle):
+    """Sec. 2.4.2 and Fig. 3, on the device engine: with the residual
+    detector blinded, the slope detector restores the magnification of the
+    Fig. 1 example (the oracle shows the blinded result without the slope
+    detector is off by more than 1e-2)."""
+    import json
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
+    g = gold["fig1_coefficients"]
+    s, q, rho = g["s"], g["q"], g["rho"]
+    zc = complex(*g["zeta"])
+    good = oracle.finite_mag(s, q, [zc.real], [zc.imag], rho, oracle.JUDGE_TOL, oracle.judge_cfg())[0][0]
+    for mixed in (0, 1):
+        m, e, n, f = emu_blind["finite"](s, q, zc.real, zc.imag, rho, 1e-4, mixed)
+        assert f & 8, "slope detector did not act"
+        assert abs(m / good - 1) <= GATE, (mixed, m, good)
+
+
+def test_slope_detector_follows_oracle(emu_blind, oracle):
+    """Blinded engine against the blinded oracle running the same sampler
+    (serial, half the stated tolerance): the same demotions, the same
+    magnification, and both still meet the gate against the unblinded
+    judge on these lenses (q = 1e-5: the misjudged pairs are all of the kind
+    the slope test can see)."""
+    import pins
+    acted = 0
+    for (s, q, rho, seed) in [(1.0, 1e-5, 1e-4, 17), (1.2, 1e-5, 1e-3, 17)]:
+        rng = np.random.default_rng(seed)
+        ca = pins.caustic(s, q, 2048)
+        z = ca[rng.integers(0, ca.size, 24)] + rho * rng.uniform(0, 2, 24) * np.exp(
+            2j * np.pi * rng.uniform(0, 1, 24))
+        cfg = oracle.cfg(5e-5, kgap=1e9)
+        rels = []
+        for zz in z:
+            m, e, n, f = emu_blind["finite"](s, q, zz.real, zz.imag, rho, 1e-4, 0)
+            rm, re_, rn, rf = oracle.finite_mag(s, q, [zz.real], [zz.imag], rho, 5e-5, cfg)
+            good = oracle.finite_mag(s, q, [zz.real], [zz.imag], rho, oracle.JUDGE_TOL,
+                                     oracle.judge_cfg())[0][0]
+            acted += bool(f & 8)
+            if n == rn[0]:  # same sample set: same demotions
+                assert bool(f & 8) == bool(rf[0] & 8), zz
+            assert abs(m / good - 1) <= GATE, (s, q, zz, m, good)
+            rels.append(abs(m / rm[0] - 1))
+        print(s, q, "slope acted so far", acted, "median rel vs oracle", np.median(rels))
+        assert np.median(rels) < 1e-8
+    assert acted >= 5

@@ -1,0 +1,278 @@
+"""Learned budget on the GPU (through the C ABI) against the float64 oracle.
+
+Tolerances of the bf16 products, derived from the arithmetic: a product of
+two bf16 numbers is exact in float32, so each pre-activation differs from
+the oracle's float64 sum of the same products only by float32 accumulation
+(about K 2^-24 relative, K <= 128).  A staged activation rounds to the same
+bf16 value on both sides unless it lies within that distance of a rounding
+midpoint; the rare flips move one activation by one bf16 unit (2^-8
+relative), a change of a few 1e-3 of one term of the next layer.  Hence the
+outputs agree to well under 1e-2 (1 + |out|).  The backward pass also
+rounds dZ and the stored activations at each product (2^-9 relative per
+operand), so gradients are compared per tensor in norm (2e-2) and by
+direction (cosine >= 0.999).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as M
+
+pytestmark = pytest.mark.gpu
+
+GATE = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_03322_amd import twk
+    c = twk.Context(0)
+    yield c
+    c.close()
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+MEAN = np.array([1.2, -3.0, 0.0, 0.0, -3.0, 0.3, 0.5, -2.0])
+STD = np.array([0.6, 1.2, 0.8, 0.8, 0.6, 0.4, 1.5, 1.5])
+
+
+def _params(seed):
+    p = M.init(seed, MEAN, STD)
+    p["b3"][0] = 7.0  # log2 counts around 2^7
+    return p
+
+
+def _features(n, seed):
+    rng = np.random.default_rng(seed)
+    return (MEAN + STD * rng.normal(size=(n, 8))).astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 31, 1000, 70001])
+def test_mlp_infer_parity(ctx, n):
+    import torch
+    p = _params(3)
+    ctx.mlp_set(M.flatten(p))
+    X = _features(n, 4)
+    out = ctx.mlp_infer(torch.as_tensor(X)).cpu().numpy().astype(np.float64)
+    ref, _ = M.forward(p, X.astype(np.float64), emulate_bf16=True)
+    err = np.abs(out - ref) / (1.0 + np.abs(ref))
+    _log(f"infer n={n}: max scaled diff {err.max():.3g} (bf16-emulated oracle)")
+    assert err.max() < 1e-2
+    # the rounding matters: the unrounded float64 network is further away
+    if n >= 1000:
+        full, _ = M.forward(p, X.astype(np.float64))
+        assert np.median(np.abs(out - full)) > np.median(np.abs(out - ref))
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.mark.parametrize("n", [777, 4096])
+def test_mlp_grad_parity(ctx, n):
+    import torch
+    p = _params(5)
+    ctx.mlp_set(M.flatten(p))
+    rng = np.random.default_rng(6)
+    X = _features(n, 7)
+    yb = rng.normal(7.0, 1.5, n).astype(np.float32)
+    yf = (rng.random(n) < 0.3).astype(np.float32)
+    loss, g = ctx.mlp_grad(torch.as_tensor(X), torch.as_tensor(yb), torch.as_tensor(yf), 1.0)
+    g = M.unflatten(g.cpu().numpy().astype(np.float64))
+    rl, rg = M.loss_and_grad(p, X.astype(np.float64), yb.astype(np.float64),
+                             yf.astype(np.float64), 1.0, emulate_bf16=True)
+    _log(f"grad n={n}: loss {loss:.6g} vs {rl:.6g}")
+    assert abs(loss / rl - 1) < 2e-3
+    for k in rg:
+        r = _rel(g[k], rg[k])
+        cos = float(np.dot(g[k].ravel(), rg[k].ravel()) /
+                    (np.linalg.norm(g[k]) * np.linalg.norm(rg[k]) + 1e-300))
+        _log(f"  {k}: rel {r:.3g} cos {cos:.6f}")
+        assert r < 2e-2, k
+        assert cos > 0.999, k
+    assert np.all(g["mean"] == 0) and np.all(g["std"] == 0)
+
+
+def test_mlp_full_batch_training_tracks_oracle(ctx):
+    """Full-batch Adam (one step per epoch, so the shuffle is irrelevant):
+    the device and the oracle start from the same weights and follow the
+    same loss trajectory."""
+    import torch
+    n = 2048
+    rng = np.random.default_rng(9)
+    X = _features(n, 10)
+    z = (X - MEAN) / STD
+    yb = (7.0 + 1.5 * np.tanh(z[:, 0]) - 0.8 * z[:, 6]).astype(np.float32)
+    yf = (z[:, 7] + 0.3 * rng.normal(size=n) > 0.5).astype(np.float32)
+    p = _params(11)
+    ctx.mlp_set(M.flatten(p))
+    steps, lr = 25, 3e-3
+    hist = ctx.mlp_train(torch.as_tensor(X), torch.as_tensor(yb), torch.as_tensor(yf),
+                         epochs=steps, batch=n, lr=lr, lr_end=lr, init=False, seed=1)
+    st = {}
+    ref = []
+    q = {k: v.copy() for k, v in p.items()}
+    for _ in range(steps):
+        l, g = M.loss_and_grad(q, X.astype(np.float64), yb.astype(np.float64),
+                               yf.astype(np.float64), 1.0, emulate_bf16=True)
+        ref.append(l)
+        M.adam_step(q, g, st, lr)
+    ref = np.array(ref)
+    _log("loss device " + " ".join(f"{v:.4f}" for v in hist[::6]))
+    _log("loss oracle " + " ".join(f"{v:.4f}" for v in ref[::6]))
+    assert hist[-1] < 0.6 * hist[0]
+    np.testing.assert_allclose(hist, ref, rtol=2e-2)
+    w = M.unflatten(ctx.mlp_get().astype(np.float64))
+    for k in ("W1", "W3", "b0"):
+        assert _rel(w[k] - p[k], q[k] - p[k]) < 0.1, k
+
+
+def test_mlp_weights_io(ctx, tmp_path):
+    from paper_2501_03322_amd import twk
+    p = M.flatten(_params(12)).astype(np.float32)
+    ctx.mlp_set(p)
+    f = str(tmp_path / "w.bin")
+    ctx.mlp_save(f)
+    ctx.mlp_set(M.flatten(_params(13)))
+    ctx.mlp_load(f)
+    np.testing.assert_array_equal(ctx.mlp_get(), p)
+    bad = str(tmp_path / "bad.bin")
+    with open(bad, "wb") as fh:
+        fh.write(b"TWKMLP01" + (5).to_bytes(4, "little"))
+    with pytest.raises(twk.TwkError):
+        ctx.mlp_load(bad)
+    np.testing.assert_array_equal(ctx.mlp_get(), p)   # unchanged after a failed load
+    q = p.copy()
+    q[8] = 0.0                                         # std must be positive
+    with pytest.raises(twk.TwkError):
+        ctx.mlp_set(q)
+    fresh = twk.Context(0)
+    with pytest.raises(twk.TwkError) as e:
+        fresh.finite_mag(1.0, 1e-3, [0.0], [0.0], 1e-3, 1e-4, twk.MODE_MLP)
+    assert e.value.status == twk.ENOMLP
+    fresh.close()
+
+
+def test_features_parity(ctx, oracle):
+    """Device features of a light-curve batch against the oracle's, epoch by
+    epoch, on the small fit-style configuration."""
+    from paper_2501_03322_amd import inputs
+    c = inputs.batched_curves()
+    ks = np.arange(0, 1024, 37)
+    tau = c.tau[::10]
+    feat, mu, ok = ctx.features(c.s[ks], c.q[ks], c.u0[ks], c.alpha[ks], c.rho[ks], tau, 1e-4)
+    feat, mu, ok = feat.cpu().numpy(), mu.cpu().numpy(), ok.cpu().numpy()
+    rng = np.random.default_rng(2)
+    pick = rng.choice(feat.shape[0], 400, replace=False)
+    mism = 0
+    for i in pick:
+        a, j = divmod(int(i), tau.size)
+        k = ks[a]
+        zx, zy = oracle.trajectory(c.u0[k], c.alpha[k], tau[j:j + 1])
+        rf, rmu, rok = oracle.features(c.s[k], c.q[k], complex(zx[0], zy[0]), c.rho[k], 1e-4)
+        assert mu[i] == pytest.approx(rmu, rel=1e-10)
+        np.testing.assert_allclose(feat[i, :6], rf[:6], rtol=1e-6, atol=1e-6)
+        assert np.sign(feat[i, 6]) == np.sign(rf[6])
+        assert abs(feat[i, 6] - rf[6]) < 1e-4 * (1 + abs(rf[6]))
+        if rf[7] > -9:
+            assert abs(feat[i, 7] - rf[7]) < 1e-3, (i, feat[i], rf)
+        else:
+            assert feat[i, 7] < -8
+        mism += int(bool(ok[i]) != rok)
+    assert mism == 0
+
+
+def test_learned_path_parity(ctx, oracle):
+    """The learned budget only moves where contour integration starts:
+    magnifications still meet the gate against the oracle judge, on the
+    single light curve and near caustics, whatever the weights say."""
+    from paper_2501_03322_amd import inputs, twk
+    for seed, bias in ((21, 6.5), (22, 9.5)):
+        p = _params(seed)
+        p["b3"][0] = bias
+        ctx.mlp_set(M.flatten(p))
+        c = inputs.single_curve()
+        zx, zy = oracle.trajectory(c.u0[0], c.alpha[0], c.tau)
+        rm, _, _, _ = oracle.finite_mag(c.s[0], c.q[0], zx, zy, c.rho[0], oracle.JUDGE_TOL,
+                                        oracle.judge_cfg())
+        for mode in (twk.MODE_MLP, twk.MODE_MLP | twk.MODE_MIXED):
+            _log(f"learned light curve bias={bias} mode={mode}")
+            mag, err, ns, fl = ctx.lightcurves(c.s, c.q, c.u0, c.alpha, c.rho, c.tau, 1e-4, mode)
+            mag, ns, fl = mag.cpu().numpy(), ns.cpu().numpy(), fl.cpu().numpy()
+            rel = np.abs(mag / rm - 1)
+            assert rel.max() <= GATE, (bias, mode, rel.max(), int(rel.argmax()))
+            # every contour started from at least its budgeted grid:
+            # n0 = 64 floor(2^(l2 - 1) / 64) within [64, 512], l2 the
+            # predicted log2 count of the epoch's features
+            fs = (fl & 1) == 0
+            feat, _, _ = ctx.features(c.s, c.q, c.u0, c.alpha, c.rho, c.tau, 1e-4)
+            l2 = ctx.mlp_infer(feat).cpu().numpy()[:, 0].astype(np.float64)
+            want = np.exp2(np.clip(l2 - 1.0, 6.0, 9.0)) / 64.0
+            n0 = np.clip(np.floor(want) * 64, 64, 512)
+            clear = np.abs(want - np.round(want)) > 1e-3
+            sel = fs & clear
+            assert np.all(ns[sel] >= n0[sel]), (bias, int(np.sum(ns[sel] < n0[sel])))
+            _log(f"  fs epochs {int(fs.sum())}, mean n0 {n0[fs].mean():.1f}, mean samples {ns[fs].mean():.1f}")
+        import pins
+        s, q, rho = 1.0, 1e-3, 1e-3
+        ca = pins.caustic(s, q, 2048)
+        rng = np.random.default_rng(seed)
+        z = ca[rng.integers(0, ca.size, 64)] + rho * rng.uniform(0, 2, 64) * np.exp(
+            2j * np.pi * rng.uniform(0, 1, 64))
+        mag, err, ns, fl = ctx.finite_mag(s, q, z.real.copy(), z.imag.copy(), rho, 1e-4,
+                                          twk.MODE_MLP | twk.MODE_ALL_FS)
+        rm, _, _, _ = oracle.finite_mag(s, q, z.real.copy(), z.imag.copy(), rho, oracle.JUDGE_TOL,
+                                        oracle.judge_cfg())
+        rel = np.abs(mag.cpu().numpy() / rm - 1)
+        assert rel.max() <= GATE
+
+
+def test_learned_batch_every_task_once(ctx, oracle):
+    """Bucketed longest-first ordering processes every queued task exactly
+    once: outputs pre-filled with NaN are all overwritten, and the sample
+    total equals the work counter."""
+    import torch
+    from paper_2501_03322_amd import inputs, twk
+    ctx.mlp_set(M.flatten(_params(31)))
+    c = inputs.batched_curves()
+    k = slice(0, 256)
+    n = 256 * c.nepochs
+    out = ctx.alloc_out(n)
+    out[0].fill_(float("nan"))
+    out[2].fill_(-1)
+    ctx.lightcurves(c.s[k], c.q[k], c.u0[k], c.alpha[k], c.rho[k], c.tau, 1e-4,
+                    twk.MODE_MLP | twk.MODE_MIXED, out=out)
+    ctx.sync()
+    mag, ns, fl = out[0].cpu().numpy(), out[2].cpu().numpy(), out[3].cpu().numpy()
+    assert np.all(np.isfinite(mag)) and np.all(ns >= 0)
+    st = ctx.stats()
+    assert st["fs_tasks"] == int(np.sum((fl & 1) == 0))
+    assert st["samples"] == int(ns.sum())
+
+
+def test_trained_weights_file(ctx, oracle):
+    """The committed weights (trained on the seed-2 training set) load and
+    give sample-count predictions that correlate with the plain path's."""
+    import torch
+    from paper_2501_03322_amd import inputs, twk
+    path = os.path.join(os.path.dirname(twk.__file__), "weights", "mlp_budget.bin")
+    if not os.path.exists(path):
+        pytest.skip("no trained weights committed")
+    ctx.mlp_load(path)
+    c = inputs.evaluation_curves()
+    k = slice(0, 64)
+    feat, mu, ok = ctx.features(c.s[k], c.q[k], c.u0[k], c.alpha[k], c.rho[k], c.tau, 1e-4)
+    out = ctx.mlp_infer(feat).cpu().numpy()
+    mag, err, ns, fl = ctx.lightcurves(c.s[k], c.q[k], c.u0[k], c.alpha[k], c.rho[k], c.tau, 1e-4,
+                                       twk.MODE_FP64 | twk.MODE_ALL_FS)
+    l2 = np.log2(ns.cpu().numpy().astype(np.float64))
+    r = np.corrcoef(out[:, 0], l2)[0, 1]
+    _log(f"trained budget: corr(pred, log2 N) = {r:.3f}")
+    assert r > 0.5

@@ -1,0 +1,137 @@
+"""Launch runtime on the GPU: graph capture and replay, launch tuning and
+the autotuner.  None of them may change a result: replays, persistent grid
+sizes and LDS capacities give bit-identical magnifications."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_03322_amd import inputs
+    c = inputs.batched_curves()
+    k = slice(0, 96)
+    dev = torch.device("cuda", 0)
+    args = [torch.as_tensor(a[k] if a.size == c.nsets else a, device=dev)
+            for a in (c.s, c.q, c.u0, c.alpha, c.rho, c.tau)]
+    return c, args
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _run(ctx, args, mode, tol=1e-4, out=None):
+    if out is None:
+        out = ctx.alloc_out(args[0].numel() * args[5].numel())
+    ctx.lightcurves(*args, tol, mode=mode, out=out)
+    ctx.sync()
+    return out
+
+
+def test_graph_replay_bitwise(lc):
+    """Graph replays of the full launch sequence (counter reset, point pass,
+    contour kernel) reproduce the eager result bit for bit, replay after
+    replay, with eager work and synchronisations in between."""
+    import torch
+    from paper_2501_03322_amd import twk
+    c, args = lc
+    st = torch.cuda.Stream()
+    ctx = twk.Context(0, stream=st)
+    with torch.cuda.stream(st):
+        for mode in (twk.MODE_MIXED, twk.MODE_FP64):
+            ctx.set_tuning(graphs=0)
+            ref = [t.clone() for t in _run(ctx, args, mode)]
+            ctx.set_tuning(graphs=1)
+            out = ctx.alloc_out(ref[0].numel())
+            for rep in range(4):
+                for t in out:
+                    t.zero_()
+                _run(ctx, args, mode, out=out)
+                for a, b in zip(out, ref):
+                    assert torch.equal(a, b), (mode, rep)
+                # eager work between the replays
+                torch.cuda.synchronize()
+                _ = (ref[0] * 2.0).sum().item()
+            # a new tolerance is a new call: captured afresh, still equal to eager
+            ctx.set_tuning(graphs=0)
+            ref2 = _run(ctx, args, mode, tol=3e-4)
+            ctx.set_tuning(graphs=1)
+            got = _run(ctx, args, mode, tol=3e-4)
+            assert torch.equal(got[0], ref2[0])
+            stats = ctx.stats()
+            assert stats["fs_tasks"] == int(((ref2[3] & 1) == 0).sum().item())
+    ctx.close()
+
+
+@pytest.mark.parametrize("cap", [256, 512, 1024])
+def test_tuning_does_not_change_results(lc, cap):
+    import torch
+    from paper_2501_03322_amd import twk
+    c, args = lc
+    ctx = twk.Context(0)
+    ref = [t.clone() for t in _run(ctx, args, twk.MODE_MIXED)]
+    t0 = ctx.get_tuning()
+    for frac in (0.25, 1.0):
+        ctx.set_tuning(lds_cap=cap, waves_per_cu=1)
+        mx = 1
+        # largest accepted grid for this capacity
+        for w in range(2, 33):
+            try:
+                ctx.set_tuning(lds_cap=cap, waves_per_cu=w)
+                mx = w
+            except twk.TwkError:
+                break
+        w = max(1, int(mx * frac))
+        ctx.set_tuning(lds_cap=cap, waves_per_cu=w)
+        _log(f"cap {cap}: waves per CU {w} of {mx}")
+        got = _run(ctx, args, twk.MODE_MIXED)
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), (cap, w)
+    ctx.close()
+
+
+def test_tuning_rejects_bad_values():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_03322_amd import twk
+    ctx = twk.Context(0, stream=torch.cuda.Stream())
+    for kw in ({"lds_cap": 300}, {"waves_per_cu": 0}, {"waves_per_cu": 1000},
+               {"budget_shift": 9.0}, {"graphs": 2}):
+        with pytest.raises(twk.TwkError):
+            ctx.set_tuning(**kw)
+    ctx.close()
+
+
+def test_autotune(lc, oracle):
+    """The autotuner returns a valid tuning, leaves it in the context, and
+    the tuned call still meets the gate (learned path, random weights)."""
+    import torch
+    from oracle import mlp_ref as M
+    from paper_2501_03322_amd import twk
+    c, args = lc
+    ctx = twk.Context(0)
+    p = M.init(3, [1.2, -3.0, 0.0, 0.0, -3.0, 0.3, 0.5, -2.0], [0.6, 1.2, 0.8, 0.8, 0.6, 0.4, 1.5, 1.5])
+    p["b3"][0] = 7.0
+    ctx.mlp_set(M.flatten(p))
+    small = [a[:32] if a.numel() == 96 else a for a in args]
+    best = ctx.autotune(*small, 1e-4, mode=twk.MODE_MLP | twk.MODE_MIXED, trials=1)
+    _log(f"autotuned: {best.as_dict()}")
+    assert best.lds_cap in (256, 512, 1024) and best.waves_per_cu >= 1
+    assert ctx.get_tuning().as_dict() == best.as_dict()
+    mag, err, ns, fl = _run(ctx, args, twk.MODE_MLP | twk.MODE_MIXED)
+    mag, fl = mag.cpu().numpy(), fl.cpu().numpy()
+    rng = np.random.default_rng(4)
+    fs = np.nonzero((fl & 1) == 0)[0]
+    for i in rng.choice(fs, min(40, fs.size), replace=False):
+        k, j = divmod(int(i), c.nepochs)
+        zx, zy = oracle.trajectory(c.u0[k], c.alpha[k], c.tau[j:j + 1])
+        rm = oracle.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], oracle.JUDGE_TOL,
+                               oracle.judge_cfg())[0][0]
+        assert abs(mag[i] / rm - 1) <= 1e-4
+    ctx.close()
