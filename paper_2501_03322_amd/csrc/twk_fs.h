@@ -22,6 +22,18 @@
 
 #include "twk_device.h"
 
+// Address spaces of the engine's pointers: sample records and spill copies
+// in global memory, sorted arrays in LDS.  Typed pointers let the compiler
+// emit global and LDS instructions instead of generic (flat) ones, which
+// wait on both memory counters and route LDS traffic through the vector
+// memory pipeline.  (A CPU emulation build defines both as nothing.)
+#ifndef TWK_GLOBAL_AS
+#define TWK_GLOBAL_AS __attribute__((address_space(1)))
+#endif
+#ifndef TWK_LDS_AS
+#define TWK_LDS_AS __attribute__((address_space(3)))
+#endif
+
 namespace twk {
 
 constexpr int WAVE = 64;
@@ -41,16 +53,22 @@ struct Task {
 
 // Per-wave slice of the sample scratch: SoA over slots [0, cap), plus room
 // for the sorted arrays when a source outgrows its LDS copy.
+typedef TWK_GLOBAL_AS double gdouble;
+typedef TWK_GLOBAL_AS uint32_t guint32;
+typedef TWK_GLOBAL_AS uint16_t guint16;
+typedef TWK_LDS_AS double ldouble;
+typedef TWK_LDS_AS uint16_t luint16;
+
 struct WaveMem {
-  c64* root;       // [5][cap] positive, negative real images, ghost pair
-  c64* dz;         // [5][cap] z' of the real images
-  double* w;       // [5][cap] z' ^ z''
-  double* th;      // [cap] limb angle of the slot
-  double* dA;      // [cap] area of the interval starting at this slot
-  double* sth;     // [cap] sorted angles (spill copy)
-  double* sE;      // [cap] sorted interval errors (spill copy)
-  uint32_t* meta;  // [cap] n | par << 3 | flags << 8
-  uint16_t* ssl;   // [cap] sorted slots (spill copy)
+  gdouble* root;   // [5][cap] (re, im) positive, negative real images, ghost pair
+  gdouble* dz;     // [5][cap] (re, im) z' of the real images
+  gdouble* w;      // [5][cap] z' ^ z''
+  gdouble* th;     // [cap] limb angle of the slot
+  gdouble* dA;     // [cap] area of the interval starting at this slot
+  gdouble* sth;    // [cap] sorted angles (spill copy)
+  gdouble* sE;     // [cap] sorted interval errors (spill copy)
+  guint32* meta;   // [cap] sample meta word
+  guint16* ssl;    // [cap] sorted slots (spill copy)
   int cap;
 };
 
@@ -60,24 +78,31 @@ __device__ __forceinline__ WaveMem wave_mem(char* base, int wave, int cap) {
   char* p = base + (size_t)wave * (size_t)cap * kSlotBytes;
   WaveMem m;
   m.cap = cap;
-  m.root = (c64*)p;
+  m.root = (gdouble*)p;
   p += (size_t)5 * cap * 16;
-  m.dz = (c64*)p;
+  m.dz = (gdouble*)p;
   p += (size_t)5 * cap * 16;
-  m.w = (double*)p;
+  m.w = (gdouble*)p;
   p += (size_t)5 * cap * 8;
-  m.th = (double*)p;
+  m.th = (gdouble*)p;
   p += (size_t)cap * 8;
-  m.dA = (double*)p;
+  m.dA = (gdouble*)p;
   p += (size_t)cap * 8;
-  m.sth = (double*)p;
+  m.sth = (gdouble*)p;
   p += (size_t)cap * 8;
-  m.sE = (double*)p;
+  m.sE = (gdouble*)p;
   p += (size_t)cap * 8;
-  m.meta = (uint32_t*)p;
+  m.meta = (guint32*)p;
   p += (size_t)cap * 4;
-  m.ssl = (uint16_t*)p;
+  m.ssl = (guint16*)p;
   return m;
+}
+
+// Complex entries of the records, stored as (re, im) pairs.
+__device__ __forceinline__ c64 ld_c(const gdouble* a, int i) { return cz(a[2 * i], a[2 * i + 1]); }
+__device__ __forceinline__ void st_c(gdouble* a, int i, c64 v) {
+  a[2 * i] = v.x;
+  a[2 * i + 1] = v.y;
 }
 
 // Interval flag bits
@@ -125,8 +150,8 @@ __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double
     c64 dz = cz(0.0, 0.0);
     double w = 0.0;
     if (k < im.n) limb_derivs(L, im.z[k], im.J[k], zp1, rho, dz, w);
-    m.root[k * m.cap + slot] = im.z[k];
-    m.dz[k * m.cap + slot] = dz;
+    st_c(m.root, k * m.cap + slot, im.z[k]);
+    st_c(m.dz, k * m.cap + slot, dz);
     m.w[k * m.cap + slot] = w;
   }
   m.th[slot] = theta;
@@ -142,8 +167,8 @@ __device__ __forceinline__ void warm_start(const WaveMem& m, int slot, double dt
   const int n = m.meta[slot] & 7u;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    r[k] = m.root[k * m.cap + slot];
-    if (k < n) r[k] = r[k] + dtheta * m.dz[k * m.cap + slot];
+    r[k] = ld_c(m.root, k * m.cap + slot);
+    if (k < n) r[k] = r[k] + dtheta * ld_c(m.dz, k * m.cap + slot);
   }
 }
 
@@ -235,8 +260,8 @@ struct Piece {
 // E3 = |dA_p| dth^2 / 10, E4 = |dA_p1 - dA_p2|.
 __device__ __forceinline__ void add_link(const WaveMem& m, int sa, int ia, int sb, int ib,
                                          double par, double dth, Piece& out) {
-  const c64 za = m.root[ia * m.cap + sa], zb = m.root[ib * m.cap + sb];
-  const c64 da = m.dz[ia * m.cap + sa], db = m.dz[ib * m.cap + sb];
+  const c64 za = ld_c(m.root, ia * m.cap + sa), zb = ld_c(m.root, ib * m.cap + sb);
+  const c64 da = ld_c(m.dz, ia * m.cap + sa), db = ld_c(m.dz, ib * m.cap + sb);
   const double wa = m.w[ia * m.cap + sa], wb = m.w[ib * m.cap + sb];
   const double dth2 = dth * dth, dth3 = dth2 * dth;
   const double dAt = 0.5 * cwedge(za, zb);
@@ -261,8 +286,8 @@ __device__ __forceinline__ void add_link(const WaveMem& m, int sa, int ia, int s
 // for creation along +theta), E3 = |dA_p| dth^2 / 10.
 __device__ __forceinline__ void add_cross(const WaveMem& m, int sc, int ip, int in, int kind,
                                           double dth, Piece& out) {
-  const c64 zp = m.root[ip * m.cap + sc], zm = m.root[in * m.cap + sc];
-  const c64 dp = m.dz[ip * m.cap + sc], dm = m.dz[in * m.cap + sc];
+  const c64 zp = ld_c(m.root, ip * m.cap + sc), zm = ld_c(m.root, in * m.cap + sc);
+  const c64 dp = ld_c(m.dz, ip * m.cap + sc), dm = ld_c(m.dz, in * m.cap + sc);
   const double wp = m.w[ip * m.cap + sc], wm = m.w[in * m.cap + sc];
   const double dd = sqrt(fabs(cdot(dp, dm)));
   const double sep = cabs64(zp - zm);
@@ -288,8 +313,8 @@ __device__ __attribute__((noinline)) Piece interval_piece_any(const WaveMem& m, 
   const int na_ = ma_ & 7u, nb_ = mb_ & 7u;
   const uint32_t para = (ma_ >> 3) & 31u, parb = (mb_ >> 3) & 31u;
   for (int k = 0; k < 5; ++k) {
-    za[k] = m.root[k * m.cap + sa];
-    zb[k] = m.root[k * m.cap + sb];
+    za[k] = ld_c(m.root, k * m.cap + sa);
+    zb[k] = ld_c(m.root, k * m.cap + sb);
   }
   int pa[5], ma[5], pb[5], mb[5];
   int npa = 0, nma = 0, npb = 0, nmb = 0;
@@ -353,8 +378,8 @@ __device__ inline Piece interval_piece(const WaveMem& m, int sa, int sb, double 
   c64 za[5], zb[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    za[k] = m.root[k * m.cap + sa];
-    zb[k] = m.root[k * m.cap + sb];
+    za[k] = ld_c(m.root, k * m.cap + sa);
+    zb[k] = ld_c(m.root, k * m.cap + sb);
   }
   Piece out{0.0, 0.0, na != nb ? (uint32_t)IF_COUNT : 0u};
   if (na == 3 && nb == 3) {
@@ -442,14 +467,18 @@ struct FsLds {
   int ivl[NNEW];      // old interval index of each accepted new sample
 };
 
-// The sorted arrays in use: the LDS copy, or, once a source outgrows it,
-// the spill copy in the wave's global slice (generic pointers address both).
-struct Sorted {
-  double* th;
-  double* E;
-  uint16_t* sl;
+// The sorted arrays in use: the LDS copy (D = ldouble, U = luint16), or,
+// once a source outgrows it, the spill copy in the wave's global slice
+// (D = gdouble, U = guint16).
+template <class D, class U>
+struct SortedT {
+  D* th;
+  D* E;
+  U* sl;
   int cap;
 };
+typedef SortedT<ldouble, luint16> SortedL;
+typedef SortedT<gdouble, guint16> SortedG;
 
 struct FsOut {
   double mag, err;
@@ -461,6 +490,7 @@ struct FsOut {
 
 // Relink the interval starting at sorted position p (of N): area to the
 // global record of its left slot, error to the sorted arrays.
+template <class Sorted>
 __device__ __forceinline__ Piece relink(const WaveMem& m, const Sorted& S, int p, int N) {
   const int q = p + 1 < N ? p + 1 : 0;
   const int sa = S.sl[p], sb = S.sl[q];
@@ -482,13 +512,13 @@ __device__ inline void permute_record(const WaveMem& m, int slot, const int* fro
   double w[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    z[k] = m.root[k * m.cap + slot];
-    d[k] = m.dz[k * m.cap + slot];
+    z[k] = ld_c(m.root, k * m.cap + slot);
+    d[k] = ld_c(m.dz, k * m.cap + slot);
     w[k] = m.w[k * m.cap + slot];
   }
   for (int k = 0; k < 5; ++k) {
-    m.root[k * m.cap + slot] = z[from[k]];
-    m.dz[k * m.cap + slot] = d[from[k]];
+    st_c(m.root, k * m.cap + slot, z[from[k]]);
+    st_c(m.dz, k * m.cap + slot, d[from[k]]);
     m.w[k * m.cap + slot] = w[from[k]];
   }
 }
@@ -536,8 +566,8 @@ __device__ inline int pair_link(const WaveMem& m, int sa, int sb, int& cp, int& 
   c64 za[5], zb[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    za[k] = m.root[k * m.cap + sa];
-    zb[k] = m.root[k * m.cap + sb];
+    za[k] = ld_c(m.root, k * m.cap + sa);
+    zb[k] = ld_c(m.root, k * m.cap + sb);
   }
   if (standard3(ma) && standard5(mb)) {
     const uint32_t p = inject_static<1, 2>(za, zb);
@@ -562,8 +592,8 @@ __device__ inline bool follow_pair(const WaveMem& m, int s0, int s1, int& cp, in
   c64 z0[5], z1[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    z0[k] = m.root[k * m.cap + s0];
-    z1[k] = m.root[k * m.cap + s1];
+    z0[k] = ld_c(m.root, k * m.cap + s0);
+    z1[k] = ld_c(m.root, k * m.cap + s1);
   }
   const uint32_t p = inject_static<2, 2>(z0, z1);
   const uint32_t n = inject_static<3, 3>(z0 + 2, z1 + 2);
@@ -583,7 +613,7 @@ __device__ inline bool perp_enough(c64 D, c64 G, c64 zref) {
 }
 
 __device__ __forceinline__ c64 root_at(const WaveMem& m, int slot, int k) {
-  return m.root[k * m.cap + slot];
+  return ld_c(m.root, k * m.cap + slot);
 }
 
 // From the three-image sample at sorted position kb, test the crossing into
@@ -592,6 +622,7 @@ __device__ __forceinline__ c64 root_at(const WaveMem& m, int slot, int k) {
 // enough, walk into the run demoting suspect samples until consecutive
 // pair differences turn perpendicular (or the whole run is walked: the
 // piece is deleted).  Returns the number of samples demoted.
+template <class Sorted>
 __device__ inline int walk_run(const WaveMem& m, const Sorted& S, int N, int kb, int first, int len,
                                bool from_start) {
   const int j0 = from_start ? 0 : len - 1, dj = from_start ? 1 : -1;
@@ -632,6 +663,7 @@ __device__ __forceinline__ int orig_n(uint32_t mt) { return (mt & M_DEMOTED) ? 5
 
 // Runs of five-image samples between three-image ones, each examined from
 // both ends (serial; sources with suspect samples are rare).
+template <class Sorted>
 __device__ inline int detect_runs(const WaveMem& m, const Sorted& S, int N) {
   int anchor = -1;
   for (int i = 0; i < N; ++i)
@@ -654,6 +686,7 @@ __device__ inline int detect_runs(const WaveMem& m, const Sorted& S, int N) {
 // Full slope-detector pass of one source: undo last round's demotions,
 // re-examine every run, relink every interval and recompute the area total
 // (compensated).  Returns true if any sample is demoted.
+template <class Sorted>
 __device__ __attribute__((noinline)) bool slope_pass(const WaveMem& m, const Sorted& S, int N,
                                                      int lane, double* Ahi, double* Alo,
                                                      uint32_t* nint) {
@@ -686,20 +719,28 @@ __device__ __attribute__((noinline)) bool slope_pass(const WaveMem& m, const Sor
 // magnification to meet tol.
 constexpr double TOL_SAFETY = 0.5;
 
-template <int LCAP, bool MIXED>
-__device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, FsLds<LCAP>& L,
-                           int lane, int n0) {
-  const double tol = tol_stated * TOL_SAFETY;
-  Sorted S{L.th, L.E, L.sl, LCAP};
-  bool spilled = false;
-  const Lens lens = make_lens(T.s, T.q);
-  const c64 yc = cz(T.zx - lens.z2, T.zy);
+// Running state of one source's contour integration: wave-uniform totals
+// and per-lane work counters.
+struct FsState {
+  int N;
+  double Ahi, Alo, A, E;
+  uint32_t fl, sw32, sw64, nint;
+  bool suspects;  // some sample may hold a misjudged ghost pair
+};
+
+// Rounds of the contour integration on the sorted arrays S.  Returns true
+// when the source is finished, false when the next round would outgrow S
+// (only the LDS copy can be outgrown): the caller moves the sorted arrays to
+// the wave's global slice and continues there.
+template <int LCAP, bool MIXED, class Sorted>
+__device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 yc, double tol,
+                                          const WaveMem& m, FsLds<LCAP>& L, const Sorted& S,
+                                          int lane, int n0, FsState& st) {
   const double rho = T.rho;
-  uint32_t fl = 0;
-  uint32_t sw32 = 0, sw64 = 0, nint = 0;  // this lane's work
-  int N = 0;
-  double Ahi = 0.0, Alo = 0.0, A = 0.0, E = 0.0;
-  bool suspects = false;  // some sample may hold a misjudged ghost pair
+  int& N = st.N;
+  double &Ahi = st.Ahi, &Alo = st.Alo, &A = st.A, &E = st.E;
+  uint32_t &fl = st.fl, &sw32 = st.sw32, &sw64 = st.sw64, &nint = st.nint;
+  bool& suspects = st.suspects;
   // One round per iteration.  The first n0 samples form the uniform grid
   // theta = 2 pi i / n0, laid down 64 at a time: round r adds the phase
   // offset r / (n0 / 64) of the base grid theta_j = 2 pi j / 64 (whose
@@ -734,17 +775,8 @@ __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, F
       }
       E = wave_sum(es);
       if (E <= tol * fabs(A)) break;
-      if (N + NNEW > S.cap && S.cap < METHOD_CAP) {
-        // outgrowing the LDS copy: continue on the spill copy in global memory
-        for (int p = lane; p < N; p += WAVE) {
-          m.sth[p] = S.th[p];
-          m.sE[p] = S.E[p];
-          m.ssl[p] = S.sl[p];
-        }
-        __syncthreads();
-        S = Sorted{m.sth, m.sE, m.ssl, METHOD_CAP};
-        spilled = true;
-      }
+      // outgrowing the LDS copy: the caller continues in global memory
+      if (N + NNEW > S.cap && S.cap < METHOD_CAP) return false;
       const int nnew = N + NNEW <= S.cap ? NNEW : S.cap - N;
       if (nnew <= 0) { fl |= F_CAP; break; }
       const double W = wave_sum(ws);
@@ -896,16 +928,52 @@ __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, F
     __syncthreads();
     if (suspects && slope_pass(m, S, N, lane, &Ahi, &Alo, &nint)) fl |= F_SLOPE;
   }
+  return true;
+}
+
+// Continuation of a source that outgrew its LDS copy (rare: kept out of line).
+// Arguments and state go by value so that nothing of the hot path has its
+// address taken.
+template <int LCAP, bool MIXED>
+__device__ __attribute__((noinline)) FsState fs_rounds_spilled(Task T, double tol, WaveMem m,
+                                                               FsLds<LCAP>& L, int lane,
+                                                               FsState st) {
+  const Lens lens = make_lens(T.s, T.q);
+  const c64 yc = cz(T.zx - lens.z2, T.zy);
+  const SortedG S{m.sth, m.sE, m.ssl, METHOD_CAP};
+  fs_rounds<LCAP, MIXED>(T, lens, yc, tol, m, L, S, lane, 0, st);
+  return st;
+}
+
+template <int LCAP, bool MIXED>
+__device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, FsLds<LCAP>& L,
+                           int lane, int n0) {
+  const double tol = tol_stated * TOL_SAFETY;
+  const Lens lens = make_lens(T.s, T.q);
+  const c64 yc = cz(T.zx - lens.z2, T.zy);
+  FsState st{0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, false};
+  const SortedL S{(ldouble*)L.th, (ldouble*)L.E, (luint16*)L.sl, LCAP};
+  bool spilled = false;
+  if (!fs_rounds<LCAP, MIXED>(T, lens, yc, tol, m, L, S, lane, n0, st)) {
+    for (int p = lane; p < st.N; p += WAVE) {
+      m.sth[p] = S.th[p];
+      m.sE[p] = S.E[p];
+      m.ssl[p] = S.sl[p];
+    }
+    __syncthreads();
+    st = fs_rounds_spilled<LCAP, MIXED>(T, tol, m, L, lane, st);
+    spilled = true;
+  }
   FsOut o;
-  const double area = PI_64 * rho * rho;
-  o.mag = A / area;
-  o.err = E / area;
-  o.n = N;
-  o.flags = wave_or(fl);
+  const double area = PI_64 * T.rho * T.rho;
+  o.mag = st.A / area;
+  o.err = st.E / area;
+  o.n = st.N;
+  o.flags = wave_or(st.fl);
   o.spilled = spilled;
-  o.sweeps32 = wave_sum((double)sw32);
-  o.sweeps64 = wave_sum((double)sw64);
-  o.intervals = wave_sum((double)nint);
+  o.sweeps32 = wave_sum((double)st.sw32);
+  o.sweeps64 = wave_sum((double)st.sw64);
+  o.intervals = wave_sum((double)st.nint);
   return o;
 }
 

@@ -13,6 +13,9 @@
 #define __host__
 #define __global__
 #define __forceinline__ inline
+// the CPU has one address space
+#define TWK_GLOBAL_AS
+#define TWK_LDS_AS
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))
 #define __builtin_amdgcn_rcpf(x) (1.0f / (x))
 
