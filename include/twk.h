@@ -140,7 +140,9 @@ int twk_last_stats(twk_ctx *ctx, int64_t *out8);
  * enable).  After a finite-source call, twk_kernel_times writes (host
  * pointer ms[5], milliseconds): for the first chunk the point-source pass,
  * the learned stage (0 without TWK_MODE_MLP) and the contour kernel; then
- * the rest of the call and the whole call.  Waits for the call.
+ * the rest of the call and the whole call.  A call replayed from a captured
+ * graph is timed as a whole (the per-stage entries read 0).  Waits for the
+ * call.
  * Errors: TWK_EINVAL if timing is off. */
 int twk_enable_timing(twk_ctx *ctx, int on);
 int twk_kernel_times(twk_ctx *ctx, double *ms5);
@@ -160,17 +162,20 @@ typedef struct {
   int32_t graphs;       /* 1: capture each call's launch sequence in a hipGraph and
                            replay it when an identical call (same arguments and
                            pointers) repeats; needs a created (non-null) stream */
+  int32_t rec_cap;      /* sample records a source keeps in LDS (the rest go to
+                           global memory): 0 .. 512, a multiple of 16 */
 } twk_tuning;
 
-/* Current tuning (defaults: the occupancy limit at lds_cap 512, shift 1, no
- * graphs). */
+/* Current tuning (defaults: the occupancy limit at lds_cap 512, records in
+ * global memory, shift 1, no graphs). */
 int twk_get_tuning(twk_ctx *ctx, twk_tuning *out);
 /* Set the tuning; synchronises the stream and drops captured graphs.
  * TWK_EINVAL for values out of range (graphs on a null stream included). */
 int twk_set_tuning(twk_ctx *ctx, const twk_tuning *t);
 /* Autotuner: times twk_lightcurves on this batch (a representative sample
- * of the workload; arguments as for twk_lightcurves) for every LDS capacity
- * and four persistent grid sizes, then, with TWK_MODE_MLP, six budget
+ * of the workload; arguments as for twk_lightcurves) for every LDS capacity,
+ * record capacities 0/64/128/192 and four persistent grid sizes each, then,
+ * with TWK_MODE_MLP, six budget
  * shifts, taking the fastest of `trials` (1..100) calls per candidate; the
  * best tuning is left in the context (graphs setting unchanged) and copied
  * to *best (may be NULL).  Synchronous; allocates its own output buffers. */

@@ -482,18 +482,20 @@ __global__ __launch_bounds__(256) void k_place(long long* cnt, const float* out,
 // Persistent finite-source kernel: each wave pops tasks until the queue is
 // drained (every wave reaches the exit: the queue length is fixed before
 // launch and each pop advances the head).
+// The first rcap sample records of each source live in the block's dynamic
+// LDS (rcap * kRecBytes bytes, given at launch).
 template <int LCAP, bool MIXED>
 #ifndef TWK_FS_WAVES_PER_EU
 #define TWK_FS_WAVES_PER_EU 2
 #endif
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES_PER_EU))) void k_fs(const Task* tasks, const long long* ntask,
-                                           long long* head, double tol, char* scratch,
-                                           double* mag, double* err, int32_t* ns,
-                                           uint32_t* flags, long long* cnt,
-                                           const int32_t* order, const int32_t* tn0) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES_PER_EU))) void k_fs(
+    const Task* tasks, const long long* ntask, long long* head, double tol, char* scratch,
+    double* mag, double* err, int32_t* ns, uint32_t* flags, long long* cnt, const int32_t* order,
+    const int32_t* tn0, int rcap) {
   __shared__ FsLds<LCAP> lds;
+  extern __shared__ __attribute__((aligned(16))) char rec_lds[];
   const int lane = threadIdx.x;
-  const WaveMem m = wave_mem(scratch, blockIdx.x, METHOD_CAP);
+  const WaveMem m = wave_mem(scratch, blockIdx.x, rcap > 0 ? rec_lds : nullptr, rcap);
   const long long n = *ntask;
   for (;;) {
     long long t = 0;
@@ -542,8 +544,8 @@ struct twk_ctx {
   bool timing = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   // launch tuning of the contour stage, and graph replay
-  twk_tuning tune{0, 512, 1.0f, 0};
-  int max_wpc[3] = {0, 0, 0};  // waves per CU the hardware allows, per LDS_CAPS entry
+  twk_tuning tune{0, 512, 1.0f, 0, 0};
+  bool capturing = false;  // no event marks inside a capture
   // captured launch sequences (replayed when a call repeats)
   struct Graph {
     uint64_t key[24];
@@ -607,13 +609,29 @@ int grow(twk_ctx* c, void** p, size_t* have, size_t need) {
   return TWK_OK;
 }
 
+size_t rec_bytes(int rcap) { return (size_t)rcap * kRecBytes; }
+
 template <int LCAP>
-hipError_t occupancy(int* blocks) {
+hipError_t occupancy(int rcap, int* blocks) {
   int b1 = 0, b2 = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fs<LCAP, false>, 64, 0);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fs<LCAP, true>, 64, 0);
-  *blocks = std::max(1, std::min(b1, b2));
+  hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fs<LCAP, false>, 64, rec_bytes(rcap));
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fs<LCAP, true>, 64, rec_bytes(rcap));
+  *blocks = std::min(b1, b2);
   return e;
+}
+
+// Waves per CU the hardware allows for an LDS capacity and a record
+// capacity (0 if the combination does not fit).
+int max_waves(int lds_cap, int rcap, int* out) {
+  hipError_t e;
+  switch (lds_cap) {
+    case 256: e = occupancy<256>(rcap, out); break;
+    case 1024: e = occupancy<1024>(rcap, out); break;
+    default: e = occupancy<512>(rcap, out); break;
+  }
+  return e == hipSuccess ? TWK_OK : TWK_EDEVICE;
 }
 
 int cap_index(int lds_cap) {
@@ -711,13 +729,13 @@ template <int LCAP>
 void launch_fs_cap(twk_ctx* c, bool mixed, double tol, double* mag, double* err, int32_t* ns,
                    uint32_t* flags, const int32_t* order, const int32_t* n0) {
   if (mixed)
-    hipLaunchKernelGGL((k_fs<LCAP, true>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
-                       &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
-                       c->cnt, order, n0);
+    hipLaunchKernelGGL((k_fs<LCAP, true>), dim3(c->waves), dim3(64), rec_bytes(c->tune.rec_cap),
+                       c->stream, c->tasks, &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch,
+                       mag, err, ns, flags, c->cnt, order, n0, (int)c->tune.rec_cap);
   else
-    hipLaunchKernelGGL((k_fs<LCAP, false>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
-                       &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
-                       c->cnt, order, n0);
+    hipLaunchKernelGGL((k_fs<LCAP, false>), dim3(c->waves), dim3(64), rec_bytes(c->tune.rec_cap),
+                       c->stream, c->tasks, &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch,
+                       mag, err, ns, flags, c->cnt, order, n0, (int)c->tune.rec_cap);
 }
 
 int launch_fs(twk_ctx* c, bool mixed, bool learned, double tol, double* mag, double* err,
@@ -740,7 +758,7 @@ int reset(twk_ctx* c, bool queue_only) {
 }
 
 int mark(twk_ctx* c, int i, bool on) {
-  if (c->timing && on) HIP_TRY(c, hipEventRecord(c->ev[i], c->stream));
+  if (c->timing && on && !c->capturing) HIP_TRY(c, hipEventRecord(c->ev[i], c->stream));
   return TWK_OK;
 }
 
@@ -782,12 +800,12 @@ int twk_create(twk_ctx** out, int device, void* stream) {
     return TWK_EDEVICE;
   }
   c->n_cu = prop.multiProcessorCount;
-  if (occupancy<256>(&c->max_wpc[0]) != hipSuccess || occupancy<512>(&c->max_wpc[1]) != hipSuccess ||
-      occupancy<1024>(&c->max_wpc[2]) != hipSuccess) {
+  int wpc = 0;
+  if (max_waves(512, 0, &wpc) != TWK_OK || wpc < 1) {
     delete c;
     return TWK_EDEVICE;
   }
-  c->tune.waves_per_cu = c->max_wpc[1];
+  c->tune.waves_per_cu = wpc;
   c->waves = fs_waves(c);
   if (hipMalloc((void**)&c->cnt, C_NCOUNTERS * sizeof(long long)) != hipSuccess) {
     delete c;
@@ -848,7 +866,7 @@ namespace {
 constexpr uint32_t KNOWN_MODES = TWK_MODE_MIXED | TWK_MODE_MLP | TWK_MODE_ALL_FS;
 
 // Identity of a call for graph replay: entry point, scalar arguments (as
-// bits), device pointers, tuning and timing state.
+// bits), device pointers and tuning.
 struct CallKey {
   uint64_t w[24] = {};
   int n = 0;
@@ -868,22 +886,32 @@ CallKey& tuning_key(CallKey& k, const twk_ctx* c) {
   uint32_t sh;
   std::memcpy(&sh, &c->tune.budget_shift, 4);
   return k.u((uint64_t)c->tune.waves_per_cu | ((uint64_t)c->tune.lds_cap << 20) |
-             ((uint64_t)sh << 32)).u(c->timing ? 1 : 0);
+             ((uint64_t)sh << 32)).u((uint64_t)c->tune.rec_cap);
 }
 
 // Issue the launch sequence of a call, or, with graph replay on, replay
 // the captured sequence of an identical earlier call (capturing it the
 // first time).  Nothing inside `issue` may allocate or synchronise.
+// With timing on, a replayed call is timed as a whole: events 0 before the
+// graph launch, 1..4 after it (per-stage times read 0).
+int launch_graph(twk_ctx* c, hipGraphExec_t ex) {
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+  HIP_TRY(c, hipGraphLaunch(ex, c->stream));
+  if (c->timing)
+    for (int i = 1; i < 5; ++i) HIP_TRY(c, hipEventRecord(c->ev[i], c->stream));
+  return TWK_OK;
+}
+
 template <class F>
 int run_captured(twk_ctx* c, const CallKey& key, F&& issue) {
   if (!c->tune.graphs) return issue();
   for (int i = 0; i < c->n_graphs; ++i)
-    if (std::memcmp(c->graphs[i].key, key.w, sizeof(key.w)) == 0) {
-      HIP_TRY(c, hipGraphLaunch(c->graphs[i].exec, c->stream));
-      return TWK_OK;
-    }
+    if (std::memcmp(c->graphs[i].key, key.w, sizeof(key.w)) == 0)
+      return launch_graph(c, c->graphs[i].exec);
   HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
   const int rc = issue();
+  c->capturing = false;
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->stream, &g);
   if (rc || e != hipSuccess) {
@@ -904,8 +932,7 @@ int run_captured(twk_ctx* c, const CallKey& key, F&& issue) {
   }
   std::memcpy(c->graphs[slot].key, key.w, sizeof(key.w));
   c->graphs[slot].exec = ex;
-  HIP_TRY(c, hipGraphLaunch(ex, c->stream));
-  return TWK_OK;
+  return launch_graph(c, ex);
 }
 
 // Mode bits: unknown bits are rejected; the learned budget needs weights.
@@ -1508,10 +1535,13 @@ int twk_get_tuning(twk_ctx* c, twk_tuning* out) {
 
 int twk_set_tuning(twk_ctx* c, const twk_tuning* t) {
   if (!c || !t) return TWK_EINVAL;
-  const int ci = cap_index(t->lds_cap);
-  if (ci < 0 || t->waves_per_cu < 1 || t->waves_per_cu > c->max_wpc[ci] ||
+  if (cap_index(t->lds_cap) < 0 || t->rec_cap < 0 || t->rec_cap > 512 || t->rec_cap % 16 ||
       !(t->budget_shift >= -2.0f && t->budget_shift <= 4.0f) || (t->graphs != 0 && t->graphs != 1))
     return TWK_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  int mx = 0;
+  if (max_waves(t->lds_cap, t->rec_cap, &mx) != TWK_OK) return TWK_EDEVICE;
+  if (t->waves_per_cu < 1 || t->waves_per_cu > mx) return TWK_EINVAL;
   // capture needs a created stream (the legacy null stream cannot be captured)
   if (t->graphs && c->stream == nullptr) return TWK_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
@@ -1571,23 +1601,28 @@ int twk_autotune(twk_ctx* c, int64_t nsets, const double* s, const double* q, co
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     rc = hip_fail(c, hipGetLastError());
   } else {
-    // persistent grid and LDS capacity, then (learned path) the budget shift
-    for (int ci = 0; ci < 3 && rc == TWK_OK; ++ci) {
-      const int mx = c->max_wpc[ci];
-      int last = 0;
-      for (int f = 1; f <= 4 && rc == TWK_OK; ++f) {
-        const int w = std::max(1, (mx * f) / 4);
-        if (w == last) continue;
-        last = w;
-        cur.lds_cap = LDS_CAPS[ci];
-        cur.waves_per_cu = w;
-        double ms;
-        if ((rc = measure(cur, &ms)) == TWK_OK && ms < best_ms) {
-          best_ms = ms;
-          top = cur;
+    // persistent grid, LDS capacity of the sorted arrays and of the sample
+    // records, then (learned path) the budget shift
+    const int rcaps[4] = {0, 64, 128, 192};
+    for (int ci = 0; ci < 3 && rc == TWK_OK; ++ci)
+      for (int ri = 0; ri < 4 && rc == TWK_OK; ++ri) {
+        int mx = 0;
+        if ((rc = max_waves(LDS_CAPS[ci], rcaps[ri], &mx)) != TWK_OK) break;
+        int last = 0;
+        for (int f = 1; f <= 4 && rc == TWK_OK && mx > 0; ++f) {
+          const int w = std::max(1, (mx * f) / 4);
+          if (w == last) continue;
+          last = w;
+          cur.lds_cap = LDS_CAPS[ci];
+          cur.rec_cap = rcaps[ri];
+          cur.waves_per_cu = w;
+          double ms;
+          if ((rc = measure(cur, &ms)) == TWK_OK && ms < best_ms) {
+            best_ms = ms;
+            top = cur;
+          }
         }
       }
-    }
     if (rc == TWK_OK && (mode & TWK_MODE_MLP)) {
       const float shifts[6] = {0.0f, 0.5f, 1.0f, 1.5f, 2.0f, 3.0f};
       cur = top;

@@ -51,58 +51,108 @@ struct Task {
   c64 roots[5];
 };
 
-// Per-wave slice of the sample scratch: SoA over slots [0, cap), plus room
-// for the sorted arrays when a source outgrows its LDS copy.
 typedef TWK_GLOBAL_AS double gdouble;
-typedef TWK_GLOBAL_AS uint32_t guint32;
 typedef TWK_GLOBAL_AS uint16_t guint16;
 typedef TWK_LDS_AS double ldouble;
 typedef TWK_LDS_AS uint16_t luint16;
 
-struct WaveMem {
-  gdouble* root;   // [5][cap] (re, im) positive, negative real images, ghost pair
-  gdouble* dz;     // [5][cap] (re, im) z' of the real images
-  gdouble* w;      // [5][cap] z' ^ z''
-  gdouble* th;     // [cap] limb angle of the slot
-  gdouble* dA;     // [cap] area of the interval starting at this slot
-  gdouble* sth;    // [cap] sorted angles (spill copy)
-  gdouble* sE;     // [cap] sorted interval errors (spill copy)
-  guint32* meta;   // [cap] sample meta word
-  guint16* ssl;    // [cap] sorted slots (spill copy)
+// Sample records, SoA over slots (slot = creation order): five roots
+// (positive, negative real images, ghost pair) as (re, im), five z' as
+// (re, im), five z' ^ z'', the area of the interval starting at the slot,
+// and the meta word.  The first rcap slots of a source live in LDS, the rest
+// in the wave's slice of global scratch; accessors pick the region per slot
+// (generic pointers), so a source that fits never leaves the CU.
+struct RecArr {
+  double* root;    // [5][cap][2]
+  double* dz;      // [5][cap][2]
+  double* w;       // [5][cap]
+  double* dA;      // [cap]
+  uint32_t* meta;  // [cap]
   int cap;
 };
 
-constexpr size_t kSlotBytes = 5 * 16 + 5 * 16 + 5 * 8 + 8 + 8 + 8 + 8 + 4 + 2;
+constexpr size_t kRecBytes = 5 * 16 + 5 * 16 + 5 * 8 + 8 + 4;  // 212 per slot
 
-__device__ __forceinline__ WaveMem wave_mem(char* base, int wave, int cap) {
-  char* p = base + (size_t)wave * (size_t)cap * kSlotBytes;
-  WaveMem m;
-  m.cap = cap;
-  m.root = (gdouble*)p;
+struct WaveMem {
+  RecArr L;      // slots [0, rcap) in LDS
+  RecArr G;      // slots [rcap, METHOD_CAP) in global memory (indexed by slot)
+  int rcap;
+  gdouble* sth;  // sorted angles (spill copy)
+  gdouble* sE;   // sorted interval errors (spill copy)
+  guint16* ssl;  // sorted slots (spill copy)
+};
+
+// Global bytes per wave: records of every slot plus the sorted spill copies.
+constexpr size_t kSlotBytes = kRecBytes + 8 + 8 + 2;
+
+__device__ __forceinline__ RecArr carve(char* p, int cap) {
+  RecArr r;
+  r.cap = cap;
+  r.root = (double*)p;
   p += (size_t)5 * cap * 16;
-  m.dz = (gdouble*)p;
+  r.dz = (double*)p;
   p += (size_t)5 * cap * 16;
-  m.w = (gdouble*)p;
+  r.w = (double*)p;
   p += (size_t)5 * cap * 8;
-  m.th = (gdouble*)p;
+  r.dA = (double*)p;
   p += (size_t)cap * 8;
-  m.dA = (gdouble*)p;
-  p += (size_t)cap * 8;
+  r.meta = (uint32_t*)p;
+  return r;
+}
+
+// lds: the wave's LDS record area (rcap * kRecBytes bytes; may be null when
+// rcap = 0).
+__device__ __forceinline__ WaveMem wave_mem(char* base, int wave, char* lds, int rcap) {
+  char* p = base + (size_t)wave * (size_t)METHOD_CAP * kSlotBytes;
+  WaveMem m;
+  m.rcap = rcap;
+  m.L = carve(lds, rcap);
+  m.G = carve(p, METHOD_CAP);
+  p += (size_t)METHOD_CAP * kRecBytes;
   m.sth = (gdouble*)p;
-  p += (size_t)cap * 8;
+  p += (size_t)METHOD_CAP * 8;
   m.sE = (gdouble*)p;
-  p += (size_t)cap * 8;
-  m.meta = (guint32*)p;
-  p += (size_t)cap * 4;
+  p += (size_t)METHOD_CAP * 8;
   m.ssl = (guint16*)p;
   return m;
 }
 
-// Complex entries of the records, stored as (re, im) pairs.
-__device__ __forceinline__ c64 ld_c(const gdouble* a, int i) { return cz(a[2 * i], a[2 * i + 1]); }
-__device__ __forceinline__ void st_c(gdouble* a, int i, c64 v) {
-  a[2 * i] = v.x;
-  a[2 * i + 1] = v.y;
+__device__ __forceinline__ const RecArr& rec(const WaveMem& m, int slot) {
+  return slot < m.rcap ? m.L : m.G;
+}
+__device__ __forceinline__ c64 ld_root(const WaveMem& m, int k, int slot) {
+  const RecArr& r = rec(m, slot);
+  const double* q = r.root + 2 * (k * r.cap + slot);
+  return cz(q[0], q[1]);
+}
+__device__ __forceinline__ c64 ld_dz(const WaveMem& m, int k, int slot) {
+  const RecArr& r = rec(m, slot);
+  const double* q = r.dz + 2 * (k * r.cap + slot);
+  return cz(q[0], q[1]);
+}
+__device__ __forceinline__ void st_root(const WaveMem& m, int k, int slot, c64 v) {
+  const RecArr& r = rec(m, slot);
+  double* q = r.root + 2 * (k * r.cap + slot);
+  q[0] = v.x;
+  q[1] = v.y;
+}
+__device__ __forceinline__ void st_dz(const WaveMem& m, int k, int slot, c64 v) {
+  const RecArr& r = rec(m, slot);
+  double* q = r.dz + 2 * (k * r.cap + slot);
+  q[0] = v.x;
+  q[1] = v.y;
+}
+__device__ __forceinline__ double& w_at(const WaveMem& m, int k, int slot) {
+  const RecArr& r = rec(m, slot);
+  return r.w[k * r.cap + slot];
+}
+__device__ __forceinline__ double& dA_at(const WaveMem& m, int slot) {
+  const RecArr& r = rec(m, slot);
+  return r.dA[slot];
+}
+__device__ __forceinline__ uint32_t& meta_at(const WaveMem& m, int slot) {
+  const RecArr& r = rec(m, slot);
+  return r.meta[slot];
 }
 
 // Interval flag bits
@@ -150,13 +200,12 @@ __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double
     c64 dz = cz(0.0, 0.0);
     double w = 0.0;
     if (k < im.n) limb_derivs(L, im.z[k], im.J[k], zp1, rho, dz, w);
-    st_c(m.root, k * m.cap + slot, im.z[k]);
-    st_c(m.dz, k * m.cap + slot, dz);
-    m.w[k * m.cap + slot] = w;
+    st_root(m, k, slot, im.z[k]);
+    st_dz(m, k, slot, dz);
+    w_at(m, k, slot) = w;
   }
-  m.th[slot] = theta;
   const bool suspect = im.n == 5 && im.par == 3u && im.margin > SUSPECT;
-  m.meta[slot] = (uint32_t)im.n | (im.par << 3) | (im.flags << 8) | (suspect ? M_SUSPECT : 0u);
+  meta_at(m, slot) = (uint32_t)im.n | (im.par << 3) | (im.flags << 8) | (suspect ? M_SUSPECT : 0u);
   *fl = im.flags | (suspect ? M_SUSPECT : 0u);
   return (uint32_t)s64 | ((uint32_t)s32 << 16);
 }
@@ -164,11 +213,11 @@ __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double
 // Warm start for a new sample dtheta away from the stored sample `slot`:
 // real images advanced by z' dtheta, ghosts copied.
 __device__ __forceinline__ void warm_start(const WaveMem& m, int slot, double dtheta, c64 r[5]) {
-  const int n = m.meta[slot] & 7u;
+  const int n = meta_at(m, slot) & 7u;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    r[k] = ld_c(m.root, k * m.cap + slot);
-    if (k < n) r[k] = r[k] + dtheta * ld_c(m.dz, k * m.cap + slot);
+    r[k] = ld_root(m, k, slot);
+    if (k < n) r[k] = r[k] + dtheta * ld_dz(m, k, slot);
   }
 }
 
@@ -260,9 +309,9 @@ struct Piece {
 // E3 = |dA_p| dth^2 / 10, E4 = |dA_p1 - dA_p2|.
 __device__ __forceinline__ void add_link(const WaveMem& m, int sa, int ia, int sb, int ib,
                                          double par, double dth, Piece& out) {
-  const c64 za = ld_c(m.root, ia * m.cap + sa), zb = ld_c(m.root, ib * m.cap + sb);
-  const c64 da = ld_c(m.dz, ia * m.cap + sa), db = ld_c(m.dz, ib * m.cap + sb);
-  const double wa = m.w[ia * m.cap + sa], wb = m.w[ib * m.cap + sb];
+  const c64 za = ld_root(m, ia, sa), zb = ld_root(m, ib, sb);
+  const c64 da = ld_dz(m, ia, sa), db = ld_dz(m, ib, sb);
+  const double wa = w_at(m, ia, sa), wb = w_at(m, ib, sb);
   const double dth2 = dth * dth, dth3 = dth2 * dth;
   const double dAt = 0.5 * cwedge(za, zb);
   const double dAp1 = (wa + wb) * dth3 * (1.0 / 24.0);
@@ -286,9 +335,9 @@ __device__ __forceinline__ void add_link(const WaveMem& m, int sa, int ia, int s
 // for creation along +theta), E3 = |dA_p| dth^2 / 10.
 __device__ __forceinline__ void add_cross(const WaveMem& m, int sc, int ip, int in, int kind,
                                           double dth, Piece& out) {
-  const c64 zp = ld_c(m.root, ip * m.cap + sc), zm = ld_c(m.root, in * m.cap + sc);
-  const c64 dp = ld_c(m.dz, ip * m.cap + sc), dm = ld_c(m.dz, in * m.cap + sc);
-  const double wp = m.w[ip * m.cap + sc], wm = m.w[in * m.cap + sc];
+  const c64 zp = ld_root(m, ip, sc), zm = ld_root(m, in, sc);
+  const c64 dp = ld_dz(m, ip, sc), dm = ld_dz(m, in, sc);
+  const double wp = w_at(m, ip, sc), wm = w_at(m, in, sc);
   const double dd = sqrt(fabs(cdot(dp, dm)));
   const double sep = cabs64(zp - zm);
   const double dtt = sep / dd;
@@ -309,12 +358,12 @@ __device__ __forceinline__ void add_cross(const WaveMem& m, int sc, int ip, int 
 __device__ __attribute__((noinline)) Piece interval_piece_any(const WaveMem& m, int sa, int sb,
                                                               double dth) {
   c64 za[5], zb[5];
-  const uint32_t ma_ = m.meta[sa], mb_ = m.meta[sb];
+  const uint32_t ma_ = meta_at(m, sa), mb_ = meta_at(m, sb);
   const int na_ = ma_ & 7u, nb_ = mb_ & 7u;
   const uint32_t para = (ma_ >> 3) & 31u, parb = (mb_ >> 3) & 31u;
   for (int k = 0; k < 5; ++k) {
-    za[k] = ld_c(m.root, k * m.cap + sa);
-    zb[k] = ld_c(m.root, k * m.cap + sb);
+    za[k] = ld_root(m, k, sa);
+    zb[k] = ld_root(m, k, sb);
   }
   int pa[5], ma[5], pb[5], mb[5];
   int npa = 0, nma = 0, npb = 0, nmb = 0;
@@ -369,7 +418,7 @@ __device__ __attribute__((noinline)) Piece interval_piece_any(const WaveMem& m, 
 // are linked with static list positions; image data are read from the
 // (cached) sample records with computed offsets.
 __device__ inline Piece interval_piece(const WaveMem& m, int sa, int sb, double dth) {
-  const uint32_t ma_ = m.meta[sa], mb_ = m.meta[sb];
+  const uint32_t ma_ = meta_at(m, sa), mb_ = meta_at(m, sb);
   const int na = ma_ & 7u, nb = mb_ & 7u;
   const uint32_t para = (ma_ >> 3) & 31u, parb = (mb_ >> 3) & 31u;
   const bool stda = (na == 3 && para == 1u) || (na == 5 && para == 3u);
@@ -378,8 +427,8 @@ __device__ inline Piece interval_piece(const WaveMem& m, int sa, int sb, double 
   c64 za[5], zb[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    za[k] = ld_c(m.root, k * m.cap + sa);
-    zb[k] = ld_c(m.root, k * m.cap + sb);
+    za[k] = ld_root(m, k, sa);
+    zb[k] = ld_root(m, k, sb);
   }
   Piece out{0.0, 0.0, na != nb ? (uint32_t)IF_COUNT : 0u};
   if (na == 3 && nb == 3) {
@@ -416,12 +465,44 @@ __device__ inline Piece interval_piece(const WaveMem& m, int sa, int sb, double 
 }
 
 // ---------------------------------------------------------------- wave ops
-__device__ __forceinline__ double wave_incl_scan(double v, int lane) {
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const double t = __shfl_up(v, o);
-    if (lane >= o) v += t;
-  }
+// Cross-lane steps use DPP lane moves (row shifts and row broadcasts
+// inside the VALU) rather than LDS-routed permutes: a 64-lane scan is four
+// row_shr steps (1, 2, 4, 8: Hillis-Steele inside each 16-lane row) and two
+// row broadcasts (lane 15 of a row into the next row, lane 31 into rows 2
+// and 3).  Doubles move as two 32-bit halves.
+template <int CTRL, int ROWS, bool ZERO>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xF, ZERO);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF, ZERO);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <int CTRL, int ROWS, bool ZERO>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, ZERO);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Value of the previous lane (lane 0 gets 0).
+__device__ __forceinline__ double prev_lane(double v) { return dpp_f64<0x138, 0xF, true>(v); }
+__device__ __forceinline__ int prev_lane(int v) {
+  return (int)dpp_u32<0x138, 0xF, true>((uint32_t)v);
+}
+
+__device__ __forceinline__ double wave_incl_scan(double v, int) {
+  v += dpp_f64<0x111, 0xF, true>(v);
+  v += dpp_f64<0x112, 0xF, true>(v);
+  v += dpp_f64<0x114, 0xF, true>(v);
+  v += dpp_f64<0x118, 0xF, true>(v);
+  v += dpp_f64<0x142, 0xA, false>(v);
+  v += dpp_f64<0x143, 0xC, false>(v);
   return v;
 }
 
@@ -432,29 +513,40 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
   e = (a - (s - bb)) + (b - bb);
 }
 
-// Wave-wide compensated sum of per-lane (hi, lo) partials; every lane gets
-// the same bits (the butterfly combines commutatively).
+template <int CTRL, int ROWS, bool ZERO>
+__device__ __forceinline__ void comp_step(double& hi, double& lo) {
+  const double h2 = dpp_f64<CTRL, ROWS, ZERO>(hi), l2 = dpp_f64<CTRL, ROWS, ZERO>(lo);
+  double s, e;
+  two_sum(hi, h2, s, e);
+  hi = s;
+  lo = lo + l2 + e;
+}
+
+// Wave-wide compensated sum of per-lane (hi, lo) partials by a compensated
+// scan; every lane receives the last lane's totals.
 __device__ __forceinline__ void wave_sum_comp(double& hi, double& lo) {
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const double h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
-    double s, e;
-    two_sum(hi, h2, s, e);
-    hi = s;
-    lo = lo + l2 + e;
-  }
+  comp_step<0x111, 0xF, true>(hi, lo);
+  comp_step<0x112, 0xF, true>(hi, lo);
+  comp_step<0x114, 0xF, true>(hi, lo);
+  comp_step<0x118, 0xF, true>(hi, lo);
+  comp_step<0x142, 0xA, false>(hi, lo);
+  comp_step<0x143, 0xC, false>(hi, lo);
+  hi = readlane_f64(hi, WAVE - 1);
+  lo = readlane_f64(lo, WAVE - 1);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) v += __shfl_xor(v, o);
-  return v;
+  return readlane_f64(wave_incl_scan(v, 0), WAVE - 1);
 }
 
 __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) v |= __shfl_xor(v, o);
-  return v;
+  v |= dpp_u32<0x111, 0xF, true>(v);
+  v |= dpp_u32<0x112, 0xF, true>(v);
+  v |= dpp_u32<0x114, 0xF, true>(v);
+  v |= dpp_u32<0x118, 0xF, true>(v);
+  v |= dpp_u32<0x142, 0xA, false>(v);
+  v |= dpp_u32<0x143, 0xC, false>(v);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, WAVE - 1);
 }
 
 // ---------------------------------------------------------------- engine
@@ -496,7 +588,7 @@ __device__ __forceinline__ Piece relink(const WaveMem& m, const Sorted& S, int p
   const int sa = S.sl[p], sb = S.sl[q];
   const double dth = (p + 1 < N ? S.th[q] : S.th[q] + TWO_PI) - S.th[p];
   const Piece pc = interval_piece(m, sa, sb, dth);
-  m.dA[sa] = pc.dA;
+  dA_at(m, sa) = pc.dA;
   S.E[p] = pc.E;
   return pc;
 }
@@ -512,14 +604,14 @@ __device__ inline void permute_record(const WaveMem& m, int slot, const int* fro
   double w[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    z[k] = ld_c(m.root, k * m.cap + slot);
-    d[k] = ld_c(m.dz, k * m.cap + slot);
-    w[k] = m.w[k * m.cap + slot];
+    z[k] = ld_root(m, k, slot);
+    d[k] = ld_dz(m, k, slot);
+    w[k] = w_at(m, k, slot);
   }
   for (int k = 0; k < 5; ++k) {
-    st_c(m.root, k * m.cap + slot, z[from[k]]);
-    st_c(m.dz, k * m.cap + slot, d[from[k]]);
-    m.w[k * m.cap + slot] = w[from[k]];
+    st_root(m, k, slot, z[from[k]]);
+    st_dz(m, k, slot, d[from[k]]);
+    w_at(m, k, slot) = w[from[k]];
   }
 }
 
@@ -529,13 +621,13 @@ __device__ inline void demote(const WaveMem& m, int slot, int cp, int cn) {
   for (int k = 2; k < 5; ++k)
     if (k != cn) from[t++] = k;
   permute_record(m, slot, from);
-  const uint32_t mt = m.meta[slot];
-  m.meta[slot] = 3u | (1u << 3) | (mt & 0xFF00u) | M_DEMOTED | ((uint32_t)cp << 17) |
+  const uint32_t mt = meta_at(m, slot);
+  meta_at(m, slot) = 3u | (1u << 3) | (mt & 0xFF00u) | M_DEMOTED | ((uint32_t)cp << 17) |
                  ((uint32_t)cn << 20) | (mt & M_SUSPECT);
 }
 
 __device__ inline void undo_demotion(const WaveMem& m, int slot) {
-  const uint32_t mt = m.meta[slot];
+  const uint32_t mt = meta_at(m, slot);
   if (!(mt & M_DEMOTED)) return;
   const int cp = (mt >> 17) & 7u, cn = (mt >> 20) & 7u;
   // current position of each original image
@@ -547,7 +639,7 @@ __device__ inline void undo_demotion(const WaveMem& m, int slot) {
   for (int k = 2; k < 5; ++k)
     if (k != cn) from[k] = t++;
   permute_record(m, slot, from);
-  m.meta[slot] = 5u | (3u << 3) | (mt & 0xFF00u) | (mt & M_SUSPECT);
+  meta_at(m, slot) = 5u | (3u << 3) | (mt & 0xFF00u) | (mt & M_SUSPECT);
 }
 
 __device__ __forceinline__ bool standard5(uint32_t mt) {
@@ -562,12 +654,12 @@ __device__ __forceinline__ bool standard3(uint32_t mt) {
 // record positions of the unmatched + and - images at the five-image
 // sample, by the same least-distance linking as the area pieces.
 __device__ inline int pair_link(const WaveMem& m, int sa, int sb, int& cp, int& cn) {
-  const uint32_t ma = m.meta[sa], mb = m.meta[sb];
+  const uint32_t ma = meta_at(m, sa), mb = meta_at(m, sb);
   c64 za[5], zb[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    za[k] = ld_c(m.root, k * m.cap + sa);
-    zb[k] = ld_c(m.root, k * m.cap + sb);
+    za[k] = ld_root(m, k, sa);
+    zb[k] = ld_root(m, k, sb);
   }
   if (standard3(ma) && standard5(mb)) {
     const uint32_t p = inject_static<1, 2>(za, zb);
@@ -588,12 +680,12 @@ __device__ inline int pair_link(const WaveMem& m, int sa, int sb, int& cp, int& 
 
 // Follow the pair (cp, cn) of five-image sample s0 to five-image sample s1.
 __device__ inline bool follow_pair(const WaveMem& m, int s0, int s1, int& cp, int& cn) {
-  if (!standard5(m.meta[s0]) || !standard5(m.meta[s1])) return false;
+  if (!standard5(meta_at(m, s0)) || !standard5(meta_at(m, s1))) return false;
   c64 z0[5], z1[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    z0[k] = ld_c(m.root, k * m.cap + s0);
-    z1[k] = ld_c(m.root, k * m.cap + s1);
+    z0[k] = ld_root(m, k, s0);
+    z1[k] = ld_root(m, k, s1);
   }
   const uint32_t p = inject_static<2, 2>(z0, z1);
   const uint32_t n = inject_static<3, 3>(z0 + 2, z1 + 2);
@@ -613,7 +705,7 @@ __device__ inline bool perp_enough(c64 D, c64 G, c64 zref) {
 }
 
 __device__ __forceinline__ c64 root_at(const WaveMem& m, int slot, int k) {
-  return ld_c(m.root, k * m.cap + slot);
+  return ld_root(m, k, slot);
 }
 
 // From the three-image sample at sorted position kb, test the crossing into
@@ -628,7 +720,7 @@ __device__ inline int walk_run(const WaveMem& m, const Sorted& S, int N, int kb,
   const int j0 = from_start ? 0 : len - 1, dj = from_start ? 1 : -1;
   const int sb = S.sl[kb];
   const int sc = S.sl[(first + j0) % N];
-  const uint32_t mc = m.meta[sc];
+  const uint32_t mc = meta_at(m, sc);
   if (!(mc & M_SUSPECT) || (mc & M_DEMOTED)) return 0;
   int cp = 0, cn = 2;
   const int kind = from_start ? pair_link(m, sb, sc, cp, cn) : pair_link(m, sc, sb, cp, cn);
@@ -639,13 +731,13 @@ __device__ inline int walk_run(const WaveMem& m, const Sorted& S, int N, int kb,
   int demoted = 0;
   for (int j = j0; j >= 0 && j < len; j += dj) {
     const int sj = S.sl[(first + j) % N];
-    if (m.meta[sj] & M_DEMOTED) break;
+    if (meta_at(m, sj) & M_DEMOTED) break;
     bool more = false;
     int np = cp, nn = cn;
     const int jn = j + dj;
     if (jn >= 0 && jn < len) {
       const int sn = S.sl[(first + jn) % N];
-      const uint32_t mn = m.meta[sn];
+      const uint32_t mn = meta_at(m, sn);
       if ((mn & M_SUSPECT) && !(mn & M_DEMOTED) && follow_pair(m, sj, sn, np, nn))
         more = !perp_enough(root_at(m, sj, cp) - root_at(m, sj, cn),
                             root_at(m, sn, np) - root_at(m, sn, nn), root_at(m, sj, cp));
@@ -667,15 +759,15 @@ template <class Sorted>
 __device__ inline int detect_runs(const WaveMem& m, const Sorted& S, int N) {
   int anchor = -1;
   for (int i = 0; i < N; ++i)
-    if (orig_n(m.meta[S.sl[i]]) == 3) { anchor = i; break; }
+    if (orig_n(meta_at(m, S.sl[i])) == 3) { anchor = i; break; }
   if (anchor < 0) return 0;
   int changed = 0;
   int i = 0;
   while (i < N) {
-    if (orig_n(m.meta[S.sl[(anchor + i) % N]]) != 5) { ++i; continue; }
+    if (orig_n(meta_at(m, S.sl[(anchor + i) % N])) != 5) { ++i; continue; }
     const int start = i;
     int len = 0;
-    while (i < N && orig_n(m.meta[S.sl[(anchor + i) % N]]) == 5) { ++len; ++i; }
+    while (i < N && orig_n(meta_at(m, S.sl[(anchor + i) % N])) == 5) { ++len; ++i; }
     const int first = (anchor + start) % N;
     changed += walk_run(m, S, N, (anchor + start - 1 + N) % N, first, len, true);
     changed += walk_run(m, S, N, (anchor + start + len) % N, first, len, false);
@@ -694,7 +786,7 @@ __device__ __attribute__((noinline)) bool slope_pass(const WaveMem& m, const Sor
   __syncthreads();
   int changed = 0;
   if (lane == 0) changed = detect_runs(m, S, N);
-  changed = __shfl(changed, 0);
+  changed = __builtin_amdgcn_readlane(changed, 0);
   __syncthreads();
   double h = 0.0, l = 0.0;
   for (int p = lane; p < N; p += WAVE) {
@@ -737,10 +829,12 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
                                           const WaveMem& m, FsLds<LCAP>& L, const Sorted& S,
                                           int lane, int n0, FsState& st) {
   const double rho = T.rho;
-  int& N = st.N;
-  double &Ahi = st.Ahi, &Alo = st.Alo, &A = st.A, &E = st.E;
-  uint32_t &fl = st.fl, &sw32 = st.sw32, &sw64 = st.sw64, &nint = st.nint;
-  bool& suspects = st.suspects;
+  // state in locals (written back once) so that it stays in registers
+  int N = st.N;
+  double Ahi = st.Ahi, Alo = st.Alo, A = st.A, E = st.E;
+  uint32_t fl = st.fl, sw32 = st.sw32, sw64 = st.sw64, nint = st.nint;
+  bool suspects = st.suspects;
+  bool outgrown = false;
   // One round per iteration.  The first n0 samples form the uniform grid
   // theta = 2 pi i / n0, laid down 64 at a time: round r adds the phase
   // offset r / (n0 / 64) of the base grid theta_j = 2 pi j / 64 (whose
@@ -776,7 +870,10 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
       E = wave_sum(es);
       if (E <= tol * fabs(A)) break;
       // outgrowing the LDS copy: the caller continues in global memory
-      if (N + NNEW > S.cap && S.cap < METHOD_CAP) return false;
+      if (N + NNEW > S.cap && S.cap < METHOD_CAP) {
+        outgrown = true;
+        break;
+      }
       const int nnew = N + NNEW <= S.cap ? NNEW : S.cap - N;
       if (nnew <= 0) { fl |= F_CAP; break; }
       const double W = wave_sum(ws);
@@ -791,7 +888,7 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
         const int p = base + lane;
         const double w = p < N ? fmax(S.E[p] - avg, 0.0) : 0.0;
         const double inc = wave_incl_scan(w, lane);
-        const double tot = __shfl(inc, WAVE - 1);
+        const double tot = readlane_f64(inc, WAVE - 1);
         const bool mine = !found && lane < nnew && u < carry + tot;
         if (__ballot(mine)) {
           int lo = 0;  // first strip position whose inclusive sum exceeds u
@@ -819,8 +916,8 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
         thn = ta + (u - w0) / wi * (tb - ta);
         valid = wi > 0.0 && thn > ta && thn < tb;
       }
-      const int piv = __shfl_up(iv, 1);
-      const double pth = __shfl_up(thn, 1);
+      const int piv = prev_lane(iv);
+      const double pth = prev_lane(thn);
       if (lane > 0 && valid && piv == iv && !(thn > pth)) valid = false;
       const uint64_t mask = __ballot(valid);
       mcount = __popcll(mask);
@@ -863,7 +960,7 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
           const int v = __shfl(myivl, sh + step - 1);
           if (v < p) sh += step;
         }
-        if (__shfl(myivl, WAVE - 1) < p) sh = WAVE;  // lifting alone stops at 63
+        if (__builtin_amdgcn_readlane(myivl, WAVE - 1) < p) sh = WAVE;  // lifting alone stops at 63
         double vt = 0.0, ve = 0.0;
         uint16_t vs = 0;
         if (p < N) {
@@ -886,7 +983,7 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
     if (valid) {
       P = N == 0 ? lane : iv + 1 + rank;
       first = N > 0 && (rank == 0 || L.ivl[rank - 1] != iv);
-      if (first) dAold = m.dA[S.sl[P - 1]];
+      if (first) dAold = dA_at(m, S.sl[P - 1]);
     }
     __syncthreads();
     if (valid) {
@@ -928,7 +1025,8 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
     __syncthreads();
     if (suspects && slope_pass(m, S, N, lane, &Ahi, &Alo, &nint)) fl |= F_SLOPE;
   }
-  return true;
+  st = FsState{N, Ahi, Alo, A, E, fl, sw32, sw64, nint, suspects};
+  return !outgrown;
 }
 
 // Continuation of a source that outgrew its LDS copy (rare: kept out of line).

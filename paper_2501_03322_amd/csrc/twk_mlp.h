@@ -85,7 +85,7 @@ __global__ __launch_bounds__(64) void k_pack(const float* __restrict__ P, bf16x8
 
 // ---------------------------------------------------------------- inference
 constexpr int ACT_LD = HID + 8;  // row stride of the activation staging (bf16)
-constexpr int INFER_WAVES = 4;
+constexpr int INFER_WAVES = 8;  // waves per block sharing one LDS copy of the weights
 
 // Bias, GELU, round to bf16 and stage one 32 x 128 activation tile in LDS.
 __device__ inline void stage(__bf16 (*act)[ACT_LD], const f32x16* acc, const float* __restrict__ b,
@@ -117,8 +117,8 @@ __device__ inline void hidden(__bf16 (*act)[ACT_LD], const bf16x8* __restrict__ 
 
 // One wave per 32-row tile, tiles taken in a grid-stride loop; the packed
 // weights sit in LDS for the whole block, activations never leave LDS.
-// feat: [n x 8] float32 (raw features); out: [n x 2] float32.  When order is
-// given, row i of the input is row order[i] of feat/out.
+// feat: [n x 8] float32 (raw features); out: [n x 2] float32; the row count
+// is n, or *n_dev when given (a device-side count of queued tasks).
 __global__ __launch_bounds__(64 * INFER_WAVES) void k_infer(const float* __restrict__ P,
                                                              const bf16x8* __restrict__ frag,
                                                              int64_t n, const long long* __restrict__ n_dev,

@@ -65,3 +65,31 @@ inline unsigned long long __ballot(int pred) {
 }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline int __ffsll(unsigned long long x) { return __builtin_ffsll((long long)x); }
+
+// DPP lane moves of one 32-bit value (the controls the engine uses:
+// row_shr:1..15, row_bcast:15, row_bcast:31, wave_shr:1).  Lanes of rows or
+// banks outside the masks keep `old`; lanes whose source does not exist get
+// 0 with bound_ctrl, else `old`.
+inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask,
+                                       bool bound_ctrl) {
+  const int l = hip_emu::t_lane, row = l >> 4, lr = l & 15;
+  int from = -1;
+  if (ctrl >= 0x111 && ctrl <= 0x11F) {
+    const int k = ctrl - 0x110;
+    from = lr >= k ? l - k : -1;
+  } else if (ctrl == 0x142) {
+    from = row >= 1 ? row * 16 - 1 : -1;
+  } else if (ctrl == 0x143) {
+    from = row >= 2 ? 31 : -1;
+  } else if (ctrl == 0x138) {
+    from = l >= 1 ? l - 1 : -1;
+  } else {
+    __builtin_trap();  // control not modelled
+  }
+  const int v = __hip_emu_exchange(src, from >= 0 ? from : l);
+  const bool on = ((row_mask >> row) & 1) && ((bank_mask >> (lr >> 2)) & 1);
+  if (!on) return old;
+  if (from < 0) return bound_ctrl ? 0 : old;
+  return v;
+}
+inline int __builtin_amdgcn_readlane(int v, int lane) { return __hip_emu_exchange(v, lane); }

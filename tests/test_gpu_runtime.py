@@ -65,6 +65,12 @@ def test_graph_replay_bitwise(lc):
             assert torch.equal(got[0], ref2[0])
             stats = ctx.stats()
             assert stats["fs_tasks"] == int(((ref2[3] & 1) == 0).sum().item())
+        # timing a replayed call: whole-call time only
+        ctx.enable_timing(True)
+        _run(ctx, args, twk.MODE_MIXED, tol=3e-4)
+        kt = ctx.kernel_times()
+        assert kt["total_ms"] > 0 and kt["fs_ms"] < 0.05 * kt["total_ms"]
+        ctx.enable_timing(False)
     ctx.close()
 
 
