@@ -155,27 +155,25 @@ int twk_kernel_times(twk_ctx *ctx, double *ms5);
 typedef struct {
   int32_t waves_per_cu; /* resident contour waves per CU: the persistent grid is
                            waves_per_cu x CUs; 1 .. the occupancy limit of lds_cap */
-  int32_t lds_cap;      /* limb samples a source keeps in LDS before continuing in
-                           global memory: 256, 512 or 1024 */
+  int32_t lds_cap;      /* limb samples a source keeps in LDS (sorted arrays and
+                           sample records) before continuing in global memory:
+                           64, 128 or 256 */
   float budget_shift;   /* learned path: starting grid from 2^(predicted log2 N -
                            budget_shift), in [-2, 4] */
   int32_t graphs;       /* 1: capture each call's launch sequence in a hipGraph and
                            replay it when an identical call (same arguments and
                            pointers) repeats; needs a created (non-null) stream */
-  int32_t rec_cap;      /* sample records a source keeps in LDS (the rest go to
-                           global memory): 0 .. 512, a multiple of 16 */
 } twk_tuning;
 
-/* Current tuning (defaults: the occupancy limit at lds_cap 512, records in
- * global memory, shift 1, no graphs). */
+/* Current tuning (defaults: the occupancy limit at lds_cap 128, shift 1, no
+ * graphs). */
 int twk_get_tuning(twk_ctx *ctx, twk_tuning *out);
 /* Set the tuning; synchronises the stream and drops captured graphs.
  * TWK_EINVAL for values out of range (graphs on a null stream included). */
 int twk_set_tuning(twk_ctx *ctx, const twk_tuning *t);
 /* Autotuner: times twk_lightcurves on this batch (a representative sample
- * of the workload; arguments as for twk_lightcurves) for every LDS capacity,
- * record capacities 0/64/128/192 and four persistent grid sizes each, then,
- * with TWK_MODE_MLP, six budget
+ * of the workload; arguments as for twk_lightcurves) for every LDS capacity
+ * and four persistent grid sizes each, then, with TWK_MODE_MLP, six budget
  * shifts, taking the fastest of `trials` (1..100) calls per candidate; the
  * best tuning is left in the context (graphs setting unchanged) and copied
  * to *best (may be NULL).  Synchronous; allocates its own output buffers. */

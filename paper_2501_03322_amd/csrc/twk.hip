@@ -33,9 +33,10 @@ using namespace twk;
 
 namespace {
 
-// Limb samples a source keeps in LDS before spilling to global memory: one
-// persistent-kernel instantiation per choice; the tuning picks one.
-constexpr int LDS_CAPS[3] = {256, 512, 1024};
+// Limb samples a source keeps in LDS (sorted arrays and sample records)
+// before continuing in global memory: one persistent-kernel instantiation
+// per choice; the tuning picks one.
+constexpr int LDS_CAPS[3] = {64, 128, 256};
 constexpr int BUDGET_MAX = 512;  // largest learned starting grid
 
 // Counters in device memory (int64 each).
@@ -482,8 +483,6 @@ __global__ __launch_bounds__(256) void k_place(long long* cnt, const float* out,
 // Persistent finite-source kernel: each wave pops tasks until the queue is
 // drained (every wave reaches the exit: the queue length is fixed before
 // launch and each pop advances the head).
-// The first rcap sample records of each source live in the block's dynamic
-// LDS (rcap * kRecBytes bytes, given at launch).
 template <int LCAP, bool MIXED>
 #ifndef TWK_FS_WAVES_PER_EU
 #define TWK_FS_WAVES_PER_EU 2
@@ -491,11 +490,10 @@ template <int LCAP, bool MIXED>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES_PER_EU))) void k_fs(
     const Task* tasks, const long long* ntask, long long* head, double tol, char* scratch,
     double* mag, double* err, int32_t* ns, uint32_t* flags, long long* cnt, const int32_t* order,
-    const int32_t* tn0, int rcap) {
+    const int32_t* tn0) {
   __shared__ FsLds<LCAP> lds;
-  extern __shared__ __attribute__((aligned(16))) char rec_lds[];
   const int lane = threadIdx.x;
-  const WaveMem m = wave_mem(scratch, blockIdx.x, rcap > 0 ? rec_lds : nullptr, rcap);
+  const WaveMem m = wave_mem(scratch, blockIdx.x);
   const long long n = *ntask;
   for (;;) {
     long long t = 0;
@@ -544,7 +542,7 @@ struct twk_ctx {
   bool timing = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   // launch tuning of the contour stage, and graph replay
-  twk_tuning tune{0, 512, 1.0f, 0, 0};
+  twk_tuning tune{0, 128, 1.0f, 0};
   bool capturing = false;  // no event marks inside a capture
   // captured launch sequences (replayed when a call repeats)
   struct Graph {
@@ -609,27 +607,22 @@ int grow(twk_ctx* c, void** p, size_t* have, size_t need) {
   return TWK_OK;
 }
 
-size_t rec_bytes(int rcap) { return (size_t)rcap * kRecBytes; }
-
 template <int LCAP>
-hipError_t occupancy(int rcap, int* blocks) {
+hipError_t occupancy(int* blocks) {
   int b1 = 0, b2 = 0;
-  hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fs<LCAP, false>, 64, rec_bytes(rcap));
-  if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fs<LCAP, true>, 64, rec_bytes(rcap));
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fs<LCAP, false>, 64, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fs<LCAP, true>, 64, 0);
   *blocks = std::min(b1, b2);
   return e;
 }
 
-// Waves per CU the hardware allows for an LDS capacity and a record
-// capacity (0 if the combination does not fit).
-int max_waves(int lds_cap, int rcap, int* out) {
+// Waves per CU the hardware allows for an LDS capacity.
+int max_waves(int lds_cap, int* out) {
   hipError_t e;
   switch (lds_cap) {
-    case 256: e = occupancy<256>(rcap, out); break;
-    case 1024: e = occupancy<1024>(rcap, out); break;
-    default: e = occupancy<512>(rcap, out); break;
+    case 64: e = occupancy<64>(out); break;
+    case 256: e = occupancy<256>(out); break;
+    default: e = occupancy<128>(out); break;
   }
   return e == hipSuccess ? TWK_OK : TWK_EDEVICE;
 }
@@ -729,13 +722,13 @@ template <int LCAP>
 void launch_fs_cap(twk_ctx* c, bool mixed, double tol, double* mag, double* err, int32_t* ns,
                    uint32_t* flags, const int32_t* order, const int32_t* n0) {
   if (mixed)
-    hipLaunchKernelGGL((k_fs<LCAP, true>), dim3(c->waves), dim3(64), rec_bytes(c->tune.rec_cap),
-                       c->stream, c->tasks, &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch,
-                       mag, err, ns, flags, c->cnt, order, n0, (int)c->tune.rec_cap);
+    hipLaunchKernelGGL((k_fs<LCAP, true>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
+                       &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
+                       c->cnt, order, n0);
   else
-    hipLaunchKernelGGL((k_fs<LCAP, false>), dim3(c->waves), dim3(64), rec_bytes(c->tune.rec_cap),
-                       c->stream, c->tasks, &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch,
-                       mag, err, ns, flags, c->cnt, order, n0, (int)c->tune.rec_cap);
+    hipLaunchKernelGGL((k_fs<LCAP, false>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
+                       &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
+                       c->cnt, order, n0);
 }
 
 int launch_fs(twk_ctx* c, bool mixed, bool learned, double tol, double* mag, double* err,
@@ -743,9 +736,9 @@ int launch_fs(twk_ctx* c, bool mixed, bool learned, double tol, double* mag, dou
   const int32_t* order = learned ? learn_bufs(c).order : nullptr;
   const int32_t* n0 = learned ? learn_bufs(c).n0 : nullptr;
   switch (c->tune.lds_cap) {
+    case 64: launch_fs_cap<64>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
     case 256: launch_fs_cap<256>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
-    case 1024: launch_fs_cap<1024>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
-    default: launch_fs_cap<512>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
+    default: launch_fs_cap<128>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
   }
   HIP_TRY(c, hipGetLastError());
   return TWK_OK;
@@ -801,7 +794,7 @@ int twk_create(twk_ctx** out, int device, void* stream) {
   }
   c->n_cu = prop.multiProcessorCount;
   int wpc = 0;
-  if (max_waves(512, 0, &wpc) != TWK_OK || wpc < 1) {
+  if (max_waves(128, &wpc) != TWK_OK || wpc < 1) {
     delete c;
     return TWK_EDEVICE;
   }
@@ -886,7 +879,7 @@ CallKey& tuning_key(CallKey& k, const twk_ctx* c) {
   uint32_t sh;
   std::memcpy(&sh, &c->tune.budget_shift, 4);
   return k.u((uint64_t)c->tune.waves_per_cu | ((uint64_t)c->tune.lds_cap << 20) |
-             ((uint64_t)sh << 32)).u((uint64_t)c->tune.rec_cap);
+             ((uint64_t)sh << 32));
 }
 
 // Issue the launch sequence of a call, or, with graph replay on, replay
@@ -1535,12 +1528,12 @@ int twk_get_tuning(twk_ctx* c, twk_tuning* out) {
 
 int twk_set_tuning(twk_ctx* c, const twk_tuning* t) {
   if (!c || !t) return TWK_EINVAL;
-  if (cap_index(t->lds_cap) < 0 || t->rec_cap < 0 || t->rec_cap > 512 || t->rec_cap % 16 ||
-      !(t->budget_shift >= -2.0f && t->budget_shift <= 4.0f) || (t->graphs != 0 && t->graphs != 1))
+  if (cap_index(t->lds_cap) < 0 || !(t->budget_shift >= -2.0f && t->budget_shift <= 4.0f) ||
+      (t->graphs != 0 && t->graphs != 1))
     return TWK_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
   int mx = 0;
-  if (max_waves(t->lds_cap, t->rec_cap, &mx) != TWK_OK) return TWK_EDEVICE;
+  if (max_waves(t->lds_cap, &mx) != TWK_OK) return TWK_EDEVICE;
   if (t->waves_per_cu < 1 || t->waves_per_cu > mx) return TWK_EINVAL;
   // capture needs a created stream (the legacy null stream cannot be captured)
   if (t->graphs && c->stream == nullptr) return TWK_EINVAL;
@@ -1601,28 +1594,24 @@ int twk_autotune(twk_ctx* c, int64_t nsets, const double* s, const double* q, co
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     rc = hip_fail(c, hipGetLastError());
   } else {
-    // persistent grid, LDS capacity of the sorted arrays and of the sample
-    // records, then (learned path) the budget shift
-    const int rcaps[4] = {0, 64, 128, 192};
-    for (int ci = 0; ci < 3 && rc == TWK_OK; ++ci)
-      for (int ri = 0; ri < 4 && rc == TWK_OK; ++ri) {
-        int mx = 0;
-        if ((rc = max_waves(LDS_CAPS[ci], rcaps[ri], &mx)) != TWK_OK) break;
-        int last = 0;
-        for (int f = 1; f <= 4 && rc == TWK_OK && mx > 0; ++f) {
-          const int w = std::max(1, (mx * f) / 4);
-          if (w == last) continue;
-          last = w;
-          cur.lds_cap = LDS_CAPS[ci];
-          cur.rec_cap = rcaps[ri];
-          cur.waves_per_cu = w;
-          double ms;
-          if ((rc = measure(cur, &ms)) == TWK_OK && ms < best_ms) {
-            best_ms = ms;
-            top = cur;
-          }
+    // persistent grid and LDS capacity, then (learned path) the budget shift
+    for (int ci = 0; ci < 3 && rc == TWK_OK; ++ci) {
+      int mx = 0;
+      if ((rc = max_waves(LDS_CAPS[ci], &mx)) != TWK_OK) break;
+      int last = 0;
+      for (int f = 1; f <= 4 && rc == TWK_OK && mx > 0; ++f) {
+        const int w = std::max(1, (mx * f) / 4);
+        if (w == last) continue;
+        last = w;
+        cur.lds_cap = LDS_CAPS[ci];
+        cur.waves_per_cu = w;
+        double ms;
+        if ((rc = measure(cur, &ms)) == TWK_OK && ms < best_ms) {
+          best_ms = ms;
+          top = cur;
         }
       }
+    }
     if (rc == TWK_OK && (mode & TWK_MODE_MLP)) {
       const float shifts[6] = {0.0f, 0.5f, 1.0f, 1.5f, 2.0f, 3.0f};
       cur = top;

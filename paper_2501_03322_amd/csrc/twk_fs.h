@@ -59,56 +59,50 @@ typedef TWK_LDS_AS uint16_t luint16;
 // Sample records, SoA over slots (slot = creation order): five roots
 // (positive, negative real images, ghost pair) as (re, im), five z' as
 // (re, im), five z' ^ z'', the area of the interval starting at the slot,
-// and the meta word.  The first rcap slots of a source live in LDS, the rest
-// in the wave's slice of global scratch; accessors pick the region per slot
-// (generic pointers), so a source that fits never leaves the CU.
-struct RecArr {
-  double* root;    // [5][cap][2]
-  double* dz;      // [5][cap][2]
-  double* w;       // [5][cap]
-  double* dA;      // [cap]
-  uint32_t* meta;  // [cap]
+// and the meta word.  A record view addresses them either in LDS (RecL: the
+// wave's LDS copy, for sources that fit) or in the wave's slice of global
+// memory (RecG: sources that outgrew LDS); every function on records is a
+// template on the view, so LDS-resident sources use LDS instructions only.
+template <class D, class U>
+struct RecView {
+  D* root;  // [5][cap][2]
+  D* dz;    // [5][cap][2]
+  D* w;     // [5][cap]
+  D* dA;    // [cap]
+  U* meta;  // [cap]
   int cap;
 };
+typedef TWK_LDS_AS uint32_t luint32;
+typedef TWK_GLOBAL_AS uint32_t guint32;
+typedef RecView<ldouble, luint32> RecL;
+typedef RecView<gdouble, guint32> RecG;
 
 constexpr size_t kRecBytes = 5 * 16 + 5 * 16 + 5 * 8 + 8 + 4;  // 212 per slot
 
+// The wave's slice of global scratch: records of every slot plus the
+// sorted-array spill copies.
 struct WaveMem {
-  RecArr L;      // slots [0, rcap) in LDS
-  RecArr G;      // slots [rcap, METHOD_CAP) in global memory (indexed by slot)
-  int rcap;
+  RecG G;
   gdouble* sth;  // sorted angles (spill copy)
   gdouble* sE;   // sorted interval errors (spill copy)
   guint16* ssl;  // sorted slots (spill copy)
 };
-
-// Global bytes per wave: records of every slot plus the sorted spill copies.
 constexpr size_t kSlotBytes = kRecBytes + 8 + 8 + 2;
 
-__device__ __forceinline__ RecArr carve(char* p, int cap) {
-  RecArr r;
-  r.cap = cap;
-  r.root = (double*)p;
-  p += (size_t)5 * cap * 16;
-  r.dz = (double*)p;
-  p += (size_t)5 * cap * 16;
-  r.w = (double*)p;
-  p += (size_t)5 * cap * 8;
-  r.dA = (double*)p;
-  p += (size_t)cap * 8;
-  r.meta = (uint32_t*)p;
-  return r;
-}
-
-// lds: the wave's LDS record area (rcap * kRecBytes bytes; may be null when
-// rcap = 0).
-__device__ __forceinline__ WaveMem wave_mem(char* base, int wave, char* lds, int rcap) {
+__device__ __forceinline__ WaveMem wave_mem(char* base, int wave) {
   char* p = base + (size_t)wave * (size_t)METHOD_CAP * kSlotBytes;
   WaveMem m;
-  m.rcap = rcap;
-  m.L = carve(lds, rcap);
-  m.G = carve(p, METHOD_CAP);
-  p += (size_t)METHOD_CAP * kRecBytes;
+  m.G.cap = METHOD_CAP;
+  m.G.root = (gdouble*)p;
+  p += (size_t)5 * METHOD_CAP * 16;
+  m.G.dz = (gdouble*)p;
+  p += (size_t)5 * METHOD_CAP * 16;
+  m.G.w = (gdouble*)p;
+  p += (size_t)5 * METHOD_CAP * 8;
+  m.G.dA = (gdouble*)p;
+  p += (size_t)METHOD_CAP * 8;
+  m.G.meta = (guint32*)p;
+  p += (size_t)METHOD_CAP * 4;
   m.sth = (gdouble*)p;
   p += (size_t)METHOD_CAP * 8;
   m.sE = (gdouble*)p;
@@ -117,43 +111,30 @@ __device__ __forceinline__ WaveMem wave_mem(char* base, int wave, char* lds, int
   return m;
 }
 
-__device__ __forceinline__ const RecArr& rec(const WaveMem& m, int slot) {
-  return slot < m.rcap ? m.L : m.G;
+template <class R>
+__device__ __forceinline__ c64 ld_root(const R& m, int k, int slot) {
+  return cz(m.root[2 * (k * m.cap + slot)], m.root[2 * (k * m.cap + slot) + 1]);
 }
-__device__ __forceinline__ c64 ld_root(const WaveMem& m, int k, int slot) {
-  const RecArr& r = rec(m, slot);
-  const double* q = r.root + 2 * (k * r.cap + slot);
-  return cz(q[0], q[1]);
+template <class R>
+__device__ __forceinline__ c64 ld_dz(const R& m, int k, int slot) {
+  return cz(m.dz[2 * (k * m.cap + slot)], m.dz[2 * (k * m.cap + slot) + 1]);
 }
-__device__ __forceinline__ c64 ld_dz(const WaveMem& m, int k, int slot) {
-  const RecArr& r = rec(m, slot);
-  const double* q = r.dz + 2 * (k * r.cap + slot);
-  return cz(q[0], q[1]);
+template <class R>
+__device__ __forceinline__ void st_root(const R& m, int k, int slot, c64 v) {
+  m.root[2 * (k * m.cap + slot)] = v.x;
+  m.root[2 * (k * m.cap + slot) + 1] = v.y;
 }
-__device__ __forceinline__ void st_root(const WaveMem& m, int k, int slot, c64 v) {
-  const RecArr& r = rec(m, slot);
-  double* q = r.root + 2 * (k * r.cap + slot);
-  q[0] = v.x;
-  q[1] = v.y;
+template <class R>
+__device__ __forceinline__ void st_dz(const R& m, int k, int slot, c64 v) {
+  m.dz[2 * (k * m.cap + slot)] = v.x;
+  m.dz[2 * (k * m.cap + slot) + 1] = v.y;
 }
-__device__ __forceinline__ void st_dz(const WaveMem& m, int k, int slot, c64 v) {
-  const RecArr& r = rec(m, slot);
-  double* q = r.dz + 2 * (k * r.cap + slot);
-  q[0] = v.x;
-  q[1] = v.y;
-}
-__device__ __forceinline__ double& w_at(const WaveMem& m, int k, int slot) {
-  const RecArr& r = rec(m, slot);
-  return r.w[k * r.cap + slot];
-}
-__device__ __forceinline__ double& dA_at(const WaveMem& m, int slot) {
-  const RecArr& r = rec(m, slot);
-  return r.dA[slot];
-}
-__device__ __forceinline__ uint32_t& meta_at(const WaveMem& m, int slot) {
-  const RecArr& r = rec(m, slot);
-  return r.meta[slot];
-}
+template <class R>
+__device__ __forceinline__ auto& w_at(const R& m, int k, int slot) { return m.w[k * m.cap + slot]; }
+template <class R>
+__device__ __forceinline__ auto& dA_at(const R& m, int slot) { return m.dA[slot]; }
+template <class R>
+__device__ __forceinline__ auto& meta_at(const R& m, int slot) { return m.meta[slot]; }
 
 // Interval flag bits
 enum : uint32_t { IF_CROSS = 1u, IF_ANOMALY = 2u, IF_COUNT = 4u };
@@ -176,9 +157,9 @@ constexpr double PAIR_FLOOR = 1e-7;
 // sample's roots advanced along their derivative; or the centre roots) and
 // write its record to `slot`.  Returns the root sweeps spent (low 16 bits
 // FP64, high 16 bits FP32) and the sample flags in *fl.
-template <bool MIXED>
+template <bool MIXED, class R>
 __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double theta, c64 r[5],
-                                       const WaveMem& m, int slot, uint32_t* fl) {
+                                       const R& m, int slot, uint32_t* fl) {
   double sn, cs;
   sincos(theta, &sn, &cs);
   const c64 y = yc + rho * cz(cs, sn);
@@ -212,7 +193,8 @@ __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double
 
 // Warm start for a new sample dtheta away from the stored sample `slot`:
 // real images advanced by z' dtheta, ghosts copied.
-__device__ __forceinline__ void warm_start(const WaveMem& m, int slot, double dtheta, c64 r[5]) {
+template <class R>
+__device__ __forceinline__ void warm_start(const R& m, int slot, double dtheta, c64 r[5]) {
   const int n = meta_at(m, slot) & 7u;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -307,7 +289,8 @@ struct Piece {
 //   dA_p1 = (w_a + w_b) dth^3 / 24,  dA_p2 = (z_b - z_a) ^ (z'_b - z'_a) dth / 12,
 // errors E1 = |w_a - w_b| dth^3/48, E2 = 1.5 |dA_p (|dz|^2/(dth^2 |z'_a.z'_b|) - 1)|,
 // E3 = |dA_p| dth^2 / 10, E4 = |dA_p1 - dA_p2|.
-__device__ __forceinline__ void add_link(const WaveMem& m, int sa, int ia, int sb, int ib,
+template <class R>
+__device__ __forceinline__ void add_link(const R& m, int sa, int ia, int sb, int ib,
                                          double par, double dth, Piece& out) {
   const c64 za = ld_root(m, ia, sa), zb = ld_root(m, ib, sb);
   const c64 da = ld_dz(m, ia, sa), db = ld_dz(m, ib, sb);
@@ -333,7 +316,8 @@ __device__ __forceinline__ void add_link(const WaveMem& m, int sa, int ia, int s
 // dtt = |z_+ - z_-| / sqrt|z'_+ . z'_-|; errors E1 = |w_+ + w_-| dtt^3/48,
 // E2 = 1.5 |(z_+ - z_-).(z'_+ - z'_-) -+ 2 |z_+ - z_-| sqrt|z'_+.z'_-|| dtt ("-"
 // for creation along +theta), E3 = |dA_p| dth^2 / 10.
-__device__ __forceinline__ void add_cross(const WaveMem& m, int sc, int ip, int in, int kind,
+template <class R>
+__device__ __forceinline__ void add_cross(const R& m, int sc, int ip, int in, int kind,
                                           double dth, Piece& out) {
   const c64 zp = ld_root(m, ip, sc), zm = ld_root(m, in, sc);
   const c64 dp = ld_dz(m, ip, sc), dm = ld_dz(m, in, sc);
@@ -355,7 +339,8 @@ __device__ __forceinline__ void add_cross(const WaveMem& m, int sc, int ip, int 
 
 // Image sets whose parity counts are not 1+2 or 2+3: general linking of
 // whatever same-parity images there are.
-__device__ __attribute__((noinline)) Piece interval_piece_any(const WaveMem& m, int sa, int sb,
+template <class R>
+__device__ __attribute__((noinline)) Piece interval_piece_any(const R& m, int sa, int sb,
                                                               double dth) {
   c64 za[5], zb[5];
   const uint32_t ma_ = meta_at(m, sa), mb_ = meta_at(m, sb);
@@ -417,7 +402,8 @@ __device__ __attribute__((noinline)) Piece interval_piece_any(const WaveMem& m, 
 // dth apart.  The four count patterns of a binary lens (3-3, 5-5, 3-5, 5-3)
 // are linked with static list positions; image data are read from the
 // (cached) sample records with computed offsets.
-__device__ inline Piece interval_piece(const WaveMem& m, int sa, int sb, double dth) {
+template <class R>
+__device__ inline Piece interval_piece(const R& m, int sa, int sb, double dth) {
   const uint32_t ma_ = meta_at(m, sa), mb_ = meta_at(m, sb);
   const int na = ma_ & 7u, nb = mb_ & 7u;
   const uint32_t para = (ma_ >> 3) & 31u, parb = (mb_ >> 3) & 31u;
@@ -553,6 +539,11 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 // LDS of one wave: the sorted arrays for sources of up to LCAP samples.
 template <int LCAP>
 struct FsLds {
+  double root[5 * LCAP * 2];  // records of the first LCAP slots (see RecView)
+  double dz[5 * LCAP * 2];
+  double w[5 * LCAP];
+  double dA[LCAP];
+  uint32_t meta[LCAP];
   double th[LCAP];    // sorted limb angles
   double E[LCAP];     // error of the interval starting at each sorted position
   uint16_t sl[LCAP];  // slot of each sorted position
@@ -582,8 +573,8 @@ struct FsOut {
 
 // Relink the interval starting at sorted position p (of N): area to the
 // global record of its left slot, error to the sorted arrays.
-template <class Sorted>
-__device__ __forceinline__ Piece relink(const WaveMem& m, const Sorted& S, int p, int N) {
+template <class Sorted, class R>
+__device__ __forceinline__ Piece relink(const R& m, const Sorted& S, int p, int N) {
   const int q = p + 1 < N ? p + 1 : 0;
   const int sa = S.sl[p], sb = S.sl[q];
   const double dth = (p + 1 < N ? S.th[q] : S.th[q] + TWO_PI) - S.th[p];
@@ -599,7 +590,8 @@ __device__ __forceinline__ Piece relink(const WaveMem& m, const Sorted& S, int p
 // demoted +, demoted -], remembering the pair so that the rewrite can be
 // undone (records are re-examined from scratch every round, as the samples
 // around a crossing change).
-__device__ inline void permute_record(const WaveMem& m, int slot, const int* from) {
+template <class R>
+__device__ inline void permute_record(const R& m, int slot, const int* from) {
   c64 z[5], d[5];
   double w[5];
 #pragma unroll
@@ -615,7 +607,8 @@ __device__ inline void permute_record(const WaveMem& m, int slot, const int* fro
   }
 }
 
-__device__ inline void demote(const WaveMem& m, int slot, int cp, int cn) {
+template <class R>
+__device__ inline void demote(const R& m, int slot, int cp, int cn) {
   int from[5] = {1 - cp, 0, 0, cp, cn};
   int t = 1;
   for (int k = 2; k < 5; ++k)
@@ -626,7 +619,8 @@ __device__ inline void demote(const WaveMem& m, int slot, int cp, int cn) {
                  ((uint32_t)cn << 20) | (mt & M_SUSPECT);
 }
 
-__device__ inline void undo_demotion(const WaveMem& m, int slot) {
+template <class R>
+__device__ inline void undo_demotion(const R& m, int slot) {
   const uint32_t mt = meta_at(m, slot);
   if (!(mt & M_DEMOTED)) return;
   const int cp = (mt >> 17) & 7u, cn = (mt >> 20) & 7u;
@@ -653,7 +647,8 @@ __device__ __forceinline__ bool standard3(uint32_t mt) {
 // b (3 -> 5), -1 if destroyed after a (5 -> 3), 0 otherwise; (cp, cn) are the
 // record positions of the unmatched + and - images at the five-image
 // sample, by the same least-distance linking as the area pieces.
-__device__ inline int pair_link(const WaveMem& m, int sa, int sb, int& cp, int& cn) {
+template <class R>
+__device__ inline int pair_link(const R& m, int sa, int sb, int& cp, int& cn) {
   const uint32_t ma = meta_at(m, sa), mb = meta_at(m, sb);
   c64 za[5], zb[5];
 #pragma unroll
@@ -679,7 +674,8 @@ __device__ inline int pair_link(const WaveMem& m, int sa, int sb, int& cp, int& 
 }
 
 // Follow the pair (cp, cn) of five-image sample s0 to five-image sample s1.
-__device__ inline bool follow_pair(const WaveMem& m, int s0, int s1, int& cp, int& cn) {
+template <class R>
+__device__ inline bool follow_pair(const R& m, int s0, int s1, int& cp, int& cn) {
   if (!standard5(meta_at(m, s0)) || !standard5(meta_at(m, s1))) return false;
   c64 z0[5], z1[5];
 #pragma unroll
@@ -704,7 +700,8 @@ __device__ inline bool perp_enough(c64 D, c64 G, c64 zref) {
   return fabs(cdot(D, G)) <= 0.70710678118654752 * a * b;
 }
 
-__device__ __forceinline__ c64 root_at(const WaveMem& m, int slot, int k) {
+template <class R>
+__device__ __forceinline__ c64 root_at(const R& m, int slot, int k) {
   return ld_root(m, k, slot);
 }
 
@@ -714,8 +711,8 @@ __device__ __forceinline__ c64 root_at(const WaveMem& m, int slot, int k) {
 // enough, walk into the run demoting suspect samples until consecutive
 // pair differences turn perpendicular (or the whole run is walked: the
 // piece is deleted).  Returns the number of samples demoted.
-template <class Sorted>
-__device__ inline int walk_run(const WaveMem& m, const Sorted& S, int N, int kb, int first, int len,
+template <class Sorted, class R>
+__device__ inline int walk_run(const R& m, const Sorted& S, int N, int kb, int first, int len,
                                bool from_start) {
   const int j0 = from_start ? 0 : len - 1, dj = from_start ? 1 : -1;
   const int sb = S.sl[kb];
@@ -755,8 +752,8 @@ __device__ __forceinline__ int orig_n(uint32_t mt) { return (mt & M_DEMOTED) ? 5
 
 // Runs of five-image samples between three-image ones, each examined from
 // both ends (serial; sources with suspect samples are rare).
-template <class Sorted>
-__device__ inline int detect_runs(const WaveMem& m, const Sorted& S, int N) {
+template <class Sorted, class R>
+__device__ inline int detect_runs(const R& m, const Sorted& S, int N) {
   int anchor = -1;
   for (int i = 0; i < N; ++i)
     if (orig_n(meta_at(m, S.sl[i])) == 3) { anchor = i; break; }
@@ -778,8 +775,8 @@ __device__ inline int detect_runs(const WaveMem& m, const Sorted& S, int N) {
 // Full slope-detector pass of one source: undo last round's demotions,
 // re-examine every run, relink every interval and recompute the area total
 // (compensated).  Returns true if any sample is demoted.
-template <class Sorted>
-__device__ __attribute__((noinline)) bool slope_pass(const WaveMem& m, const Sorted& S, int N,
+template <class Sorted, class R>
+__device__ __attribute__((noinline)) bool slope_pass(const R& m, const Sorted& S, int N,
                                                      int lane, double* Ahi, double* Alo,
                                                      uint32_t* nint) {
   for (int p = lane; p < N; p += WAVE) undo_demotion(m, p);
@@ -824,9 +821,9 @@ struct FsState {
 // when the source is finished, false when the next round would outgrow S
 // (only the LDS copy can be outgrown): the caller moves the sorted arrays to
 // the wave's global slice and continues there.
-template <int LCAP, bool MIXED, class Sorted>
+template <int LCAP, bool MIXED, class Sorted, class R>
 __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 yc, double tol,
-                                          const WaveMem& m, FsLds<LCAP>& L, const Sorted& S,
+                                          const R& m, FsLds<LCAP>& L, const Sorted& S,
                                           int lane, int n0, FsState& st) {
   const double rho = T.rho;
   // state in locals (written back once) so that it stays in registers
@@ -1029,9 +1026,9 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
   return !outgrown;
 }
 
-// Continuation of a source that outgrew its LDS copy (rare: kept out of line).
-// Arguments and state go by value so that nothing of the hot path has its
-// address taken.
+// Continuation of a source that outgrew its LDS copy (rare: kept out of
+// line).  Arguments and state go by value so that nothing of the hot path
+// has its address taken.
 template <int LCAP, bool MIXED>
 __device__ __attribute__((noinline)) FsState fs_rounds_spilled(Task T, double tol, WaveMem m,
                                                                FsLds<LCAP>& L, int lane,
@@ -1039,27 +1036,41 @@ __device__ __attribute__((noinline)) FsState fs_rounds_spilled(Task T, double to
   const Lens lens = make_lens(T.s, T.q);
   const c64 yc = cz(T.zx - lens.z2, T.zy);
   const SortedG S{m.sth, m.sE, m.ssl, METHOD_CAP};
-  fs_rounds<LCAP, MIXED>(T, lens, yc, tol, m, L, S, lane, 0, st);
+  fs_rounds<LCAP, MIXED>(T, lens, yc, tol, m.G, L, S, lane, 0, st);
   return st;
 }
 
+// One source: rounds on the LDS copies of the records and sorted arrays;
+// a source that would outgrow LDS has both copied to the wave's global
+// slice and continues there.
 template <int LCAP, bool MIXED>
-__device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& m, FsLds<LCAP>& L,
+__device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& gm, FsLds<LCAP>& L,
                            int lane, int n0) {
   const double tol = tol_stated * TOL_SAFETY;
   const Lens lens = make_lens(T.s, T.q);
   const c64 yc = cz(T.zx - lens.z2, T.zy);
   FsState st{0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, false};
   const SortedL S{(ldouble*)L.th, (ldouble*)L.E, (luint16*)L.sl, LCAP};
+  const RecL R{(ldouble*)L.root, (ldouble*)L.dz, (ldouble*)L.w, (ldouble*)L.dA,
+               (luint32*)L.meta, LCAP};
   bool spilled = false;
-  if (!fs_rounds<LCAP, MIXED>(T, lens, yc, tol, m, L, S, lane, n0, st)) {
+  if (!fs_rounds<LCAP, MIXED>(T, lens, yc, tol, R, L, S, lane, n0, st)) {
     for (int p = lane; p < st.N; p += WAVE) {
-      m.sth[p] = S.th[p];
-      m.sE[p] = S.E[p];
-      m.ssl[p] = S.sl[p];
+      gm.sth[p] = S.th[p];
+      gm.sE[p] = S.E[p];
+      gm.ssl[p] = S.sl[p];
+      // slot p's record (slots are 0 .. N-1)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        st_root(gm.G, k, p, ld_root(R, k, p));
+        st_dz(gm.G, k, p, ld_dz(R, k, p));
+        w_at(gm.G, k, p) = w_at(R, k, p);
+      }
+      dA_at(gm.G, p) = dA_at(R, p);
+      meta_at(gm.G, p) = meta_at(R, p);
     }
     __syncthreads();
-    st = fs_rounds_spilled<LCAP, MIXED>(T, tol, m, L, lane, st);
+    st = fs_rounds_spilled<LCAP, MIXED>(T, tol, gm, L, lane, st);
     spilled = true;
   }
   FsOut o;

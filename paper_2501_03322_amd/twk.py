@@ -49,7 +49,7 @@ class TrainCfg(C.Structure):
 class Tuning(C.Structure):
     """twk_tuning."""
     _fields_ = [("waves_per_cu", C.c_int32), ("lds_cap", C.c_int32), ("budget_shift", C.c_float),
-                ("graphs", C.c_int32), ("rec_cap", C.c_int32)]
+                ("graphs", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

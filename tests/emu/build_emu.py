@@ -9,12 +9,16 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libengine_emu.so")
 
 
-def build(kgap=None) -> str:
+def build(kgap=None, lcap=None) -> str:
     """kgap: override of the residual detector's gap factor (a blinded
-    detector exercises the slope detector)."""
+    detector exercises the slope detector); lcap: LDS capacity of the
+    emulated engine (default 512)."""
     os.makedirs(OUT_DIR, exist_ok=True)
-    lib = LIB if kgap is None else os.path.join(OUT_DIR, f"libengine_emu_kgap{kgap:g}.so")
-    defs = [] if kgap is None else [f"-DTWK_KGAP={kgap!r}"]
+    name = "libengine_emu" + ("" if kgap is None else f"_kgap{kgap:g}") + \
+        ("" if lcap is None else f"_lcap{lcap}") + ".so"
+    lib = os.path.join(OUT_DIR, name)
+    defs = ([] if kgap is None else [f"-DTWK_KGAP={kgap!r}"]) + \
+        ([] if lcap is None else [f"-DEMU_LCAP={int(lcap)}"])
     cmd = ["g++", "-std=c++20", "-O2", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
            "-I", os.path.join(HERE, "include")] + defs + ["-o", lib + ".tmp",
                                                         os.path.join(HERE, "engine_emu.cpp")]

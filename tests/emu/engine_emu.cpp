@@ -12,12 +12,14 @@
 using namespace twk;
 
 namespace {
-constexpr int LCAP = 512;
+#ifndef EMU_LCAP
+#define EMU_LCAP 512
+#endif
+constexpr int LCAP = EMU_LCAP;
 
-void run_wave(const Task& T, double tol, bool mixed, int n0, int rcap, FsOut* out) {
+void run_wave(const Task& T, double tol, bool mixed, int n0, FsOut* out) {
   std::vector<char> scratch((size_t)METHOD_CAP * kSlotBytes);
-  std::vector<double> rec((size_t)rcap * kRecBytes / 8 + 1);
-  const WaveMem m = wave_mem(scratch.data(), 0, rcap > 0 ? (char*)rec.data() : nullptr, rcap);
+  const WaveMem m = wave_mem(scratch.data(), 0);
   auto* lds = new FsLds<LCAP>();
   hip_emu::Wave wave;
   hip_emu::g_wave = &wave;
@@ -39,10 +41,10 @@ void run_wave(const Task& T, double tol, bool mixed, int n0, int rcap, FsOut* ou
 extern "C" {
 
 // Centre roots by the device cold-start solve, then the contour engine
-// starting from a uniform grid of n0 samples (a multiple of 64, <= 512),
-// with the first rcap sample records in the (emulated) LDS.
+// starting from a uniform grid of n0 samples (a multiple of 64, at most the
+// LDS capacity the emulation is built with).
 int emu_finite_mag(double s, double q, double zx, double zy, double rho, double tol, int mixed,
-                   int n0, int rcap, double* mag, double* err, int* nsamp, unsigned* flags, double* sweeps) {
+                   int n0, double* mag, double* err, int* nsamp, unsigned* flags, double* sweeps) {
   const Lens L = make_lens(s, q);
   const c64 yc = cz(zx - L.z2, zy);
   Images im;
@@ -57,8 +59,8 @@ int emu_finite_mag(double s, double q, double zx, double zy, double rho, double 
   T.zy = zy;
   for (int k = 0; k < 5; ++k) T.roots[k] = im.z[k];
   FsOut o;
-  if (n0 < 64 || n0 > LCAP || n0 % 64 || rcap < 0 || rcap > METHOD_CAP) return -1;
-  run_wave(T, tol, mixed != 0, n0, rcap, &o);
+  if (n0 < 64 || n0 > LCAP || n0 % 64) return -1;
+  run_wave(T, tol, mixed != 0, n0, &o);
   *mag = o.mag;
   *err = o.err;
   *nsamp = o.n;

@@ -209,13 +209,15 @@ def test_learned_path_parity(ctx, oracle):
             rel = np.abs(mag / rm - 1)
             assert rel.max() <= GATE, (bias, mode, rel.max(), int(rel.argmax()))
             # every contour started from at least its budgeted grid:
-            # n0 = 64 floor(2^(l2 - 1) / 64) within [64, 512], l2 the
-            # predicted log2 count of the epoch's features
+            # n0 = 64 floor(2^(l2 - shift) / 64) within [64, 512] and at
+            # most the LDS capacity, l2 the predicted log2 count of the
+            # epoch's features
             fs = (fl & 1) == 0
             feat, _, _ = ctx.features(c.s, c.q, c.u0, c.alpha, c.rho, c.tau, 1e-4)
             l2 = ctx.mlp_infer(feat).cpu().numpy()[:, 0].astype(np.float64)
-            want = np.exp2(np.clip(l2 - 1.0, 6.0, 9.0)) / 64.0
-            n0 = np.clip(np.floor(want) * 64, 64, 512)
+            tune = ctx.get_tuning()
+            want = np.exp2(np.clip(l2 - tune.budget_shift, 6.0, 9.0)) / 64.0
+            n0 = np.clip(np.floor(want) * 64, 64, min(512, tune.lds_cap))
             clear = np.abs(want - np.round(want)) > 1e-3
             sel = fs & clear
             assert np.all(ns[sel] >= n0[sel]), (bias, int(np.sum(ns[sel] < n0[sel])))

@@ -74,7 +74,7 @@ def test_graph_replay_bitwise(lc):
     ctx.close()
 
 
-@pytest.mark.parametrize("cap", [256, 512, 1024])
+@pytest.mark.parametrize("cap", [64, 128, 256])
 def test_tuning_does_not_change_results(lc, cap):
     import torch
     from paper_2501_03322_amd import twk
@@ -128,7 +128,7 @@ def test_autotune(lc, oracle):
     small = [a[:32] if a.numel() == 96 else a for a in args]
     best = ctx.autotune(*small, 1e-4, mode=twk.MODE_MLP | twk.MODE_MIXED, trials=1)
     _log(f"autotuned: {best.as_dict()}")
-    assert best.lds_cap in (256, 512, 1024) and best.waves_per_cu >= 1
+    assert best.lds_cap in (64, 128, 256) and best.waves_per_cu >= 1
     assert ctx.get_tuning().as_dict() == best.as_dict()
     mag, err, ns, fl = _run(ctx, args, twk.MODE_MLP | twk.MODE_MIXED)
     mag, fl = mag.cpu().numpy(), fl.cpu().numpy()
