@@ -402,14 +402,42 @@ __device__ __attribute__((noinline)) Piece interval_piece_any(const R& m, int sa
 // dth apart.  The four count patterns of a binary lens (3-3, 5-5, 3-5, 5-3)
 // are linked with static list positions; image data are read from the
 // (cached) sample records with computed offsets.
-template <class R>
-__device__ inline Piece interval_piece(const R& m, int sa, int sb, double dth) {
-  const uint32_t ma_ = meta_at(m, sa), mb_ = meta_at(m, sb);
-  const int na = ma_ & 7u, nb = mb_ & 7u;
-  const uint32_t para = (ma_ >> 3) & 31u, parb = (mb_ >> 3) & 31u;
+// Count pattern of an interval: 0 = 3-3, 1 = 5-5, 2 = 3-5 or 5-3 (all with
+// the standard image order), 3 = anything else.
+__device__ __forceinline__ int link_pattern(uint32_t ma, uint32_t mb) {
+  const int na = ma & 7u, nb = mb & 7u;
+  const uint32_t para = (ma >> 3) & 31u, parb = (mb >> 3) & 31u;
   const bool stda = (na == 3 && para == 1u) || (na == 5 && para == 3u);
   const bool stdb = (nb == 3 && parb == 1u) || (nb == 5 && parb == 3u);
-  if (!stda || !stdb) return interval_piece_any(m, sa, sb, dth);
+  if (!stda || !stdb) return 3;
+  return na == nb ? (na == 5 ? 1 : 0) : 2;
+}
+
+// Distance of a pair of the padded lists in the unified linking below
+// (0 unless both entries are present).
+__device__ __forceinline__ double pair_dist(c64 a, bool pa, c64 b, bool pb) {
+  return (pa && pb) ? cabs64(a - b) : 0.0;
+}
+
+// Area and error of the interval between slots sa and sb, dth apart.
+// path (the same for every active lane of the wave) selects the code:
+// 0 = every interval of the wave is 3-3, 1 = every one is 5-5, 2 = mixed
+// patterns.  Path 2 links every count pattern with the same instructions:
+// the positive lists are padded to two entries and the negative lists to
+// three with absent entries; among the permutations of each padded pair of
+// lists that pair as few absent entries with present ones as possible, the
+// one of least total distance over present pairs is the least-total-distance
+// injection of the shorter list into the longer (first minimum in
+// lexicographic order, like the static code); present-present pairs are
+// links, and the two images
+// left over at the five-image sample are the pair created (or destroyed) on
+// the critical curve.  Patterns other than the binary-lens ones take the
+// general (out-of-line) code.
+template <class R>
+__device__ inline Piece interval_piece(const R& m, int sa, int sb, double dth, int path) {
+  const uint32_t ma_ = meta_at(m, sa), mb_ = meta_at(m, sb);
+  const int na = ma_ & 7u, nb = mb_ & 7u;
+  if (link_pattern(ma_, mb_) == 3) return interval_piece_any(m, sa, sb, dth);
   c64 za[5], zb[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -417,12 +445,14 @@ __device__ inline Piece interval_piece(const R& m, int sa, int sb, double dth) {
     zb[k] = ld_root(m, k, sb);
   }
   Piece out{0.0, 0.0, na != nb ? (uint32_t)IF_COUNT : 0u};
-  if (na == 3 && nb == 3) {
+  if (path == 0) {
     add_link(m, sa, 0, sb, 0, 1.0, dth, out);
     const uint32_t c = inject_static<2, 2>(za + 1, zb + 1);
     add_link(m, sa, 1, sb, 1 + (c & 3u), -1.0, dth, out);
     add_link(m, sa, 2, sb, 1 + ((c >> 2) & 3u), -1.0, dth, out);
-  } else if (na == 5 && nb == 5) {
+    return out;
+  }
+  if (path == 1) {
     const uint32_t cp = inject_static<2, 2>(za, zb);
     add_link(m, sa, 0, sb, cp & 3u, 1.0, dth, out);
     add_link(m, sa, 1, sb, (cp >> 2) & 3u, 1.0, dth, out);
@@ -430,24 +460,84 @@ __device__ inline Piece interval_piece(const R& m, int sa, int sb, double dth) {
     add_link(m, sa, 2, sb, 2 + (cn & 3u), -1.0, dth, out);
     add_link(m, sa, 3, sb, 2 + ((cn >> 2) & 3u), -1.0, dth, out);
     add_link(m, sa, 4, sb, 2 + ((cn >> 4) & 3u), -1.0, dth, out);
-  } else if (na == 3) {  // 3 -> 5: a pair is created before sample b
-    const uint32_t cp = inject_static<1, 2>(za, zb);
-    add_link(m, sa, 0, sb, cp & 3u, 1.0, dth, out);
-    const uint32_t cn = inject_static<2, 3>(za + 1, zb + 2);
-    const int j0 = cn & 3u, j1 = (cn >> 2) & 3u;
-    add_link(m, sa, 1, sb, 2 + j0, -1.0, dth, out);
-    add_link(m, sa, 2, sb, 2 + j1, -1.0, dth, out);
-    add_cross(m, sb, 1 - (int)(cp & 3u), 2 + (3 - j0 - j1), 1, dth, out);
-  } else {  // 5 -> 3: a pair is destroyed after sample a
-    const uint32_t cp = inject_static<1, 2>(zb, za);
-    add_link(m, sa, cp & 3u, sb, 0, 1.0, dth, out);
-    const uint32_t cn = inject_static<2, 3>(zb + 1, za + 2);
-    const int j0 = cn & 3u, j1 = (cn >> 2) & 3u;
-    add_link(m, sa, 2 + j0, sb, 1, -1.0, dth, out);
-    add_link(m, sa, 2 + j1, sb, 2, -1.0, dth, out);
-    add_cross(m, sa, 1 - (int)(cp & 3u), 2 + (3 - j0 - j1), -1, dth, out);
+    return out;
   }
+  // padded lists: record positions and presence
+  const bool a5 = na == 5, b5 = nb == 5;
+  const int pia[2] = {0, 1}, pib[2] = {0, 1};
+  const bool ppa[2] = {true, a5}, ppb[2] = {true, b5};
+  const int nia[3] = {a5 ? 2 : 1, a5 ? 3 : 2, 4}, nib[3] = {b5 ? 2 : 1, b5 ? 3 : 2, 4};
+  const bool npa[3] = {true, true, a5}, npb[3] = {true, true, b5};
+  c64 pza[2], pzb[2], nza[3], nzb[3];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    pza[i] = za[pia[i]];
+    pzb[i] = zb[pib[i]];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    nza[i] = a5 ? za[2 + i] : za[i < 2 ? 1 + i : 0];
+    nzb[i] = b5 ? zb[2 + i] : zb[i < 2 ? 1 + i : 0];
+  }
+  // positives: identity or swap
+  const int mid = (ppa[0] != ppb[0]) + (ppa[1] != ppb[1]);
+  const int msw = (ppa[0] != ppb[1]) + (ppa[1] != ppb[0]);
+  const double pid = pair_dist(pza[0], ppa[0], pzb[0], ppb[0]) + pair_dist(pza[1], ppa[1], pzb[1], ppb[1]);
+  const double psw = pair_dist(pza[0], ppa[0], pzb[1], ppb[1]) + pair_dist(pza[1], ppa[1], pzb[0], ppb[0]);
+  const bool swp = msw < mid || (msw == mid && psw < pid);
+  // negatives: the six permutations in lexicographic order
+  double nc[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) nc[i][j] = pair_dist(nza[i], npa[i], nzb[j], npb[j]);
+  const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  double best = 0.0;
+  int bp = -1, bm = 4;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int mis = (npa[0] != npb[perms[q][0]]) + (npa[1] != npb[perms[q][1]]) +
+                    (npa[2] != npb[perms[q][2]]);
+    const double t = nc[0][perms[q][0]] + nc[1][perms[q][1]] + nc[2][perms[q][2]];
+    if (mis < bm || (mis == bm && t < best)) {
+      bm = mis;
+      best = t;
+      bp = q;
+    }
+  }
+  // links (the absent ones contribute nothing) and the left-over pair
+  int lpos = 0, lneg = 0;
+  bool lp_at_b = false;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int j = swp ? 1 - i : i;
+    if (ppa[i] && ppb[j]) add_link(m, sa, pia[i], sb, pib[j], 1.0, dth, out);
+    else if (ppb[j]) { lpos = pib[j]; lp_at_b = true; }
+    else if (ppa[i]) lpos = pia[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    int j = perms[0][i];
+#pragma unroll
+    for (int q = 1; q < 6; ++q)
+      if (bp == q) j = perms[q][i];
+    if (npa[i] && npb[j]) add_link(m, sa, nia[i], sb, nib[j], -1.0, dth, out);
+    else if (npb[j]) lneg = nib[j];
+    else if (npa[i]) lneg = nia[i];
+  }
+  // 3 -> 5: the pair is created at b; 5 -> 3: destroyed after a
+  if (na != nb) add_cross(m, lp_at_b ? sb : sa, lpos, lneg, lp_at_b ? 1 : -1, dth, out);
   return out;
+}
+
+// Path of interval_piece for the wave: every lane calls it (inactive lanes
+// with act = false); the ballots make the choice uniform.
+__device__ __forceinline__ int link_path(bool act, int pattern) {
+  const uint64_t b33 = __ballot(act && pattern == 0);
+  const uint64_t b55 = __ballot(act && pattern == 1);
+  const uint64_t bmx = __ballot(act && pattern == 2);
+  if (bmx || (b33 && b55)) return 2;
+  return b55 ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- wave ops
@@ -573,12 +663,19 @@ struct FsOut {
 
 // Relink the interval starting at sorted position p (of N): area to the
 // global record of its left slot, error to the sorted arrays.
+// Count pattern of the interval starting at sorted position p (of N).
 template <class Sorted, class R>
-__device__ __forceinline__ Piece relink(const R& m, const Sorted& S, int p, int N) {
+__device__ __forceinline__ int relink_pattern(const R& m, const Sorted& S, int p, int N) {
+  const int q = p + 1 < N ? p + 1 : 0;
+  return link_pattern(meta_at(m, (int)S.sl[p]), meta_at(m, (int)S.sl[q]));
+}
+
+template <class Sorted, class R>
+__device__ __forceinline__ Piece relink(const R& m, const Sorted& S, int p, int N, int path) {
   const int q = p + 1 < N ? p + 1 : 0;
   const int sa = S.sl[p], sb = S.sl[q];
   const double dth = (p + 1 < N ? S.th[q] : S.th[q] + TWO_PI) - S.th[p];
-  const Piece pc = interval_piece(m, sa, sb, dth);
+  const Piece pc = interval_piece(m, sa, sb, dth, path);
   dA_at(m, sa) = pc.dA;
   S.E[p] = pc.E;
   return pc;
@@ -786,8 +883,12 @@ __device__ __attribute__((noinline)) bool slope_pass(const R& m, const Sorted& S
   changed = __builtin_amdgcn_readlane(changed, 0);
   __syncthreads();
   double h = 0.0, l = 0.0;
-  for (int p = lane; p < N; p += WAVE) {
-    const Piece pc = relink(m, S, p, N);
+  for (int base = 0; base < N; base += WAVE) {
+    const int p = base + lane;
+    const bool act = p < N;
+    const int path = link_path(act, act ? relink_pattern(m, S, p, N) : -1);
+    if (!act) continue;
+    const Piece pc = relink(m, S, p, N, path);
     double s1, e1;
     two_sum(h, pc.dA, s1, e1);
     h = s1;
@@ -996,8 +1097,11 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
     double dh = 0.0, dl = 0.0;
 #pragma unroll 1
     for (int j = 0; j < 2; ++j) {
-      if (valid && (j == 0 || first)) {
-        const Piece pc = relink(m, S, j == 0 ? P : P - 1, N);
+      const bool act = valid && (j == 0 || first);
+      const int pp = j == 0 ? P : P - 1;
+      const int path = link_path(act, act ? relink_pattern(m, S, pp, N) : -1);
+      if (act) {
+        const Piece pc = relink(m, S, pp, N, path);
         ++nint;
         double s1, e1;
         two_sum(dh, pc.dA, s1, e1);
