@@ -643,15 +643,27 @@ struct FsLds {
 // The sorted arrays in use: the LDS copy (D = ldouble, U = luint16), or,
 // once a source outgrows it, the spill copy in the wave's global slice
 // (D = gdouble, U = guint16).
-template <class D, class U>
+template <class D, class U, bool LDS>
 struct SortedT {
+  static constexpr bool kLds = LDS;
   D* th;
   D* E;
   U* sl;
   int cap;
 };
-typedef SortedT<ldouble, luint16> SortedL;
-typedef SortedT<gdouble, guint16> SortedG;
+typedef SortedT<ldouble, luint16, true> SortedL;
+typedef SortedT<gdouble, guint16, false> SortedG;
+
+// Synchronisation of the lanes of the source's wave (a workgroup is one
+// wave).  While the source's arrays are in LDS only the compiler must not
+// move LDS accesses across the point: one wave's LDS operations are executed
+// in issue order.  Once they are in global memory a full workgroup barrier
+// (which waits for every outstanding memory operation) orders them.
+template <class Sorted>
+__device__ __forceinline__ void lane_sync() {
+  if constexpr (Sorted::kLds) __builtin_amdgcn_wave_barrier();
+  else __syncthreads();
+}
 
 struct FsOut {
   double mag, err;
@@ -877,11 +889,11 @@ __device__ __attribute__((noinline)) bool slope_pass(const R& m, const Sorted& S
                                                      int lane, double* Ahi, double* Alo,
                                                      uint32_t* nint) {
   for (int p = lane; p < N; p += WAVE) undo_demotion(m, p);
-  __syncthreads();
+  lane_sync<Sorted>();
   int changed = 0;
   if (lane == 0) changed = detect_runs(m, S, N);
   changed = __builtin_amdgcn_readlane(changed, 0);
-  __syncthreads();
+  lane_sync<Sorted>();
   double h = 0.0, l = 0.0;
   for (int base = 0; base < N; base += WAVE) {
     const int p = base + lane;
@@ -898,7 +910,7 @@ __device__ __attribute__((noinline)) bool slope_pass(const R& m, const Sorted& S
   wave_sum_comp(h, l);
   *Ahi = h;
   *Alo = l;
-  __syncthreads();
+  lane_sync<Sorted>();
   return changed > 0;
 }
 
@@ -1045,7 +1057,7 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
       if (sf & M_SUSPECT) suspects = true;
     }
     suspects = __ballot(suspects) != 0;
-    __syncthreads();
+    lane_sync<Sorted>();
     // merge: old position p moves up by #(new samples in intervals < p);
     // strips from the top so that no unread entry is overwritten
     if (N > 0) {
@@ -1066,13 +1078,13 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
           ve = S.E[p];
           vs = S.sl[p];
         }
-        __syncthreads();
+        lane_sync<Sorted>();
         if (p < N && sh > 0) {
           S.th[p + sh] = vt;
           S.E[p + sh] = ve;
           S.sl[p + sh] = vs;
         }
-        __syncthreads();
+        lane_sync<Sorted>();
       }
     }
     int P = 0;
@@ -1083,13 +1095,13 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
       first = N > 0 && (rank == 0 || L.ivl[rank - 1] != iv);
       if (first) dAold = dA_at(m, S.sl[P - 1]);
     }
-    __syncthreads();
+    lane_sync<Sorted>();
     if (valid) {
       S.th[P] = thn;
       S.sl[P] = (uint16_t)(N + rank);
     }
     N += mcount;
-    __syncthreads();
+    lane_sync<Sorted>();
     // relink the intervals touching new samples: the one starting at the
     // new sample, and for the first new sample of a split interval the one
     // ending there; the area total changes by the new pieces minus the
@@ -1123,7 +1135,7 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
       Ahi = s1;
       Alo += dl + e1;
     }
-    __syncthreads();
+    lane_sync<Sorted>();
     if (suspects && slope_pass(m, S, N, lane, &Ahi, &Alo, &nint)) fl |= F_SLOPE;
   }
   st = FsState{N, Ahi, Alo, A, E, fl, sw32, sw64, nint, suspects};

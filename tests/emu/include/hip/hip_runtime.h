@@ -32,6 +32,8 @@ inline thread_local int t_lane = 0;
 }  // namespace hip_emu
 
 inline void __syncthreads() { hip_emu::g_wave->bar.arrive_and_wait(); }
+// The emulated lanes are threads: a wave barrier must synchronise them too.
+inline void __builtin_amdgcn_wave_barrier() { hip_emu::g_wave->bar.arrive_and_wait(); }
 
 template <class T>
 inline T __hip_emu_exchange(T v, int src) {
