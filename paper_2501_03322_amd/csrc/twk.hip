@@ -495,6 +495,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES
   const int lane = threadIdx.x;
   const WaveMem m = wave_mem(scratch, blockIdx.x);
   const long long n = *ntask;
+  unsigned long long w_samples = 0, w_sw32 = 0, w_sw64 = 0, w_int = 0, w_runs = 0, w_over = 0;
   for (;;) {
     long long t = 0;
     if (lane == 0) t = atomicAdd((unsigned long long*)head, 1ull);
@@ -509,14 +510,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES
       err[task.out] = o.err;
       ns[task.out] = o.n;
       flags[task.out] = o.flags;
-      atomicAdd((unsigned long long*)&cnt[C_SAMPLES], (unsigned long long)o.n);
-      atomicAdd((unsigned long long*)&cnt[C_SW32], (unsigned long long)o.sweeps32);
-      atomicAdd((unsigned long long*)&cnt[C_SW64], (unsigned long long)o.sweeps64);
-      atomicAdd((unsigned long long*)&cnt[C_INTERVALS], (unsigned long long)o.intervals);
-      atomicAdd((unsigned long long*)&cnt[C_RUNS], 1ull);
-      if (o.spilled) atomicAdd((unsigned long long*)&cnt[C_NOVER], 1ull);
+      w_samples += (unsigned long long)o.n;
+      w_sw32 += (unsigned long long)o.sweeps32;
+      w_sw64 += (unsigned long long)o.sweeps64;
+      w_int += (unsigned long long)o.intervals;
+      w_runs += 1ull;
+      w_over += o.spilled ? 1ull : 0ull;
     }
     __syncthreads();
+  }
+  // work counters: one flush per wave, not per source (the counters share a
+  // cache line that every wave would otherwise hit once per source)
+  if (lane == 0 && w_runs > 0) {
+    atomicAdd((unsigned long long*)&cnt[C_SAMPLES], w_samples);
+    atomicAdd((unsigned long long*)&cnt[C_SW32], w_sw32);
+    atomicAdd((unsigned long long*)&cnt[C_SW64], w_sw64);
+    atomicAdd((unsigned long long*)&cnt[C_INTERVALS], w_int);
+    atomicAdd((unsigned long long*)&cnt[C_RUNS], w_runs);
+    if (w_over) atomicAdd((unsigned long long*)&cnt[C_NOVER], w_over);
   }
 }
 
