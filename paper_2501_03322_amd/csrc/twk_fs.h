@@ -166,7 +166,7 @@ __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double
   c64 c[6];
   coefficients(L, y, c);
   int it, s32 = 0, s64;
-  if (MIXED) s32 = aberth32(c, r, 30);
+  if (MIXED) s32 = aberth32(c, r, 12);
   it = aberth64(c, r, 40);
   s64 = it;
   if (it > 40) {
