@@ -141,6 +141,42 @@ def measured_traffic(lib_path):
     return t.get("hbm_bytes_per_launch")
 
 
+def pmc_summary(fetch_dir, write_dir):
+    """HBM traffic of one contour-kernel launch from two counter runs.
+    FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by
+    what it reads for the 1 GiB device copies of the same run (the copy
+    reads and writes exactly 1 GiB), and the launch is the run's last
+    contour-kernel dispatch (the timed step)."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter:
+                        rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        per = {}
+        for did, name, v in rows:
+            per.setdefault(did, [name, 0.0])[1] += v
+        fs = [per[k][1] for k in sorted(per) if "k_fs" in per[k][0]]
+        # the probe's three 1 GiB copies are the run's largest copy dispatches
+        cp = sorted(per[k][1] for k in per if "copyBuffer" in per[k][0])[-3:]
+        if not fs or not cp:
+            raise SystemExit(f"{d}: no contour-kernel or copy dispatch with {counter}")
+        kib = float(1 << 20)  # 1 GiB in KiB
+        factor = kib / float(np.median(cp))
+        return fs[-1] * 1024.0 * factor, factor
+
+    fetch, ff = read(fetch_dir, "FETCH_SIZE")
+    write, wf = read(write_dir, "WRITE_SIZE")
+    from paper_2501_03322_amd import twk
+    return {"lib_sha256": lib_digest(twk.LIB_PATH), "hbm_bytes_per_launch": fetch + write,
+            "fetch_bytes": fetch, "write_bytes": write,
+            "fetch_copy_factor": ff, "write_copy_factor": wf}
+
+
 def path_summary(n, r):
     st = r["stats"]
     fs_s = r["fs_kernel_ms"] * 1e-3
@@ -167,7 +203,17 @@ def main():
                     help="skip the autotuner (default launch parameters)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="issue every call eagerly instead of replaying a captured graph")
+    ap.add_argument("--tune", metavar="LDS,WAVES,SHIFT",
+                    help="fixed launch tuning (LDS capacity, waves per CU, budget shift) instead "
+                         "of the autotuner, e.g. to profile the configuration a bench run chose")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no run: turn two rocprofv3 --pmc output folders (FETCH_SIZE, then "
+                         "WRITE_SIZE, each of a run with --copy-probe) into the traffic record "
+                         "of the contour kernel, printed as JSON")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(json.dumps(pmc_summary(*args.pmc_summary)))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -189,7 +235,11 @@ def main():
     log(f"workload: {c.nsets} sets x {c.nepochs} epochs = {n} magnifications, tol {c.tol}")
 
     head_mode = twk.MODE_MLP | twk.MODE_MIXED
-    if not args.no_tune:
+    if args.tune:
+        lds, waves, shift = args.tune.split(",")
+        ctx.set_tuning(lds_cap=int(lds), waves_per_cu=int(waves), budget_shift=float(shift))
+        log(f"fixed tuning: {ctx.get_tuning().as_dict()}")
+    elif not args.no_tune:
         t0 = time.perf_counter()
         tuned = ctx.autotune(c.s, c.q, c.u0, c.alpha, c.rho, c.tau, c.tol, mode=head_mode, trials=1)
         log(f"autotuned on the workload in {time.perf_counter() - t0:.1f} s: {tuned.as_dict()}")
@@ -245,7 +295,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
                      "traffic": measured_traffic(twk.LIB_PATH),
-                     "kernel": "k_fs<512, mixed>",
+                     "kernel": f"k_fs<{tuning['lds_cap']}, mixed>",
                      "flops_per_launch": flops, "kernel_ms": best["fs_kernel_ms"]},
         "work": {"fs_fraction": best["fs_fraction"], **{k: int(v) for k, v in st.items()},
                  "samples_per_source_cumulative": best["samples_hist"],
