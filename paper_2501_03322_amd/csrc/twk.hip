@@ -105,14 +105,24 @@ __device__ inline double pair_stat(const Lens& L, const Images& im) {
 }
 
 // probe: solve the four stencil points (needed by the test and by the
-// learned features); test: decide adequacy.
+// learned features); test: decide adequacy.  start: roots to start the
+// centre solve from (a nearby source's), or null for a cold start; a warm
+// start that has not converged in 60 sweeps is replaced by a cold one.
 __device__ inline PsResult point_source_pass(const Lens& L, c64 yc, double rho, double tol,
-                                             bool probe, bool test) {
+                                             bool probe, bool test, const c64* start = nullptr) {
   PsResult out;
   c64 c[6], r[5];
   coefficients(L, yc, c);
-  cold_start(c, r);
-  aberth64(c, r, 200);
+  bool cold = start == nullptr;
+  if (!cold) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) r[k] = start[k];
+    cold = aberth64(c, r, 60) > 60;
+  }
+  if (cold) {
+    cold_start(c, r);
+    aberth64(c, r, 200);
+  }
   Images im;
   finish_images(L, yc, r, im);
   out.mu = point_mag(im);
@@ -236,10 +246,14 @@ __device__ inline int64_t queue_push(bool push, int count, long long* counter) {
 // annuli (limb darkening), the source is recorded in fs_epoch[] and na
 // uniform-disk tasks of radii rho sqrt(k/na), k = 1..na, are queued; their
 // results land in the annulus buffers at f*na + k - 1.
+// carry (optional): on entry, with *warm set, the centre roots of a nearby
+// source of the same lens to start from; on return the centre roots of this
+// source (and *warm says whether there are any).
 __device__ inline void emit_source(int64_t out, double s, double q, double zx, double zy,
                                    double rho, double tol, bool all_fs, int na, Task* tasks,
                                    long long* cnt, int64_t* fs_epoch, double* mag, double* err,
-                                   int32_t* ns, uint32_t* flags, bool active, float* tfeat) {
+                                   int32_t* ns, uint32_t* flags, bool active, float* tfeat,
+                                   c64* carry = nullptr, bool* warm = nullptr) {
   bool push = false;
   PsResult ps;
   const Lens L = make_lens(s, q);
@@ -250,8 +264,15 @@ __device__ inline void emit_source(int64_t out, double s, double q, double zx, d
       err[out] = __builtin_nan("");
       ns[out] = 0;
       flags[out] = F_NONFINITE;
+      if (warm) *warm = false;
     } else {
-      ps = point_source_pass(L, cz(zx - L.z2, zy), rho, tol, !all_fs || tfeat, !all_fs);
+      ps = point_source_pass(L, cz(zx - L.z2, zy), rho, tol, !all_fs || tfeat, !all_fs,
+                             warm && *warm ? carry : nullptr);
+      if (carry) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) carry[k] = ps.roots[k];
+        *warm = true;
+      }
       if (ps.adequate) {
         mag[out] = ps.mu;
         err[out] = 0.0;
@@ -330,7 +351,14 @@ __global__ __launch_bounds__(256) void k_map(double s, double q, double rho, dou
 }
 
 // Light curves: element (set k, epoch j) at index k * nepochs + j.  Source
-// centre on the straight trajectory of set k (centre-of-mass frame).
+// centre on the straight trajectory of set k (centre-of-mass frame).  A lane
+// takes LC_RUN consecutive epochs of one set; after the first, each centre
+// solve starts from the previous epoch's roots (the source has moved by one
+// epoch step), which saves most of a cold start's sweeps.
+constexpr int LC_RUN = 4;
+__host__ __device__ inline int64_t lc_lanes(int64_t nsets, int64_t nep) {
+  return nsets * ((nep + LC_RUN - 1) / LC_RUN);
+}
 __global__ __launch_bounds__(256) void k_lc(int64_t nsets, const double* ps, const double* pq,
                                             const double* pu0, const double* pal,
                                             const double* prho, int64_t nep,
@@ -339,21 +367,32 @@ __global__ __launch_bounds__(256) void k_lc(int64_t nsets, const double* ps, con
                                             double* mag, double* err, int32_t* ns,
                                             uint32_t* flags, float* tfeat) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = i < nsets * nep;
-  double s = 1.0, q = 1.0, zx = 0.0, zy = 0.0, rho = 1.0;
-  if (active) {
-    const int64_t k = i / nep, j = i - k * nep;
+  const int64_t runs = (nep + LC_RUN - 1) / LC_RUN;
+  const bool lane_on = i < nsets * runs;
+  const int64_t k = lane_on ? i / runs : 0, j0 = lane_on ? (i - k * runs) * LC_RUN : 0;
+  double s = 1.0, q = 1.0, rho = 1.0, u0 = 0.0, sa = 0.0, ca = 1.0;
+  if (lane_on) {
     s = ps[k];
     q = pq[k];
     rho = prho[k];
-    double sa, ca;
+    u0 = pu0[k];
     sincos(pal[k], &sa, &ca);
-    const double t = tau[j], u0 = pu0[k];
-    zx = t * ca - u0 * sa;
-    zy = t * sa + u0 * ca;
   }
-  emit_source(i, s, q, zx, zy, rho, tol, all_fs != 0, na, tasks, cnt, fs_epoch, mag, err, ns,
-              flags, active, tfeat);
+  c64 carry[5];
+  bool warm = false;
+  // every lane runs LC_RUN steps: the queue appends are wave-wide
+  for (int e = 0; e < LC_RUN; ++e) {
+    const int64_t j = j0 + e;
+    const bool active = lane_on && j < nep;
+    double zx = 0.0, zy = 0.0;
+    if (active) {
+      const double t = tau[j];
+      zx = t * ca - u0 * sa;
+      zy = t * sa + u0 * ca;
+    }
+    emit_source(k * nep + j, s, q, zx, zy, rho, tol, all_fs != 0, na, tasks, cnt, fs_epoch, mag,
+                err, ns, flags, active, tfeat, carry, &warm);
+  }
 }
 
 // Linear limb darkening over na equal-area annuli (x_k = k/na of the squared
@@ -1077,7 +1116,7 @@ int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q,
       const int64_t nk = std::min(chunk_sets, nsets - k0);
       const int64_t o = k0 * nepochs;
       if (k0 > 0 && (r = reset(c, true))) return r;
-      hipLaunchKernelGGL(k_lc, dim3(blocks_for(nk * nepochs)), dim3(256), 0, c->stream, nk,
+      hipLaunchKernelGGL(k_lc, dim3(blocks_for(lc_lanes(nk, nepochs))), dim3(256), 0, c->stream, nk,
                          s + k0, q + k0, u0 + k0, alpha + k0, rho + k0, nepochs, tau, tol, all_fs,
                          na, c->tasks, c->cnt, c->fs_epoch, mag + o, err + o, ns + o, flags + o,
                          tfeat);
