@@ -154,7 +154,9 @@ int twk_kernel_times(twk_ctx *ctx, double *ms5);
  * ---------------------------------------------------------------------- */
 typedef struct {
   int32_t waves_per_cu; /* resident contour waves per CU: the persistent grid is
-                           waves_per_cu x CUs; 1 .. the occupancy limit of lds_cap */
+                           waves_per_cu x CUs; 1 .. the occupancy limit of lds_cap
+                           for the mixed path (whose sample records are smaller);
+                           an FP64-path launch uses at most its own limit */
   int32_t lds_cap;      /* limb samples a source keeps in LDS (sorted arrays and
                            sample records) before continuing in global memory:
                            64, 128 or 256 */

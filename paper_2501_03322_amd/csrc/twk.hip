@@ -530,9 +530,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES
     const Task* tasks, const long long* ntask, long long* head, double tol, char* scratch,
     double* mag, double* err, int32_t* ns, uint32_t* flags, long long* cnt, const int32_t* order,
     const int32_t* tn0) {
-  __shared__ FsLds<LCAP> lds;
+  __shared__ FsLds<LCAP, MIXED> lds;
   const int lane = threadIdx.x;
-  const WaveMem m = wave_mem(scratch, blockIdx.x);
+  const WaveMem<MIXED> m = wave_mem<MIXED>(scratch, blockIdx.x);
   const long long n = *ntask;
   unsigned long long w_samples = 0, w_sw32 = 0, w_sw64 = 0, w_int = 0, w_runs = 0, w_over = 0;
   for (;;) {
@@ -593,6 +593,7 @@ struct twk_ctx {
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   // launch tuning of the contour stage, and graph replay
   twk_tuning tune{0, 128, 1.0f, 0};
+  int occ[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // resident waves per CU [LDS cap][fp64, mixed]
   bool capturing = false;  // no event marks inside a capture
   // captured launch sequences (replayed when a call repeats)
   struct Graph {
@@ -657,24 +658,32 @@ int grow(twk_ctx* c, void** p, size_t* have, size_t need) {
   return TWK_OK;
 }
 
+// Resident contour waves per CU of the FP64 and the mixed kernel for an LDS
+// capacity (the mixed kernel's smaller records allow more).
 template <int LCAP>
-hipError_t occupancy(int* blocks) {
-  int b1 = 0, b2 = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fs<LCAP, false>, 64, 0);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fs<LCAP, true>, 64, 0);
-  *blocks = std::min(b1, b2);
+hipError_t occupancy(int* fp64, int* mixed) {
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(fp64, k_fs<LCAP, false>, 64, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(mixed, k_fs<LCAP, true>, 64, 0);
   return e;
 }
 
-// Waves per CU the hardware allows for an LDS capacity.
-int max_waves(int lds_cap, int* out) {
+int occupancy_of(int lds_cap, int* fp64, int* mixed) {
   hipError_t e;
   switch (lds_cap) {
-    case 64: e = occupancy<64>(out); break;
-    case 256: e = occupancy<256>(out); break;
-    default: e = occupancy<128>(out); break;
+    case 64: e = occupancy<64>(fp64, mixed); break;
+    case 256: e = occupancy<256>(fp64, mixed); break;
+    default: e = occupancy<128>(fp64, mixed); break;
   }
   return e == hipSuccess ? TWK_OK : TWK_EDEVICE;
+}
+
+// Waves per CU a tuning may ask for at an LDS capacity: the larger of the
+// two kernels' limits (a launch of the other kernel is clamped to its own).
+int max_waves(int lds_cap, int* out) {
+  int a = 0, b = 0;
+  const int rc = occupancy_of(lds_cap, &a, &b);
+  *out = std::max(a, b);
+  return rc;
 }
 
 int cap_index(int lds_cap) {
@@ -695,7 +704,7 @@ int ensure_fs(twk_ctx* c, int64_t ntask_max) {
     return rc;
   c->task_cap = (int64_t)(have / sizeof(Task));
   c->waves = fs_waves(c);
-  const size_t need = (size_t)c->waves * METHOD_CAP * kSlotBytes;
+  const size_t need = (size_t)c->waves * METHOD_CAP * kSlotBytesMax;
   return grow(c, (void**)&c->scratch, &c->scratch_bytes, need);
 }
 
@@ -771,12 +780,16 @@ int learned_stage(twk_ctx* c, int64_t ntask_max) {
 template <int LCAP>
 void launch_fs_cap(twk_ctx* c, bool mixed, double tol, double* mag, double* err, int32_t* ns,
                    uint32_t* flags, const int32_t* order, const int32_t* n0) {
+  // the persistent grid: the tuned waves per CU, at most what the launched
+  // kernel can keep resident
+  const int ci = cap_index(LCAP);
+  const int waves = std::min(c->waves, c->occ[ci][mixed ? 1 : 0] * c->n_cu);
   if (mixed)
-    hipLaunchKernelGGL((k_fs<LCAP, true>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
+    hipLaunchKernelGGL((k_fs<LCAP, true>), dim3(waves), dim3(64), 0, c->stream, c->tasks,
                        &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
                        c->cnt, order, n0);
   else
-    hipLaunchKernelGGL((k_fs<LCAP, false>), dim3(c->waves), dim3(64), 0, c->stream, c->tasks,
+    hipLaunchKernelGGL((k_fs<LCAP, false>), dim3(waves), dim3(64), 0, c->stream, c->tasks,
                        &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
                        c->cnt, order, n0);
 }
@@ -844,6 +857,13 @@ int twk_create(twk_ctx** out, int device, void* stream) {
   }
   c->n_cu = prop.multiProcessorCount;
   int wpc = 0;
+  for (int i = 0; i < 3; ++i) {
+    if (occupancy_of(LDS_CAPS[i], &c->occ[i][0], &c->occ[i][1]) != TWK_OK ||
+        c->occ[i][0] < 1 || c->occ[i][1] < 1) {
+      delete c;
+      return TWK_EDEVICE;
+    }
+  }
   if (max_waves(128, &wpc) != TWK_OK || wpc < 1) {
     delete c;
     return TWK_EDEVICE;

@@ -19,6 +19,7 @@
 // sorted arrays by an in-place descending-strip move.  Only intervals that
 // touch a new sample are relinked.
 #pragma once
+#include <type_traits>
 
 #include "twk_device.h"
 
@@ -55,6 +56,25 @@ typedef TWK_GLOBAL_AS double gdouble;
 typedef TWK_GLOBAL_AS uint16_t guint16;
 typedef TWK_LDS_AS double ldouble;
 typedef TWK_LDS_AS uint16_t luint16;
+typedef TWK_GLOBAL_AS float gfloat;
+typedef TWK_LDS_AS float lfloat;
+
+// Record fields that only enter correction terms, error estimates and warm
+// starts (z', z' ^ z'', interval errors) are stored in FP32 on the mixed
+// path (clamped to FP32's finite range) and in FP64 on the FP64 path; roots,
+// angles and interval areas are FP64 on both.  The smaller records let more
+// samples of a source stay in LDS.
+template <bool MIXED>
+using corr_t = typename std::conditional<MIXED, float, double>::type;
+template <bool MIXED>
+using lcorr_t = typename std::conditional<MIXED, lfloat, ldouble>::type;
+template <bool MIXED>
+using gcorr_t = typename std::conditional<MIXED, gfloat, gdouble>::type;
+template <class T>
+__device__ __forceinline__ void put(T& d, double v) {
+  if constexpr (sizeof(T) == 4) d = (float)fmin(fmax(v, -3.0e38), 3.0e38);
+  else d = v;
+}
 
 // Sample records, SoA over slots (slot = creation order): five roots
 // (positive, negative real images, ghost pair) as (re, im), five z' as
@@ -63,50 +83,59 @@ typedef TWK_LDS_AS uint16_t luint16;
 // wave's LDS copy, for sources that fit) or in the wave's slice of global
 // memory (RecG: sources that outgrew LDS); every function on records is a
 // template on the view, so LDS-resident sources use LDS instructions only.
-template <class D, class U>
+template <class D, class F, class U>
 struct RecView {
   D* root;  // [5][cap][2]
-  D* dz;    // [5][cap][2]
-  D* w;     // [5][cap]
+  F* dz;    // [5][cap][2]
+  F* w;     // [5][cap]
   D* dA;    // [cap]
   U* meta;  // [cap]
   int cap;
 };
 typedef TWK_LDS_AS uint32_t luint32;
 typedef TWK_GLOBAL_AS uint32_t guint32;
-typedef RecView<ldouble, luint32> RecL;
-typedef RecView<gdouble, guint32> RecG;
+template <bool MIXED>
+using RecL = RecView<ldouble, lcorr_t<MIXED>, luint32>;
+template <bool MIXED>
+using RecG = RecView<gdouble, gcorr_t<MIXED>, guint32>;
 
-constexpr size_t kRecBytes = 5 * 16 + 5 * 16 + 5 * 8 + 8 + 4;  // 212 per slot
+// Bytes per slot: records (212 on the FP64 path, 152 mixed) plus the
+// sorted arrays (angle, interval error, slot).
+__host__ __device__ constexpr size_t slot_bytes(bool mixed) {
+  return mixed ? 5 * 16 + 5 * 8 + 5 * 4 + 8 + 4 + 8 + 4 + 2 : 5 * 16 + 5 * 16 + 5 * 8 + 8 + 4 + 8 + 8 + 2;
+}
+constexpr size_t kSlotBytesMax = slot_bytes(false);
 
 // The wave's slice of global scratch: records of every slot plus the
-// sorted-array spill copies.
+// sorted-array spill copies (slices are kSlotBytesMax * METHOD_CAP apart).
+template <bool MIXED>
 struct WaveMem {
-  RecG G;
-  gdouble* sth;  // sorted angles (spill copy)
-  gdouble* sE;   // sorted interval errors (spill copy)
-  guint16* ssl;  // sorted slots (spill copy)
+  RecG<MIXED> G;
+  gdouble* sth;         // sorted angles (spill copy)
+  gcorr_t<MIXED>* sE;   // sorted interval errors (spill copy)
+  guint16* ssl;         // sorted slots (spill copy)
 };
-constexpr size_t kSlotBytes = kRecBytes + 8 + 8 + 2;
 
-__device__ __forceinline__ WaveMem wave_mem(char* base, int wave) {
-  char* p = base + (size_t)wave * (size_t)METHOD_CAP * kSlotBytes;
-  WaveMem m;
+template <bool MIXED>
+__device__ __forceinline__ WaveMem<MIXED> wave_mem(char* base, int wave) {
+  constexpr size_t c = sizeof(corr_t<MIXED>);
+  char* p = base + (size_t)wave * (size_t)METHOD_CAP * kSlotBytesMax;
+  WaveMem<MIXED> m;
   m.G.cap = METHOD_CAP;
   m.G.root = (gdouble*)p;
   p += (size_t)5 * METHOD_CAP * 16;
-  m.G.dz = (gdouble*)p;
-  p += (size_t)5 * METHOD_CAP * 16;
-  m.G.w = (gdouble*)p;
-  p += (size_t)5 * METHOD_CAP * 8;
+  m.G.dz = (gcorr_t<MIXED>*)p;
+  p += (size_t)5 * METHOD_CAP * 2 * c;
+  m.G.w = (gcorr_t<MIXED>*)p;
+  p += (size_t)5 * METHOD_CAP * c;
   m.G.dA = (gdouble*)p;
   p += (size_t)METHOD_CAP * 8;
   m.G.meta = (guint32*)p;
   p += (size_t)METHOD_CAP * 4;
   m.sth = (gdouble*)p;
   p += (size_t)METHOD_CAP * 8;
-  m.sE = (gdouble*)p;
-  p += (size_t)METHOD_CAP * 8;
+  m.sE = (gcorr_t<MIXED>*)p;
+  p += (size_t)METHOD_CAP * c;
   m.ssl = (guint16*)p;
   return m;
 }
@@ -117,7 +146,7 @@ __device__ __forceinline__ c64 ld_root(const R& m, int k, int slot) {
 }
 template <class R>
 __device__ __forceinline__ c64 ld_dz(const R& m, int k, int slot) {
-  return cz(m.dz[2 * (k * m.cap + slot)], m.dz[2 * (k * m.cap + slot) + 1]);
+  return cz((double)m.dz[2 * (k * m.cap + slot)], (double)m.dz[2 * (k * m.cap + slot) + 1]);
 }
 template <class R>
 __device__ __forceinline__ void st_root(const R& m, int k, int slot, c64 v) {
@@ -126,8 +155,8 @@ __device__ __forceinline__ void st_root(const R& m, int k, int slot, c64 v) {
 }
 template <class R>
 __device__ __forceinline__ void st_dz(const R& m, int k, int slot, c64 v) {
-  m.dz[2 * (k * m.cap + slot)] = v.x;
-  m.dz[2 * (k * m.cap + slot) + 1] = v.y;
+  put(m.dz[2 * (k * m.cap + slot)], v.x);
+  put(m.dz[2 * (k * m.cap + slot) + 1], v.y);
 }
 template <class R>
 __device__ __forceinline__ auto& w_at(const R& m, int k, int slot) { return m.w[k * m.cap + slot]; }
@@ -183,7 +212,7 @@ __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double
     if (k < im.n) limb_derivs(L, im.z[k], im.J[k], zp1, rho, dz, w);
     st_root(m, k, slot, im.z[k]);
     st_dz(m, k, slot, dz);
-    w_at(m, k, slot) = w;
+    put(w_at(m, k, slot), w);
   }
   const bool suspect = im.n == 5 && im.par == 3u && im.margin > SUSPECT;
   meta_at(m, slot) = (uint32_t)im.n | (im.par << 3) | (im.flags << 8) | (suspect ? M_SUSPECT : 0u);
@@ -627,15 +656,15 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 
 // ---------------------------------------------------------------- engine
 // LDS of one wave: the sorted arrays for sources of up to LCAP samples.
-template <int LCAP>
+template <int LCAP, bool MIXED>
 struct FsLds {
   double root[5 * LCAP * 2];  // records of the first LCAP slots (see RecView)
-  double dz[5 * LCAP * 2];
-  double w[5 * LCAP];
+  corr_t<MIXED> dz[5 * LCAP * 2];
+  corr_t<MIXED> w[5 * LCAP];
   double dA[LCAP];
   uint32_t meta[LCAP];
-  double th[LCAP];    // sorted limb angles
-  double E[LCAP];     // error of the interval starting at each sorted position
+  double th[LCAP];          // sorted limb angles
+  corr_t<MIXED> E[LCAP];    // error of the interval starting at each sorted position
   uint16_t sl[LCAP];  // slot of each sorted position
   int ivl[NNEW];      // old interval index of each accepted new sample
 };
@@ -643,16 +672,18 @@ struct FsLds {
 // The sorted arrays in use: the LDS copy (D = ldouble, U = luint16), or,
 // once a source outgrows it, the spill copy in the wave's global slice
 // (D = gdouble, U = guint16).
-template <class D, class U, bool LDS>
+template <class D, class F, class U, bool LDS>
 struct SortedT {
   static constexpr bool kLds = LDS;
   D* th;
-  D* E;
+  F* E;
   U* sl;
   int cap;
 };
-typedef SortedT<ldouble, luint16, true> SortedL;
-typedef SortedT<gdouble, guint16, false> SortedG;
+template <bool MIXED>
+using SortedL = SortedT<ldouble, lcorr_t<MIXED>, luint16, true>;
+template <bool MIXED>
+using SortedG = SortedT<gdouble, gcorr_t<MIXED>, guint16, false>;
 
 // Synchronisation of the lanes of the source's wave (a workgroup is one
 // wave).  While the source's arrays are in LDS only the compiler must not
@@ -689,7 +720,7 @@ __device__ __forceinline__ Piece relink(const R& m, const Sorted& S, int p, int 
   const double dth = (p + 1 < N ? S.th[q] : S.th[q] + TWO_PI) - S.th[p];
   const Piece pc = interval_piece(m, sa, sb, dth, path);
   dA_at(m, sa) = pc.dA;
-  S.E[p] = pc.E;
+  put(S.E[p], pc.E);
   return pc;
 }
 
@@ -712,7 +743,7 @@ __device__ inline void permute_record(const R& m, int slot, const int* from) {
   for (int k = 0; k < 5; ++k) {
     st_root(m, k, slot, z[from[k]]);
     st_dz(m, k, slot, d[from[k]]);
-    w_at(m, k, slot) = w[from[k]];
+    put(w_at(m, k, slot), w[from[k]]);
   }
 }
 
@@ -936,7 +967,7 @@ struct FsState {
 // the wave's global slice and continues there.
 template <int LCAP, bool MIXED, class Sorted, class R>
 __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 yc, double tol,
-                                          const R& m, FsLds<LCAP>& L, const Sorted& S,
+                                          const R& m, FsLds<LCAP, MIXED>& L, const Sorted& S,
                                           int lane, int n0, FsState& st) {
   const double rho = T.rho;
   // state in locals (written back once) so that it stays in registers
@@ -1081,7 +1112,7 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
         lane_sync<Sorted>();
         if (p < N && sh > 0) {
           S.th[p + sh] = vt;
-          S.E[p + sh] = ve;
+          put(S.E[p + sh], ve);
           S.sl[p + sh] = vs;
         }
         lane_sync<Sorted>();
@@ -1146,12 +1177,13 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
 // line).  Arguments and state go by value so that nothing of the hot path
 // has its address taken.
 template <int LCAP, bool MIXED>
-__device__ __attribute__((noinline)) FsState fs_rounds_spilled(Task T, double tol, WaveMem m,
-                                                               FsLds<LCAP>& L, int lane,
+__device__ __attribute__((noinline)) FsState fs_rounds_spilled(Task T, double tol,
+                                                               WaveMem<MIXED> m,
+                                                               FsLds<LCAP, MIXED>& L, int lane,
                                                                FsState st) {
   const Lens lens = make_lens(T.s, T.q);
   const c64 yc = cz(T.zx - lens.z2, T.zy);
-  const SortedG S{m.sth, m.sE, m.ssl, METHOD_CAP};
+  const SortedG<MIXED> S{m.sth, m.sE, m.ssl, METHOD_CAP};
   fs_rounds<LCAP, MIXED>(T, lens, yc, tol, m.G, L, S, lane, 0, st);
   return st;
 }
@@ -1160,14 +1192,15 @@ __device__ __attribute__((noinline)) FsState fs_rounds_spilled(Task T, double to
 // a source that would outgrow LDS has both copied to the wave's global
 // slice and continues there.
 template <int LCAP, bool MIXED>
-__device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem& gm, FsLds<LCAP>& L,
+__device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem<MIXED>& gm,
+                           FsLds<LCAP, MIXED>& L,
                            int lane, int n0) {
   const double tol = tol_stated * TOL_SAFETY;
   const Lens lens = make_lens(T.s, T.q);
   const c64 yc = cz(T.zx - lens.z2, T.zy);
   FsState st{0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, false};
-  const SortedL S{(ldouble*)L.th, (ldouble*)L.E, (luint16*)L.sl, LCAP};
-  const RecL R{(ldouble*)L.root, (ldouble*)L.dz, (ldouble*)L.w, (ldouble*)L.dA,
+  const SortedL<MIXED> S{(ldouble*)L.th, (lcorr_t<MIXED>*)L.E, (luint16*)L.sl, LCAP};
+  const RecL<MIXED> R{(ldouble*)L.root, (lcorr_t<MIXED>*)L.dz, (lcorr_t<MIXED>*)L.w, (ldouble*)L.dA,
                (luint32*)L.meta, LCAP};
   bool spilled = false;
   if (!fs_rounds<LCAP, MIXED>(T, lens, yc, tol, R, L, S, lane, n0, st)) {

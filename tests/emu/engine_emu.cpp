@@ -17,24 +17,29 @@ namespace {
 #endif
 constexpr int LCAP = EMU_LCAP;
 
-void run_wave(const Task& T, double tol, bool mixed, int n0, FsOut* out) {
-  std::vector<char> scratch((size_t)METHOD_CAP * kSlotBytes);
-  const WaveMem m = wave_mem(scratch.data(), 0);
-  auto* lds = new FsLds<LCAP>();
+template <bool MIXED>
+void run_wave_t(const Task& T, double tol, int n0, FsOut* out) {
+  std::vector<char> scratch((size_t)METHOD_CAP * kSlotBytesMax);
+  const WaveMem<MIXED> m = wave_mem<MIXED>(scratch.data(), 0);
+  auto* lds = new FsLds<LCAP, MIXED>();
   hip_emu::Wave wave;
   hip_emu::g_wave = &wave;
   std::vector<std::thread> th;
   for (int l = 0; l < hip_emu::kLanes; ++l) {
     th.emplace_back([&, l] {
       hip_emu::t_lane = l;
-      FsOut o = mixed ? fs_source<LCAP, true>(T, tol, m, *lds, l, n0)
-                      : fs_source<LCAP, false>(T, tol, m, *lds, l, n0);
+      FsOut o = fs_source<LCAP, MIXED>(T, tol, m, *lds, l, n0);
       if (l == 0) *out = o;
     });
   }
   for (auto& t : th) t.join();
   hip_emu::g_wave = nullptr;
   delete lds;
+}
+
+void run_wave(const Task& T, double tol, bool mixed, int n0, FsOut* out) {
+  if (mixed) run_wave_t<true>(T, tol, n0, out);
+  else run_wave_t<false>(T, tol, n0, out);
 }
 }  // namespace
 
