@@ -273,23 +273,38 @@ __device__ __forceinline__ c64 residual(const Lens& L, c64 y, c64 eta) {
 // (<= 1e-8 min(|eta|, |eta + s|)) and at least halves |R|; a ghost has no
 // nearby solution and its step is refused.  On return R holds the residual
 // of each (possibly polished) root.
-__device__ inline void polish_lens(const Lens& L, c64 y, c64 r[5], c64 R[5]) {
+// The residual, f' and J of a point all follow from the two inverses
+// 1/(eta + s) and 1/eta (1/conj(x) = conj(1/x)); on return J[k] is the
+// Jacobian at the final root.
+struct LensPoint {
+  c64 R, fp;
+  double J;
+};
+__device__ __forceinline__ LensPoint lens_point(const Lens& L, c64 y, c64 e) {
+  const c64 ia1 = cinv(e + L.s), ie = cinv(e);
+  LensPoint o;
+  o.R = y - e + L.m1 * cconj(ia1) + L.m2 * cconj(ie);
+  o.fp = L.m1 * (ia1 * ia1) + L.m2 * (ie * ie);
+  o.J = 1.0 - cnorm(o.fp);
+  return o;
+}
+
+__device__ inline void polish_lens(const Lens& L, c64 y, c64 r[5], c64 R[5], double J[5]) {
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const c64 e = r[k];
-    const c64 Rk = residual(L, y, e);
-    const c64 a1 = e + L.s;
-    const c64 fp = L.m1 * cinv(a1 * a1) + L.m2 * cinv(e * e);
-    const double J = 1.0 - cnorm(fp);
-    const c64 dz = (1.0 / J) * (Rk - cconj(fp) * cconj(Rk));
-    const double scale = fmin(cnorm(e), cnorm(a1));
-    R[k] = Rk;
+    const LensPoint p = lens_point(L, y, e);
+    const c64 dz = rcp64(p.J) * (p.R - cconj(p.fp) * cconj(p.R));
+    const double scale = fmin(cnorm(e), cnorm(e + L.s));
+    R[k] = p.R;
+    J[k] = p.J;
     if (cnorm(dz) <= 1e-16 * scale) {
       const c64 cand = e + dz;
-      const c64 Rc = residual(L, y, cand);
-      if (cnorm(Rc) < 0.25 * cnorm(Rk)) {
+      const LensPoint pc = lens_point(L, y, cand);
+      if (cnorm(pc.R) < 0.25 * cnorm(p.R)) {
         r[k] = cand;
-        R[k] = Rc;
+        R[k] = pc.R;
+        J[k] = pc.J;
       }
     }
   }
@@ -310,34 +325,44 @@ __device__ inline void polish_lens(const Lens& L, c64 y, c64 r[5], c64 R[5]) {
 constexpr double KGAP = TWK_KGAP;
 constexpr double EPS64 = 2.220446049250313e-16;
 
-__device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 R[5], Images& im) {
-  double aR[5], sg[5];
-  const double ay = cabs64(y);
+// sqrt to FP32 precision, for the rounding scale of the noise level only
+__device__ __forceinline__ double sqrt_rough(double x) {
+  return (double)__builtin_sqrtf((float)x);
+}
+
+__device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 R[5],
+                                const double J[5], Images& im) {
+  // squared residual lengths rank the roots; lengths are taken only where
+  // a value is needed (the two largest and the noise level)
+  double aR2[5], sg[5];
+  const double ay = sqrt_rough(cnorm(y));
   c64 Rs = cz(0.0, 0.0);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    aR[k] = cabs64(R[k]);
+    aR2[k] = cnorm(R[k]);
     Rs = Rs + R[k];
-    const double ae = cabs64(r[k]);
-    sg[k] = 64.0 * EPS64 * (ay + ae + L.m1 / cabs64(r[k] + L.s) + L.m2 / ae);
+    const double ae2 = cnorm(r[k]), as2 = cnorm(r[k] + L.s);
+    sg[k] = 64.0 * EPS64 *
+            (ay + sqrt_rough(ae2) + L.m1 * sqrt_rough(rcp64(as2)) + L.m2 * sqrt_rough(rcp64(ae2)));
   }
   // the two largest residuals (first index wins ties)
   int a = 0;
 #pragma unroll
   for (int k = 1; k < 5; ++k)
-    if (aR[k] > aR[a]) a = k;
+    if (aR2[k] > aR2[a]) a = k;
   int b = a == 0 ? 1 : 0;
 #pragma unroll
   for (int k = 0; k < 5; ++k)
-    if (k != a && aR[k] > aR[b]) b = k;
-  double noise = cabs64(Rs), ra = 0.0, rb = 0.0;
+    if (k != a && aR2[k] > aR2[b]) b = k;
+  double noise2 = cnorm(Rs), ra2 = 0.0, rb2 = 0.0;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    if (k != a && k != b) noise = fmax(noise, fmax(aR[k], sg[k]));
-    if (k == a) ra = aR[k];
-    if (k == b) rb = aR[k];
+    if (k != a && k != b) noise2 = fmax(noise2, fmax(aR2[k], sg[k] * sg[k]));
+    if (k == a) ra2 = aR2[k];
+    if (k == b) rb2 = aR2[k];
   }
-  const double margin = rb / noise;
+  const double ra = sqrt(ra2), rb = sqrt(rb2);
+  const double margin = rb / sqrt(noise2);
   const bool ghosts = margin > KGAP;
   im.margin = margin;
   im.flags = 0;
@@ -348,9 +373,7 @@ __device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 
   int key[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const c64 a1 = r[k] + L.s;
-    const c64 fp = L.m1 * cinv(a1 * a1) + L.m2 * cinv(r[k] * r[k]);
-    im.J[k] = 1.0 - cnorm(fp);
+    im.J[k] = J[k];
     im.z[k] = r[k];
     const bool g = ghosts && (k == a || k == b);
     key[k] = g ? 2 : (im.J[k] > 0.0 ? 0 : 1);
@@ -383,8 +406,9 @@ __device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 
 // Roots -> polished roots, residuals and classification.
 __device__ inline void finish_images(const Lens& L, c64 y, c64 r[5], Images& im) {
   c64 R[5];
-  polish_lens(L, y, r, R);
-  classify(L, y, r, R, im);
+  double J[5];
+  polish_lens(L, y, r, R, J);
+  classify(L, y, r, R, J, im);
 }
 
 __device__ __forceinline__ double point_mag(const Images& im) {
