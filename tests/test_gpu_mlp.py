@@ -278,3 +278,48 @@ def test_trained_weights_file(ctx, oracle):
     r = np.corrcoef(out[:, 0], l2)[0, 1]
     _log(f"trained budget: corr(pred, log2 N) = {r:.3f}")
     assert r > 0.5
+
+
+def test_trained_network_gain(ctx):
+    """What the trained budget gains on the bench workload (1024 sets x 2000
+    epochs, tol 1e-4): at one launch tuning for both paths (LDS capacity 128
+    samples, the most resident waves, budget shift 0) the learned path needs
+    fewer limb samples than the plain mixed path and less time per call,
+    its learned stage (features and inference) included.  Accuracy of the
+    learned path is checked by test_learned_path_parity."""
+    import torch
+    from paper_2501_03322_amd import inputs, twk
+    path = os.path.join(os.path.dirname(twk.__file__), "weights", "mlp_budget.bin")
+    if not os.path.exists(path):
+        pytest.skip("no trained weights committed")
+    ctx.mlp_load(path)
+    c = inputs.batched_curves()
+    dev = torch.device("cuda", 0)
+    args = [torch.as_tensor(a, device=dev) for a in (c.s, c.q, c.u0, c.alpha, c.rho, c.tau)]
+    out = ctx.alloc_out(c.nsets * c.nepochs)
+    mx = 1
+    for w in range(2, 33):
+        try:
+            ctx.set_tuning(lds_cap=128, waves_per_cu=w, budget_shift=0.0)
+            mx = w
+        except twk.TwkError:
+            break
+    ctx.set_tuning(lds_cap=128, waves_per_cu=mx, budget_shift=0.0)
+    ctx.enable_timing(True)
+
+    def run(mode):
+        ctx.lightcurves(*args, c.tol, mode=mode, out=out)
+        ctx.sync()
+        ms = []
+        for _ in range(3):
+            ctx.lightcurves(*args, c.tol, mode=mode, out=out)
+            ms.append(ctx.kernel_times()["total_ms"])
+        return float(np.median(ms)), ctx.stats()["samples"]
+
+    t_plain, n_plain = run(twk.MODE_MIXED)
+    t_learn, n_learn = run(twk.MODE_MLP | twk.MODE_MIXED)
+    ctx.enable_timing(False)
+    _log(f"waves/CU {mx}: plain {t_plain:.2f} ms, {n_plain} samples; "
+         f"learned {t_learn:.2f} ms, {n_learn} samples")
+    assert n_learn <= 0.98 * n_plain
+    assert t_learn < 0.95 * t_plain
