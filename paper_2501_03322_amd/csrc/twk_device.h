@@ -325,9 +325,10 @@ __device__ inline void polish_lens(const Lens& L, c64 y, c64 r[5], c64 R[5], dou
 constexpr double KGAP = TWK_KGAP;
 constexpr double EPS64 = 2.220446049250313e-16;
 
-// sqrt to FP32 precision, for the rounding scale of the noise level only
+// sqrt to FP32 precision (the hardware square root, about 1 ulp), for the
+// rounding scale of the noise level only
 __device__ __forceinline__ double sqrt_rough(double x) {
-  return (double)__builtin_sqrtf((float)x);
+  return (double)__builtin_amdgcn_sqrtf((float)x);
 }
 
 __device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 R[5],

@@ -19,6 +19,7 @@
 #define TWK_LDS_AS
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))
 #define __builtin_amdgcn_rcpf(x) (1.0f / (x))
+#define __builtin_amdgcn_sqrtf(x) std::sqrt((float)(x))
 
 namespace hip_emu {
 constexpr int kLanes = 64;
