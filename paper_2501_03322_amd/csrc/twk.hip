@@ -94,8 +94,13 @@ struct PsResult {
 __device__ inline double pair_stat(const Lens& L, const Images& im) {
   const int npos = __popc(im.par);
   double best = INFINITY;
-  for (int a = 0; a < npos; ++a)
-    for (int b = npos; b < im.n; ++b) {
+  // static indices (the image record stays in registers); a pair (a, b) is
+  // positive-negative when a < npos <= b < n
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a + 1; b < 5; ++b) {
+      if (!(a < npos && b >= npos && b < im.n)) continue;
       const c64 mid = 0.5 * (im.z[a] + im.z[b]);
       const c64 a1 = mid + L.s;
       const c64 f2 = -2.0 * (L.m1 * cinv(a1 * a1 * a1) + L.m2 * cinv(mid * mid * mid));
