@@ -240,3 +240,56 @@ def test_magnification_map(ctx, oracle):
             iy, ix = divmod(int(p), n)
             rm = oracle.finite_mag(s, q, [x[ix]], [y[iy]], rho, oracle.JUDGE_TOL, oracle.judge_cfg())[0][0]
             assert abs(mag[p] / rm - 1) <= GATE, (n, ix, iy, mag[p], rm)
+
+
+def test_large_limb_darkened_batch_full_size(ctx, oracle):
+    """The high-cadence limb-darkened batch at its full size (16384 sets x
+    8000 epochs, 10 annuli) in one call on the headline path (learned budget
+    + mixed precision, the committed weights when present) at the launch
+    tuning the benchmark's autotuner picks on this chip (LDS capacity 128,
+    the most resident waves, budget shift 0): every value finite, and
+    sampled epochs against the oracle's annulus combination."""
+    import os
+    import time
+    from paper_2501_03322_amd import inputs, twk
+    c = inputs.large_ld_curves()
+    n = c.nsets * c.nepochs
+    mode = twk.MODE_MIXED
+    wpath = os.path.join(os.path.dirname(twk.__file__), "weights", "mlp_budget.bin")
+    if os.path.exists(wpath):
+        ctx.mlp_load(wpath)
+        mode |= twk.MODE_MLP
+    saved = ctx.get_tuning()
+    mx = 1
+    for w in range(2, 33):
+        try:
+            ctx.set_tuning(lds_cap=128, waves_per_cu=w, budget_shift=0.0)
+            mx = w
+        except twk.TwkError:
+            break
+    ctx.set_tuning(lds_cap=128, waves_per_cu=mx, budget_shift=0.0)
+    try:
+        _log(f"limb darkened full size: {c.nsets} x {c.nepochs} x 10 annuli, mode {mode}")
+        t0 = time.perf_counter()
+        mag, err, ns, fl = ctx.lightcurves(c.s, c.q, c.u0, c.alpha, c.rho, c.tau, 1e-4, mode,
+                                           gamma=c.gamma, n_annuli=10)
+        ctx.sync()
+        _log(f"  call done in {time.perf_counter() - t0:.1f} s; stats {ctx.stats()}")
+        mag, fl = _np(mag), _np(fl)
+        del err, ns
+    finally:
+        ctx.set_tuning(**saved.as_dict())
+    assert mag.shape == (n,) and np.all(np.isfinite(mag))
+    fs = np.nonzero((fl & 1) == 0)[0]
+    pt = np.nonzero((fl & 1) != 0)[0]
+    _log(f"  contour epochs {fs.size} of {n}")
+    rng = np.random.default_rng(16384)
+    pick = np.concatenate([rng.choice(fs, min(12, fs.size), replace=False),
+                           rng.choice(pt, min(6, pt.size), replace=False)])
+    for i in pick:
+        k, j = divmod(int(i), c.nepochs)
+        zx, zy = oracle.trajectory(c.u0[k], c.alpha[k], c.tau[j:j + 1])
+        mu_k = [oracle.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k] * np.sqrt(a / 10), oracle.JUDGE_TOL,
+                                  oracle.judge_cfg())[0][0] for a in range(1, 11)]
+        ref = oracle.ld_combine(c.gamma[k], mu_k)
+        assert abs(mag[i] / ref - 1) <= GATE, (i, k, j, mag[i], ref)
