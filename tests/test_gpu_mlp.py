@@ -323,3 +323,48 @@ def test_trained_network_gain(ctx):
          f"learned {t_learn:.2f} ms, {n_learn} samples")
     assert n_learn <= 0.98 * n_plain
     assert t_learn < 0.95 * t_plain
+
+
+def test_learned_path_on_evaluation_batch(ctx, oracle):
+    """The held-out evaluation batch at full size (1024 sets x 4000 epochs,
+    seed 3, not used in training) on the learned + mixed path with the
+    committed weights: sampled contour and point epochs meet the gate against
+    the oracle judge, and the budget needs fewer limb samples than the plain
+    mixed path at the same tuning."""
+    import torch
+    from paper_2501_03322_amd import inputs, twk
+    path = os.path.join(os.path.dirname(twk.__file__), "weights", "mlp_budget.bin")
+    if not os.path.exists(path):
+        pytest.skip("no trained weights committed")
+    ctx.mlp_load(path)
+    c = inputs.evaluation_curves()
+    dev = torch.device("cuda", 0)
+    args = [torch.as_tensor(a, device=dev) for a in (c.s, c.q, c.u0, c.alpha, c.rho, c.tau)]
+    out = ctx.alloc_out(c.nsets * c.nepochs)
+    mx = 1
+    for w in range(2, 33):
+        try:
+            ctx.set_tuning(lds_cap=128, waves_per_cu=w, budget_shift=0.0)
+            mx = w
+        except twk.TwkError:
+            break
+    ctx.set_tuning(lds_cap=128, waves_per_cu=mx, budget_shift=0.0)
+    ctx.lightcurves(*args, c.tol, mode=twk.MODE_MIXED, out=out)
+    ctx.sync()
+    n_plain = ctx.stats()["samples"]
+    ctx.lightcurves(*args, c.tol, mode=twk.MODE_MLP | twk.MODE_MIXED, out=out)
+    ctx.sync()
+    n_learn = ctx.stats()["samples"]
+    mag, fl = out[0].cpu().numpy(), out[3].cpu().numpy()
+    _log(f"evaluation batch: samples plain {n_plain}, learned {n_learn}")
+    assert np.all(np.isfinite(mag))
+    assert n_learn < n_plain
+    fs = np.nonzero((fl & 1) == 0)[0]
+    pt = np.nonzero((fl & 1) != 0)[0]
+    rng = np.random.default_rng(3)
+    for i in np.concatenate([rng.choice(fs, 30, replace=False), rng.choice(pt, 10, replace=False)]):
+        k, j = divmod(int(i), c.nepochs)
+        zx, zy = oracle.trajectory(c.u0[k], c.alpha[k], c.tau[j:j + 1])
+        rm = oracle.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], oracle.JUDGE_TOL,
+                               oracle.judge_cfg())[0][0]
+        assert abs(mag[i] / rm - 1) <= GATE, (i, k, j, mag[i], rm)
