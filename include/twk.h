@@ -90,8 +90,8 @@ int twk_point_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *zet
  * point-source test may return the point value (flag bit 0).  With
  * TWK_MODE_MLP the learned budget (weights from twk_mlp_set/load/train)
  * sets each contour's starting grid (a multiple of 64, at most 512 uniform
- * samples) and the queue runs sources longest first; the stop rule and the
- * tolerance are unchanged.
+ * samples and at most the tuned LDS capacity) and the queue runs sources
+ * longest first; the stop rule and the tolerance are unchanged.
  * Errors: TWK_EINVAL for s, q, rho, tol <= 0 or non-finite, n < 0, NULL
  * pointers or unknown mode bits; TWK_ENOMLP for TWK_MODE_MLP without
  * weights; TWK_ENOMEM / TWK_EDEVICE. */

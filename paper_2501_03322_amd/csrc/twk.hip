@@ -6,14 +6,21 @@
 // Pipeline of a finite-source call (all on the caller's stream):
 //   k_reset      clear the queue counters (a kernel, not a memset, so that
 //                the sequence may be captured in a graph)
-//   k_prep/k_lc  one lane per source: centre (and stencil) point solves,
-//                point-source adequacy test (Sec. 2.3); adequate sources get
-//                the point value, the rest are appended to the task queue
-//                with their centre roots (wave-aggregated atomics)
-//   k_fs<C>      persistent: each 64-lane wave pops tasks from the queue and
-//                runs the adaptive contour integration, keeping up to C limb
-//                samples' sorted arrays in LDS and continuing in its global
-//                slice for larger sources (method cap 4096).
+//   k_prep/k_lc  one lane per source (k_lc: a run of four consecutive
+//                epochs, each centre solve warm-started from the previous
+//                one): centre and stencil point solves, point-source
+//                adequacy test (Sec. 2.3); adequate sources get the point
+//                value, the rest are appended to the task queue with their
+//                centre roots (wave-aggregated atomics)
+//   mlp::k_infer, k_budget, k_place   (learned path) inference on the
+//                features the point pass wrote, starting grids, longest-first
+//                queue order
+//   k_fs<C, MIXED>  persistent: each 64-lane wave pops tasks from the queue
+//                and runs the adaptive contour integration, keeping up to C
+//                limb samples (records and sorted arrays) in LDS and
+//                continuing in its global slice for larger sources (method
+//                cap 4096); MIXED selects FP32 bulk root sweeps and FP32
+//                storage of the correction-term inputs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
