@@ -66,6 +66,46 @@ __device__ __forceinline__ c32 cinv(c32 b) {
   return c32{b.x * r, -b.y * r};
 }
 
+// ---------------------------------------------------------------- angles
+// sin and cos of a limb angle (|theta| <= 8; the engine's angles lie in
+// [0, 2 pi]).  Cody-Waite reduction by pi/2: theta = k pi/2 + r with pi/2
+// split into three doubles whose first two carry 33 significant bits, so
+// that k times each part is exact for the few quadrants used and r is exact
+// to about 1e-17; then the Taylor series of sin r through r^15 and of cos r
+// through r^16 on |r| <= pi/4 (truncation below 1e-16 relative), by Horner's
+// rule in r^2.  About one ulp; the library routine carries a reduction for
+// any argument, which this path does not need.
+__device__ __forceinline__ void limb_sincos(double theta, double* sn, double* cs) {
+  constexpr double PIO2_1 = 1.5707963267341256;     // pi/2, first 33 bits
+  constexpr double PIO2_2 = 6.077100506303966e-11;  // next 33 bits
+  constexpr double PIO2_3 = 2.0222662487959506e-21; // remainder
+  const double kf = __builtin_rint(theta * 0.6366197723675814);
+  const int k = (int)kf;
+  const double r = ((theta - kf * PIO2_1) - kf * PIO2_2) - kf * PIO2_3;
+  const double r2 = r * r;
+  // 1/n! with alternating signs
+  double ps = 1.0 / 1307674368000.0;   // r^15: -1/15!, sign applied below
+  ps = __builtin_fma(ps, -r2, 1.0 / 6227020800.0);
+  ps = __builtin_fma(ps, -r2, 1.0 / 39916800.0);
+  ps = __builtin_fma(ps, -r2, 1.0 / 362880.0);
+  ps = __builtin_fma(ps, -r2, 1.0 / 5040.0);
+  ps = __builtin_fma(ps, -r2, 1.0 / 120.0);
+  ps = __builtin_fma(ps, -r2, 1.0 / 6.0);
+  const double s = __builtin_fma(-ps * r2, r, r);
+  double pc = 1.0 / 20922789888000.0;  // r^16: +1/16!
+  pc = __builtin_fma(pc, -r2, 1.0 / 87178291200.0);
+  pc = __builtin_fma(pc, -r2, 1.0 / 479001600.0);
+  pc = __builtin_fma(pc, -r2, 1.0 / 3628800.0);
+  pc = __builtin_fma(pc, -r2, 1.0 / 40320.0);
+  pc = __builtin_fma(pc, -r2, 1.0 / 720.0);
+  pc = __builtin_fma(pc, -r2, 1.0 / 24.0);
+  pc = __builtin_fma(pc, -r2, 0.5);
+  const double c = __builtin_fma(-pc, r2, 1.0);
+  const int q = k & 3;
+  *sn = q == 0 ? s : (q == 1 ? c : (q == 2 ? -s : -c));
+  *cs = q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
+}
+
 // ---------------------------------------------------------------- lens
 // Sec. 2.1: masses normalised by the total mass; m1 = 1/(1+q), m2 = q/(1+q);
 // lens 2 at z2 = s/(1+q) in the centre-of-mass frame.

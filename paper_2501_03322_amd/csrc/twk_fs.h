@@ -190,7 +190,7 @@ template <bool MIXED, class R>
 __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double theta, c64 r[5],
                                        const R& m, int slot, uint32_t* fl) {
   double sn, cs;
-  sincos(theta, &sn, &cs);
+  limb_sincos(theta, &sn, &cs);
   const c64 y = yc + rho * cz(cs, sn);
   c64 c[6];
   coefficients(L, y, c);

@@ -78,6 +78,11 @@ int emu_finite_mag(double s, double q, double zx, double zy, double rho, double 
   return 0;
 }
 
+// sin and cos of n limb angles by the device routine
+void emu_limb_sincos(int n, const double* theta, double* sn, double* cs) {
+  for (int i = 0; i < n; ++i) limb_sincos(theta[i], &sn[i], &cs[i]);
+}
+
 int emu_point(double s, double q, double zx, double zy, double* mag, int* n, unsigned* flags,
               double* img10) {
   const Lens L = make_lens(s, q);
