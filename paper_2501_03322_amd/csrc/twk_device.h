@@ -49,6 +49,11 @@ __device__ __forceinline__ double rcp64(double a) {
   e = __builtin_fma(-a, r, 1.0);
   return __builtin_fma(r, e, r);
 }
+// a * b + c with four fused multiply-adds
+__device__ __forceinline__ c64 cfma(c64 a, c64 b, c64 c) {
+  return c64{__builtin_fma(a.x, b.x, __builtin_fma(-a.y, b.y, c.x)),
+             __builtin_fma(a.x, b.y, __builtin_fma(a.y, b.x, c.y))};
+}
 __device__ __forceinline__ c64 cinv(c64 b) {
   double r = rcp64(cnorm(b));
   return c64{b.x * r, -b.y * r};
@@ -61,6 +66,10 @@ __device__ __forceinline__ c32 operator*(c32 a, c32 b) {
   return c32{__builtin_fmaf(a.x, b.x, -a.y * b.y), __builtin_fmaf(a.x, b.y, a.y * b.x)};
 }
 __device__ __forceinline__ float cnorm(c32 a) { return __builtin_fmaf(a.x, a.x, a.y * a.y); }
+__device__ __forceinline__ c32 cfma(c32 a, c32 b, c32 c) {
+  return c32{__builtin_fmaf(a.x, b.x, __builtin_fmaf(-a.y, b.y, c.x)),
+             __builtin_fmaf(a.x, b.y, __builtin_fmaf(a.y, b.x, c.y))};
+}
 __device__ __forceinline__ c32 cinv(c32 b) {
   float r = __builtin_amdgcn_rcpf(cnorm(b));
   return c32{b.x * r, -b.y * r};
@@ -144,12 +153,12 @@ __device__ __forceinline__ void coefficients(const Lens& L, c64 y, c64 c[6]) {
 // sample, cold starts from a circle.  The paper delegates this step to the
 // Skowron & Gould solver; any all-roots method of full precision serves.
 __device__ __forceinline__ void horner64(const c64 c[6], c64 x, c64& p, c64& d) {
-  p = c[5];
-  d = cz(0.0, 0.0);
+  d = c[5];
+  p = cfma(c[5], x, c[4]);
 #pragma unroll
-  for (int k = 4; k >= 0; --k) {
-    d = d * x + p;
-    p = p * x + c[k];
+  for (int k = 3; k >= 0; --k) {
+    d = cfma(d, x, p);
+    p = cfma(p, x, c[k]);
   }
 }
 
@@ -181,7 +190,6 @@ __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
       const c64 x = r[0];
       c64 p, d;
       horner64(c, x, p, d);
-      const c64 ratio = cdiv(p, d);
       c64 rep = cz(0.0, 0.0);
       const double inr = rcp64(fmax(cnorm(x), 1e-300));
       double n2min = 1e300;
@@ -194,7 +202,8 @@ __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
         rep = rep + cz(dd.x * ir, -dd.y * ir);
       }
       closest = fmin(closest, n2min * inr);
-      c64 w = cdiv(ratio, cz(1.0, 0.0) - ratio * rep);
+      // Newton's ratio deflated against the other roots, in one division
+      c64 w = p * cinv(cfma(-p, rep, d));
       double nw = cnorm(w);
       if (!(nw < 1e300)) {  // vanishing derivative or coincident iterates
         const double a = 1.0 + sqrt(cnorm(x));
@@ -241,17 +250,16 @@ __device__ inline int aberth32(const c64 c64c[6], c64 r64[5], int maxit) {
 #pragma unroll 1
     for (int k = 0; k < 5; ++k) {
       const c32 x = r[0];
-      c32 p = c[5], d = c32{0.f, 0.f};
+      c32 d = c[5], p = cfma(c[5], x, c[4]);
 #pragma unroll
-      for (int j = 4; j >= 0; --j) {
-        d = d * x + p;
-        p = p * x + c[j];
+      for (int j = 3; j >= 0; --j) {
+        d = cfma(d, x, p);
+        p = cfma(p, x, c[j]);
       }
-      const c32 ratio = p * cinv(d);
       c32 rep = c32{0.f, 0.f};
 #pragma unroll
       for (int j = 1; j < 5; ++j) rep = rep + cinv(x - r[j]);
-      c32 w = ratio * cinv(c32{1.f, 0.f} - ratio * rep);
+      c32 w = p * cinv(cfma(c32{-p.x, -p.y}, rep, d));
       float nw = cnorm(w);
       if (!(nw < 1e30f)) {
         w = c32{1e-3f, -7e-4f};
