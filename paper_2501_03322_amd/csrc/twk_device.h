@@ -181,7 +181,8 @@ __device__ __forceinline__ void cold_start(const c64 c[6], c64 r[5]) {
 // Returns the number of sweeps used (maxit + 1 when not converged).
 __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
   for (int it = 0; it < maxit; ++it) {
-    double worst = 0.0, closest = 1.0;
+    double worst = 0.0;
+    bool close = false;  // some root within 1e-3 (relative) of another
     // Gauss-Seidel order: root 0 is corrected against roots 1..4, then the
     // roots rotate by one place; after five steps the order is restored.
     // Only static register indices appear.
@@ -191,7 +192,6 @@ __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
       c64 p, d;
       horner64(c, x, p, d);
       c64 rep = cz(0.0, 0.0);
-      const double inr = rcp64(fmax(cnorm(x), 1e-300));
       double n2min = 1e300;
 #pragma unroll
       for (int j = 1; j < 5; ++j) {
@@ -201,12 +201,12 @@ __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
         const double ir = rcp64(n2);
         rep = rep + cz(dd.x * ir, -dd.y * ir);
       }
-      closest = fmin(closest, n2min * inr);
+      close = close || n2min <= 1e-6 * fmax(cnorm(x), 1e-300);
       // Newton's ratio deflated against the other roots, in one division
       c64 w = p * cinv(cfma(-p, rep, d));
       double nw = cnorm(w);
       if (!(nw < 1e300)) {  // vanishing derivative or coincident iterates
-        const double a = 1.0 + sqrt(cnorm(x));
+        const double a = 1.0 + fabs(x.x) + fabs(x.y);  // step scale ~ 1 + |x|
         w = cz(-1e-3 * a, 7e-4 * a);
         nw = 1.0;
         worst = 1.0;
@@ -220,7 +220,7 @@ __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
       r[3] = r[4];
       r[4] = xn;
     }
-    if (worst < 1e-28 || (worst < 1e-12 && closest > 1e-6)) return it + 1;
+    if (worst < 1e-28 || (worst < 1e-12 && !close)) return it + 1;
   }
   return maxit + 1;
 }
