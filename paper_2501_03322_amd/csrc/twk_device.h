@@ -35,6 +35,21 @@ __device__ __forceinline__ c64 operator-(c64 a, double s) { return c64{a.x - s, 
 __device__ __forceinline__ c64 cconj(c64 a) { return c64{a.x, -a.y}; }
 __device__ __forceinline__ double cnorm(c64 a) { return __builtin_fma(a.x, a.x, a.y * a.y); }
 __device__ __forceinline__ double cabs64(c64 a) { return sqrt(cnorm(a)); }
+
+// Square root of x >= 0 for lengths that only rank candidates or meet a
+// threshold (linking distances, residual lengths): Goldschmidt's iteration
+// from the hardware reciprocal square root (one coupled step, then one
+// Newton correction), within about one ulp; x = 0 gives 0.
+__device__ __forceinline__ double sqrt_fast(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  g = __builtin_fma(__builtin_fma(-g, g, x), h, g);
+  return x > 0.0 ? g : 0.0;
+}
+__device__ __forceinline__ double cabs_fast(c64 a) { return sqrt_fast(cnorm(a)); }
 // a ^ b = Im(conj(a) b);  a . b = Re(conj(a) b)
 __device__ __forceinline__ double cwedge(c64 a, c64 b) { return __builtin_fma(a.x, b.y, -a.y * b.x); }
 __device__ __forceinline__ double cdot(c64 a, c64 b) { return __builtin_fma(a.x, b.x, a.y * b.y); }
@@ -410,8 +425,8 @@ __device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 
     if (k == a) ra2 = aR2[k];
     if (k == b) rb2 = aR2[k];
   }
-  const double ra = sqrt(ra2), rb = sqrt(rb2);
-  const double margin = rb / sqrt(noise2);
+  const double ra = sqrt_fast(ra2), rb = sqrt_fast(rb2);
+  const double margin = rb / sqrt_fast(noise2);
   const bool ghosts = margin > KGAP;
   im.margin = margin;
   im.flags = 0;

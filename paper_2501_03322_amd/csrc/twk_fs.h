@@ -249,7 +249,7 @@ __device__ __forceinline__ uint32_t inject_static(const c64* za, const c64* zb) 
 #pragma unroll
   for (int i = 0; i < KA; ++i)
 #pragma unroll
-    for (int j = 0; j < KB; ++j) d[i][j] = cabs64(za[i] - zb[j]);
+    for (int j = 0; j < KB; ++j) d[i][j] = cabs_fast(za[i] - zb[j]);
   double best = 1e308;
   uint32_t code = 0;
 #pragma unroll
@@ -445,7 +445,7 @@ __device__ __forceinline__ int link_pattern(uint32_t ma, uint32_t mb) {
 // Distance of a pair of the padded lists in the unified linking below
 // (0 unless both entries are present).
 __device__ __forceinline__ double pair_dist(c64 a, bool pa, c64 b, bool pb) {
-  return (pa && pb) ? cabs64(a - b) : 0.0;
+  return (pa && pb) ? cabs_fast(a - b) : 0.0;
 }
 
 // Area and error of the interval between slots sa and sb, dth apart.
