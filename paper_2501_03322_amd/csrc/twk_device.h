@@ -54,9 +54,9 @@ __device__ __forceinline__ double cabs_fast(c64 a) { return sqrt_fast(cnorm(a));
 __device__ __forceinline__ double cwedge(c64 a, c64 b) { return __builtin_fma(a.x, b.y, -a.y * b.x); }
 __device__ __forceinline__ double cdot(c64 a, c64 b) { return __builtin_fma(a.x, b.x, a.y * b.y); }
 
-// Reciprocal of a positive double to full precision: hardware estimate plus
-// two Newton steps (each squares the relative error).  The quotients on the
-// hot path never need IEEE rounding, only full precision.
+// Reciprocal of a finite nonzero double to full precision: hardware
+// estimate plus two Newton steps (each squares the relative error).  The
+// quotients on the hot path never need IEEE rounding, only full precision.
 __device__ __forceinline__ double rcp64(double a) {
   double r = __builtin_amdgcn_rcp(a);
   double e = __builtin_fma(-a, r, 1.0);
@@ -426,7 +426,7 @@ __device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 
     if (k == b) rb2 = aR2[k];
   }
   const double ra = sqrt_fast(ra2), rb = sqrt_fast(rb2);
-  const double margin = rb / sqrt_fast(noise2);
+  const double margin = rb * rcp64(sqrt_fast(noise2));
   const bool ghosts = margin > KGAP;
   im.margin = margin;
   im.flags = 0;
@@ -503,7 +503,7 @@ __device__ __forceinline__ void limb_derivs(const Lens& L, c64 eta, double J, c6
   c64 ia2 = ia1 * ia1, ie2 = ie * ie;
   c64 fp = L.m1 * ia2 + L.m2 * ie2;
   c64 fpp = -2.0 * (L.m1 * (ia2 * ia1) + L.m2 * (ie2 * ie));
-  double iJ = 1.0 / J;
+  const double iJ = rcp64(J);
   dz = iJ * (zp1 - cconj(fp) * cconj(zp1));
   w = iJ * (rho * rho + ((dz * dz) * zp1 * fpp).y);
 }

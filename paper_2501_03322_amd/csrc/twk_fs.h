@@ -332,7 +332,7 @@ __device__ __forceinline__ void add_link(const R& m, int sa, int ia, int sb, int
   out.dA += par * (dAt + dAp);
   const double E1 = fabs(wa - wb) * dth3 * (1.0 / 48.0);
   const double ch2 = cnorm(za - zb);
-  const double E2 = 1.5 * fabs(dAp * (ch2 / (dth2 * fabs(cdot(da, db))) - 1.0));
+  const double E2 = 1.5 * fabs(dAp * (ch2 * rcp64(dth2 * fabs(cdot(da, db))) - 1.0));
   const double E3 = 0.1 * fabs(dAp) * dth2;
   const double E4 = fabs(dAp1 - dAp2);
   out.E += E1 + E2 + E3 + E4;
