@@ -36,10 +36,10 @@ METRIC = "finite-source magnifications/sec at \u22641e-4 rel. err, learned-batch
 # root sweep (all five roots of one limb point), one limb sample outside the
 # sweeps (coefficients, lens-equation polish, residual classification,
 # derivatives, angle), one interval link (assignment, area, error).
-F_SWEEP64 = 1050.0
-F_SWEEP32 = 810.0
-F_SAMPLE = 1550.0
-F_INTERVAL = 400.0
+F_SWEEP64 = 925.0
+F_SWEEP32 = 715.0
+F_SAMPLE = 1285.0
+F_INTERVAL = 300.0
 
 # MI355X vector peak: 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 # FP64 FMA runs at full rate; FP32 without packed instructions (disabled for
