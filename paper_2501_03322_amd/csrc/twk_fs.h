@@ -8,13 +8,14 @@
 // MI355X mapping.  One 64-lane wavefront owns one extended source.  Each
 // round, lane j solves one new limb point (coefficients, roots, residual
 // classification, limb derivatives) in registers and writes the sample
-// record to the wave's slice of a global scratch buffer (SoA, one slot per
-// sample, slots in creation order; L2-resident).  The sorted order of the
-// limb angles lives in LDS: th[] (angle), E[] (error of the interval that
-// starts there) and sl[] (slot), 18 bytes per sample.  The area total is
-// kept incrementally (compensated) from the intervals that change; the
-// error total, the tolerance-subtracted weights, their prefix sum and the
-// quantile inversion are one pass of wave-wide shuffle scans over 64-wide
+// record (SoA, one slot per sample, slots in creation order) and its place
+// in the sorted order of the limb angles (th[] angle, E[] error of the
+// interval that starts there, sl[] slot) into the wave's LDS block.  A
+// source that would outgrow the block has both copied to the wave's slice
+// of global memory and continues there.  The area total is kept
+// incrementally (compensated) from the intervals that change; the error
+// total, the tolerance-subtracted weights, their prefix sum and the
+// quantile inversion are one pass of wave-wide DPP scans over 64-wide
 // strips of the sorted arrays.  The 64 new samples are merged into the
 // sorted arrays by an in-place descending-strip move.  Only intervals that
 // touch a new sample are relinked.
@@ -23,8 +24,8 @@
 
 #include "twk_device.h"
 
-// Address spaces of the engine's pointers: sample records and spill copies
-// in global memory, sorted arrays in LDS.  Typed pointers let the compiler
+// Address spaces of the engine's pointers: records and sorted arrays in LDS,
+// or (sources that outgrew LDS) in global memory.  Typed pointers let the compiler
 // emit global and LDS instructions instead of generic (flat) ones, which
 // wait on both memory counters and route LDS traffic through the vector
 // memory pipeline.  (A CPU emulation build defines both as nothing.)
@@ -655,7 +656,8 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 }
 
 // ---------------------------------------------------------------- engine
-// LDS of one wave: the sorted arrays for sources of up to LCAP samples.
+// LDS of one wave: sample records and sorted arrays for sources of up to
+// LCAP samples (correction-term inputs in FP32 on the mixed path).
 template <int LCAP, bool MIXED>
 struct FsLds {
   double root[5 * LCAP * 2];  // records of the first LCAP slots (see RecView)
@@ -669,9 +671,9 @@ struct FsLds {
   int ivl[NNEW];      // old interval index of each accepted new sample
 };
 
-// The sorted arrays in use: the LDS copy (D = ldouble, U = luint16), or,
+// The sorted arrays in use: the LDS copy (ldouble/lcorr_t/luint16), or,
 // once a source outgrows it, the spill copy in the wave's global slice
-// (D = gdouble, U = guint16).
+// (gdouble/gcorr_t/guint16).
 template <class D, class F, class U, bool LDS>
 struct SortedT {
   static constexpr bool kLds = LDS;
