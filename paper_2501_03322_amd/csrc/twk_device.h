@@ -242,9 +242,9 @@ __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
 
 // Mixed precision: the bulk sweeps in FP32 (polynomial scaled by 1/c5 so
 // that FP32 keeps its range) from a start given in FP64; the caller then
-// polishes with FP64 sweeps.  FP32 stops at a relative correction of 1e-4:
-// the root is then accurate to FP32's rounding level, and the first FP64
-// sweep takes it to full precision (cubic convergence).  A lane that has not
+// polishes with FP64 sweeps.  FP32 stops at a relative correction of 1e-3:
+// by cubic convergence the root is then accurate to about FP32's rounding
+// level, and the first FP64 sweep takes it to full precision.  A lane that has not
 // got there within the sweep cap (near-double roots converge linearly and
 // FP32 rounding stalls them) hands over to the FP64 sweeps, which cost the
 // same on a VALU without packed FP32 and can finish the job; the cap keeps
@@ -289,7 +289,7 @@ __device__ inline int aberth32(const c64 c64c[6], c64 r64[5], int maxit) {
       r[3] = r[4];
       r[4] = xn;
     }
-    if (worst < 1e-8f) {
+    if (worst < 1e-6f) {
       ++it;
       break;
     }
