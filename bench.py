@@ -76,9 +76,12 @@ def run_path(ctx, dev, c, mode, steps, warmup, label):
         fs_ms.append(kt["fs_ms"])
         tot_ms.append(kt["total_ms"])
         mlp_ms.append(kt["mlp_ms"])
-        log(f"[{label}] step {k + 1}/{steps}: {kt['total_ms']:.2f} ms (contour kernel {kt['fs_ms']:.2f} ms,"
-            f" point pass {kt['ps_ms']:.2f} ms, learned stage {kt['mlp_ms']:.2f} ms,"
-            f" rest {kt['rest_ms']:.2f} ms)")
+        if "graph" in label:  # a replayed call is timed as a whole
+            log(f"[{label}] step {k + 1}/{steps}: {kt['total_ms']:.2f} ms")
+        else:
+            log(f"[{label}] step {k + 1}/{steps}: {kt['total_ms']:.2f} ms (contour kernel {kt['fs_ms']:.2f} ms,"
+                f" point pass {kt['ps_ms']:.2f} ms, learned stage {kt['mlp_ms']:.2f} ms,"
+                f" rest {kt['rest_ms']:.2f} ms)")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = ctx.stats()
@@ -128,15 +131,36 @@ def lib_digest(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
+def device_code_digest(path):
+    """sha256 of the library's device code: the `.hip_fatbin` section of the
+    ELF shared object, which holds every kernel's gfx950 code object and no
+    host code (a host-only change leaves it unchanged)."""
+    import hashlib
+    import struct
+    with open(path, "rb") as f:
+        b = f.read()
+    if b[:4] != b"\x7fELF" or b[4] != 2:
+        raise ValueError(f"{path}: not a 64-bit ELF file")
+    shoff, = struct.unpack_from("<Q", b, 0x28)
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", b, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQIIQQ", b, shoff + i * shentsize) for i in range(shnum)]
+    names = secs[shstrndx][4]
+    for name_off, _, _, _, off, size, *_ in secs:
+        end = b.index(b"\0", names + name_off)
+        if b[names + name_off:end] == b".hip_fatbin":
+            return hashlib.sha256(b[off:off + size]).hexdigest()
+    raise ValueError(f"{path}: no .hip_fatbin section")
+
+
 def measured_traffic(lib_path):
     """HBM bytes per launch of the contour kernel from the committed counter
     runs (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
-    valid only for the library build they were taken on."""
+    valid only while the library's device code is the one they were taken on."""
     if not os.path.exists(TRAFFIC):
         return None
     with open(TRAFFIC) as f:
         t = json.load(f)
-    if t.get("lib_sha256") != lib_digest(lib_path):
+    if t.get("device_code_sha256") != device_code_digest(lib_path):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -172,7 +196,8 @@ def pmc_summary(fetch_dir, write_dir):
     fetch, ff = read(fetch_dir, "FETCH_SIZE")
     write, wf = read(write_dir, "WRITE_SIZE")
     from paper_2501_03322_amd import twk
-    return {"lib_sha256": lib_digest(twk.LIB_PATH), "hbm_bytes_per_launch": fetch + write,
+    return {"lib_sha256": lib_digest(twk.LIB_PATH),
+            "device_code_sha256": device_code_digest(twk.LIB_PATH), "hbm_bytes_per_launch": fetch + write,
             "fetch_bytes": fetch, "write_bytes": write,
             "fetch_copy_factor": ff, "write_copy_factor": wf}
 

@@ -141,8 +141,8 @@ int twk_last_stats(twk_ctx *ctx, int64_t *out8);
  * pointer ms[5], milliseconds): for the first chunk the point-source pass,
  * the learned stage (0 without TWK_MODE_MLP) and the contour kernel; then
  * the rest of the call and the whole call.  A call replayed from a captured
- * graph is timed as a whole (the per-stage entries read 0).  Waits for the
- * call.
+ * graph is timed as a whole: the three stage entries read 0 and the rest
+ * and whole-call entries both hold the whole call.  Waits for the call.
  * Errors: TWK_EINVAL if timing is off. */
 int twk_enable_timing(twk_ctx *ctx, int on);
 int twk_kernel_times(twk_ctx *ctx, double *ms5);

@@ -967,13 +967,14 @@ CallKey& tuning_key(CallKey& k, const twk_ctx* c) {
 // Issue the launch sequence of a call, or, with graph replay on, replay
 // the captured sequence of an identical earlier call (capturing it the
 // first time).  Nothing inside `issue` may allocate or synchronise.
-// With timing on, a replayed call is timed as a whole: events 0 before the
-// graph launch, 1..4 after it (per-stage times read 0).
+// With timing on, a replayed call is timed as a whole: events 0..3 before
+// the graph launch, 4 after it (the stage times read 0, the rest of the
+// call is the whole call).
 int launch_graph(twk_ctx* c, hipGraphExec_t ex) {
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-  HIP_TRY(c, hipGraphLaunch(ex, c->stream));
   if (c->timing)
-    for (int i = 1; i < 5; ++i) HIP_TRY(c, hipEventRecord(c->ev[i], c->stream));
+    for (int i = 0; i < 4; ++i) HIP_TRY(c, hipEventRecord(c->ev[i], c->stream));
+  HIP_TRY(c, hipGraphLaunch(ex, c->stream));
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
   return TWK_OK;
 }
 

@@ -69,7 +69,9 @@ def test_graph_replay_bitwise(lc):
         ctx.enable_timing(True)
         _run(ctx, args, twk.MODE_MIXED, tol=3e-4)
         kt = ctx.kernel_times()
-        assert kt["total_ms"] > 0 and kt["fs_ms"] < 0.05 * kt["total_ms"]
+        assert kt["total_ms"] > 0
+        assert kt["ps_ms"] < 0.05 * kt["total_ms"] and kt["mlp_ms"] < 0.05 * kt["total_ms"]
+        assert kt["fs_ms"] < 0.05 * kt["total_ms"] and kt["rest_ms"] > 0.95 * kt["total_ms"]
         ctx.enable_timing(False)
     ctx.close()
 

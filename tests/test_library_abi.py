@@ -44,3 +44,17 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(twk, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         twk.load()
+
+
+def test_device_code_digest_covers_device_code_only():
+    """The committed HBM-traffic record is keyed on the device code: the
+    digest reads the .hip_fatbin section, which is present, non-trivial and
+    differs from the digest of the whole file."""
+    import bench
+    from paper_2501_03322_amd import twk
+    if not os.path.exists(twk.LIB_PATH):
+        pytest.skip("library not built")
+    d = bench.device_code_digest(twk.LIB_PATH)
+    assert re.fullmatch(r"[0-9a-f]{64}", d)
+    assert d != bench.lib_digest(twk.LIB_PATH)
+    assert d == bench.device_code_digest(twk.LIB_PATH)
