@@ -98,6 +98,31 @@ def test_finite_mag_near_caustics(ctx, oracle, lens):
         assert rel.max() <= GATE, (lens, mode, rel.max(), int(rel.argmax()))
 
 
+def test_sample_cap(ctx, oracle):
+    """A tolerance that 4096 samples cannot meet: the refinement ends at the
+    cap, the result carries the cap flag, its sample count and a finite error
+    estimate above the requested one, and the capped value still agrees with
+    the oracle's tight value.  The oracle's serial run of the same sampler
+    ends at the cap as well."""
+    from paper_2501_03322_amd import twk
+    s, q, rho, tol = 1.0, 1e-3, 1e-3, 1e-12
+    zx, zy = _near_caustic_sources(s, q, rho, 8, seed=21)
+    rm = oracle.finite_mag(s, q, zx, zy, rho, oracle.JUDGE_TOL, oracle.judge_cfg())[0]
+    om, oe, on, of = oracle.finite_mag(s, q, zx, zy, rho, tol)
+    assert np.all(of & oracle.FLAG_CAP) and np.all(on <= 4096) and np.all(on > 4096 - 64)
+    for mode in (twk.MODE_FP64, twk.MODE_MIXED):
+        _log(f"sample cap mode={mode}")
+        mag, err, ns, fl = [_np(t) for t in ctx.finite_mag(s, q, zx, zy, rho, tol,
+                                                           mode | twk.MODE_ALL_FS)]
+        assert np.all(fl & twk.FLAG_CAP), (mode, fl)
+        assert np.all(ns <= 4096) and np.all(ns > 4096 - 64), (mode, ns)
+        assert np.all(np.isfinite(err)) and np.all(err > tol * mag), (mode, err / mag)
+        rel = np.abs(mag / rm - 1)
+        assert rel.max() <= GATE, (mode, rel.max())
+        if mode == twk.MODE_FP64:  # the same sampler, stopped at the same cap
+            assert np.abs(mag / om - 1).max() <= 1e-6
+
+
 def test_fp64_engine_follows_paper_sampler(ctx, oracle):
     """The FP64 engine and the oracle's serial run of the same sampler
     (64 initial, 64 per round, cap 4096) agree closely, and mostly use the
