@@ -117,11 +117,14 @@ __device__ inline double pair_stat(const Lens& L, const Images& im) {
 }
 
 // probe: solve the four stencil points (needed by the test and by the
-// learned features); test: decide adequacy.  start: roots to start the
-// centre solve from (a nearby source's), or null for a cold start; a warm
-// start that has not converged in 60 sweeps is replaced by a cold one.
+// learned features); test: decide adequacy; feat: the features are wanted
+// (without them the stencil stops at the first point that fails the test).
+// start: roots to start the centre solve from (a nearby source's), or null
+// for a cold start; a warm start that has not converged in 60 sweeps is
+// replaced by a cold one.
 __device__ inline PsResult point_source_pass(const Lens& L, c64 yc, double rho, double tol,
-                                             bool probe, bool test, const c64* start = nullptr) {
+                                             bool probe, bool test, bool feat,
+                                             const c64* start = nullptr) {
   PsResult out;
   c64 c[6], r[5];
   coefficients(L, yc, c);
@@ -160,7 +163,7 @@ __device__ inline PsResult point_source_pass(const Lens& L, c64 yc, double rho, 
   out.gx = 0.0;
   out.gy = 0.0;
 #pragma unroll 1
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 4 && (ok || feat); ++k) {
     // stencil point k: zeta_c + rho, + i rho, - rho, - i rho
     const double sx = k == 0 ? rho : (k == 2 ? -rho : 0.0);
     const double sy = k == 1 ? rho : (k == 3 ? -rho : 0.0);
@@ -278,7 +281,7 @@ __device__ inline void emit_source(int64_t out, double s, double q, double zx, d
       flags[out] = F_NONFINITE;
       if (warm) *warm = false;
     } else {
-      ps = point_source_pass(L, cz(zx - L.z2, zy), rho, tol, !all_fs || tfeat, !all_fs,
+      ps = point_source_pass(L, cz(zx - L.z2, zy), rho, tol, !all_fs || tfeat, !all_fs, tfeat,
                              warm && *warm ? carry : nullptr);
       if (carry) {
 #pragma unroll
@@ -465,7 +468,7 @@ __global__ __launch_bounds__(256) void k_feat(int64_t nsets, const double* ps, c
     adequate[i] = 0;
     return;
   }
-  const PsResult r = point_source_pass(L, cz(zx - L.z2, zy), prho[k], tol, true, true);
+  const PsResult r = point_source_pass(L, cz(zx - L.z2, zy), prho[k], tol, true, true, true);
   float f[8];
   ps_features(ps[k], pq[k], zx, zy, prho[k], r, f);
 #pragma unroll
