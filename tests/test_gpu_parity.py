@@ -156,6 +156,31 @@ def test_lightcurve_single(ctx, oracle):
         assert np.array_equal(ps, dec)
 
 
+@pytest.mark.parametrize("nepochs", [1, 3, 6, 101])
+def test_lightcurve_ragged_runs(ctx, oracle, nepochs):
+    """Epoch counts that are not a multiple of the point-source pass's run of
+    consecutive epochs (and shorter than one run): every epoch against the
+    oracle, and the point-source decisions equal to the oracle's."""
+    from paper_2501_03322_amd import inputs
+    c = inputs.batched_curves(nsets=3, nepochs=nepochs, seed=7)
+    for mode in (0, 1):
+        _log(f"ragged light curves: 3 x {nepochs}, mode={mode}")
+        mag, err, ns, fl = [_np(t) for t in ctx.lightcurves(c.s, c.q, c.u0, c.alpha, c.rho, c.tau,
+                                                            1e-4, mode)]
+        assert mag.shape == (3 * nepochs,)
+        for k in range(3):
+            zx, zy = oracle.trajectory(c.u0[k], c.alpha[k], c.tau)
+            rm = oracle.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], oracle.JUDGE_TOL,
+                                   oracle.judge_cfg())[0]
+            got = mag[k * nepochs:(k + 1) * nepochs]
+            rel = np.abs(got / rm - 1)
+            assert rel.max() <= GATE, (mode, k, rel.max(), int(rel.argmax()))
+            ps = (fl[k * nepochs:(k + 1) * nepochs] & 1) != 0
+            dec = np.array([oracle.ps_adequate(c.s[k], c.q[k], complex(x, y), c.rho[k], 1e-4)[0]
+                            for x, y in zip(zx, zy)])
+            assert np.array_equal(ps, dec), (mode, k)
+
+
 def test_lightcurve_batch_sampled(ctx, oracle):
     """The full fit-style batch (1024 sets x 2000 epochs) in one call, checked
     on a stratified sample of epochs against the oracle one by one."""
