@@ -18,6 +18,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "twk_gelu.h"
+
 namespace twk {
 namespace mlp {
 
@@ -49,12 +51,7 @@ __device__ inline f32x16 mma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-
-__device__ inline float gelu_grad(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
-         x * 0.39894228040143268f * expf(-0.5f * x * x);
-}
+// gelu(x) and gelu_grad(x) of the hidden layers: twk_gelu.h
 
 // ---------------------------------------------------------------- packing
 // Inference keeps the four weight matrices as ready-made B operands:

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../paper_2501_03322_amd/csrc/twk_fs.h"
+#include "../../paper_2501_03322_amd/csrc/twk_gelu.h"
 
 using namespace twk;
 
@@ -81,6 +82,13 @@ int emu_finite_mag(double s, double q, double zx, double zy, double rho, double 
 // sin and cos of n limb angles by the device routine
 void emu_limb_sincos(int n, const double* theta, double* sn, double* cs) {
   for (int i = 0; i < n; ++i) limb_sincos(theta[i], &sn[i], &cs[i]);
+}
+
+void emu_gelu(int n, const float* x, float* y, float* dy) {
+  for (int i = 0; i < n; ++i) {
+    y[i] = mlp::gelu(x[i]);
+    dy[i] = mlp::gelu_grad(x[i]);
+  }
 }
 
 int emu_point(double s, double q, double zx, double zy, double* mag, int* n, unsigned* flags,

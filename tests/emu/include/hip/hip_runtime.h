@@ -21,6 +21,7 @@
 #define __builtin_amdgcn_rcpf(x) (1.0f / (x))
 #define __builtin_amdgcn_sqrtf(x) std::sqrt((float)(x))
 #define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt((double)(x)))
+#define __builtin_amdgcn_exp2f(x) std::exp2((float)(x))
 
 namespace hip_emu {
 constexpr int kLanes = 64;

@@ -39,7 +39,15 @@ def _load(kgap=None, lcap=None):
                             cs.ctypes.data_as(dp))
         return sn, cs
 
-    return dict(finite=finite, point=point, limb_sincos=limb_sincos)
+    def gelu(x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y, dy = np.empty_like(x), np.empty_like(x)
+        fp = C.POINTER(C.c_float)
+        lib.emu_gelu(C.c_int(x.size), x.ctypes.data_as(fp), y.ctypes.data_as(fp),
+                     dy.ctypes.data_as(fp))
+        return y, dy
+
+    return dict(finite=finite, point=point, limb_sincos=limb_sincos, gelu=gelu)
 
 
 @pytest.fixture(scope="module")
@@ -224,3 +232,23 @@ def test_limb_sincos_accuracy(emu):
     z = int(np.nonzero(th == 0.0)[0][0])
     assert sn[z] == 0.0 and cs[z] == 1.0
     assert np.max(np.abs(sn * sn + cs * cs - 1.0)) < 4e-16
+
+
+def test_gelu_against_definition(emu):
+    """The learned budget's device GELU (float32, through an erfc fit) against
+    x Phi(x) from scipy's erf/erfc in float64: relative error below 1.5e-5,
+    absolute below 4e-7, and its derivative Phi(x) + x phi(x) within 1e-6,
+    over [-10, 10] (both tails, zero and the dense middle)."""
+    from scipy.special import erfc
+    x = np.concatenate([np.linspace(-10.0, 10.0, 400001), [0.0, -0.0, 1e-30, -1e-30, 1e-3]])
+    x = x.astype(np.float32)
+    y, dy = emu["gelu"](x)
+    xd = x.astype(np.float64)
+    ref = xd * 0.5 * erfc(-xd / np.sqrt(2.0))
+    dref = 0.5 * erfc(-xd / np.sqrt(2.0)) + xd * np.exp(-0.5 * xd * xd) / np.sqrt(2.0 * np.pi)
+    err = np.abs(y - ref)
+    assert err.max() < 4e-7
+    big = np.abs(ref) > 1e-30
+    assert (err[big] / np.abs(ref[big])).max() < 1.5e-5
+    assert np.abs(dy - dref).max() < 1e-6
+    assert y[np.argmax(x == 0.0)] == 0.0

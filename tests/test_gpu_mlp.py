@@ -3,9 +3,10 @@
 Tolerances of the bf16 products, derived from the arithmetic: a product of
 two bf16 numbers is exact in float32, so each pre-activation differs from
 the oracle's float64 sum of the same products only by float32 accumulation
-(about K 2^-24 relative, K <= 128).  A staged activation rounds to the same
-bf16 value on both sides unless it lies within that distance of a rounding
-midpoint; the rare flips move one activation by one bf16 unit (2^-8
+(about K 2^-24 relative, K <= 128), and each activation by that and the
+kernel's GELU (an erfc fit: below 1e-5 relative, 3e-7 absolute).  A staged
+activation rounds to the same bf16 value on both sides unless it lies within
+that distance of a rounding midpoint; the rare flips move one activation by one bf16 unit (2^-8
 relative), a change of a few 1e-3 of one term of the next layer.  Hence the
 outputs agree to well under 1e-2 (1 + |out|).  The backward pass also
 rounds dZ and the stored activations at each product (2^-9 relative per
