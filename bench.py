@@ -240,7 +240,8 @@ def main():
         print(json.dumps(pmc_summary(*args.pmc_summary)))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs one GPU per process; --gpus must be 1 "
+                                   "(a batch shards by parameter sets, one process per GPU)"}))
         sys.exit(2)
 
     import torch

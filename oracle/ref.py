@@ -141,14 +141,14 @@ def cfg(tol, **kw):
     return c
 
 
-# The judge configuration: a much tighter tolerance than the GPU's 1e-4
+# The tight configuration: a much tighter tolerance than the GPU's 1e-4
 # gate, more initial samples, geometric growth of the sample count and a
 # large cap, so that the oracle's own error is negligible against the gate.
-JUDGE_TOL = 1e-6
+TIGHT_TOL = 1e-6
 
 
-def judge_cfg():
-    return cfg(JUDGE_TOL, n0=256, nnew=64, cap=1 << 17, grow=4)
+def tight_cfg():
+    return cfg(TIGHT_TOL, n0=256, nnew=64, cap=1 << 17, grow=4)
 
 
 def finite_mag(s, q, zx, zy, rho, tol, config=None):

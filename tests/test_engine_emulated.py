@@ -79,7 +79,7 @@ CASES = [
 def test_engine_cases_against_oracle(emu, oracle, mixed):
     for (s, q, z, rho) in CASES:
         m, e, n, f = emu["finite"](s, q, z.real, z.imag, rho, 1e-4, mixed)
-        r = oracle.finite_mag(s, q, [z.real], [z.imag], rho, oracle.JUDGE_TOL, oracle.judge_cfg())[0][0]
+        r = oracle.finite_mag(s, q, [z.real], [z.imag], rho, oracle.TIGHT_TOL, oracle.tight_cfg())[0][0]
         assert abs(m / r - 1) <= GATE, (s, q, z, rho, m, r)
         assert 64 <= n <= 4096
 
@@ -93,8 +93,8 @@ def test_engine_near_caustics_against_oracle(emu, oracle):
             2j * np.pi * rng.uniform(0, 1, 12))
         for zz in z:
             m, e, n, f = emu["finite"](s, q, zz.real, zz.imag, rho, 1e-4, 0)
-            r = oracle.finite_mag(s, q, [zz.real], [zz.imag], rho, oracle.JUDGE_TOL,
-                                  oracle.judge_cfg())[0][0]
+            r = oracle.finite_mag(s, q, [zz.real], [zz.imag], rho, oracle.TIGHT_TOL,
+                                  oracle.tight_cfg())[0][0]
             assert abs(m / r - 1) <= GATE, (s, q, zz, rho, m, r)
 
 
@@ -141,7 +141,7 @@ def test_engine_initial_budget(emu, oracle, n0):
     the serial sampler started from the same grid."""
     for (s, q, z, rho) in CASES[:4]:
         m, e, n, f = emu["finite"](s, q, z.real, z.imag, rho, 1e-4, 1, n0)
-        r = oracle.finite_mag(s, q, [z.real], [z.imag], rho, oracle.JUDGE_TOL, oracle.judge_cfg())[0][0]
+        r = oracle.finite_mag(s, q, [z.real], [z.imag], rho, oracle.TIGHT_TOL, oracle.tight_cfg())[0][0]
         assert abs(m / r - 1) <= GATE, (s, q, z, rho, n0, m, r)
         assert n >= n0
     s, q, z, rho = CASES[3]
@@ -161,7 +161,7 @@ def test_slope_detector_repairs_blinded_engine(emu_blind, oracle):
     g = gold["fig1_coefficients"]
     s, q, rho = g["s"], g["q"], g["rho"]
     zc = complex(*g["zeta"])
-    good = oracle.finite_mag(s, q, [zc.real], [zc.imag], rho, oracle.JUDGE_TOL, oracle.judge_cfg())[0][0]
+    good = oracle.finite_mag(s, q, [zc.real], [zc.imag], rho, oracle.TIGHT_TOL, oracle.tight_cfg())[0][0]
     for mixed in (0, 1):
         m, e, n, f = emu_blind["finite"](s, q, zc.real, zc.imag, rho, 1e-4, mixed)
         assert f & 8, "slope detector did not act"
@@ -172,7 +172,7 @@ def test_slope_detector_follows_oracle(emu_blind, oracle):
     """Blinded engine against the blinded oracle running the same sampler
     (serial, half the stated tolerance): the same demotions, the same
     magnification, and both still meet the gate against the unblinded
-    judge on these lenses (q = 1e-5: the misjudged pairs are all of the kind
+    tight oracle run on these lenses (q = 1e-5: the misjudged pairs are all of the kind
     the slope test can see)."""
     import pins
     acted = 0
@@ -187,8 +187,8 @@ def test_slope_detector_follows_oracle(emu_blind, oracle):
         for zz in z:
             m, e, n, f = emu_blind["finite"](s, q, zz.real, zz.imag, rho, 1e-4, 0)
             rm, re_, rn, rf = oracle.finite_mag(s, q, [zz.real], [zz.imag], rho, 5e-5, cfg)
-            good = oracle.finite_mag(s, q, [zz.real], [zz.imag], rho, oracle.JUDGE_TOL,
-                                     oracle.judge_cfg())[0][0]
+            good = oracle.finite_mag(s, q, [zz.real], [zz.imag], rho, oracle.TIGHT_TOL,
+                                     oracle.tight_cfg())[0][0]
             acted += bool(f & 8)
             if n == rn[0]:  # same schedule: mostly the same demotions (a
                 # decision at its threshold can flip with rounding order)

@@ -192,7 +192,7 @@ def test_features_parity(ctx, oracle):
 
 def test_learned_path_parity(ctx, oracle):
     """The learned budget only moves where contour integration starts:
-    magnifications still meet the gate against the oracle judge, on the
+    magnifications still meet the gate against the tight oracle run, on the
     single light curve and near caustics, whatever the weights say."""
     from paper_2501_03322_amd import inputs, twk
     for seed, bias in ((21, 6.5), (22, 9.5)):
@@ -201,8 +201,8 @@ def test_learned_path_parity(ctx, oracle):
         ctx.mlp_set(M.flatten(p))
         c = inputs.single_curve()
         zx, zy = oracle.trajectory(c.u0[0], c.alpha[0], c.tau)
-        rm, _, _, _ = oracle.finite_mag(c.s[0], c.q[0], zx, zy, c.rho[0], oracle.JUDGE_TOL,
-                                        oracle.judge_cfg())
+        rm, _, _, _ = oracle.finite_mag(c.s[0], c.q[0], zx, zy, c.rho[0], oracle.TIGHT_TOL,
+                                        oracle.tight_cfg())
         for mode in (twk.MODE_MLP, twk.MODE_MLP | twk.MODE_MIXED):
             _log(f"learned light curve bias={bias} mode={mode}")
             mag, err, ns, fl = ctx.lightcurves(c.s, c.q, c.u0, c.alpha, c.rho, c.tau, 1e-4, mode)
@@ -231,8 +231,8 @@ def test_learned_path_parity(ctx, oracle):
             2j * np.pi * rng.uniform(0, 1, 64))
         mag, err, ns, fl = ctx.finite_mag(s, q, z.real.copy(), z.imag.copy(), rho, 1e-4,
                                           twk.MODE_MLP | twk.MODE_ALL_FS)
-        rm, _, _, _ = oracle.finite_mag(s, q, z.real.copy(), z.imag.copy(), rho, oracle.JUDGE_TOL,
-                                        oracle.judge_cfg())
+        rm, _, _, _ = oracle.finite_mag(s, q, z.real.copy(), z.imag.copy(), rho, oracle.TIGHT_TOL,
+                                        oracle.tight_cfg())
         rel = np.abs(mag.cpu().numpy() / rm - 1)
         assert rel.max() <= GATE
 
@@ -330,7 +330,7 @@ def test_learned_path_on_evaluation_batch(ctx, oracle):
     """The held-out evaluation batch at full size (1024 sets x 4000 epochs,
     seed 3, not used in training) on the learned + mixed path with the
     committed weights: sampled contour and point epochs meet the gate against
-    the oracle judge, and the budget needs fewer limb samples than the plain
+    the tight oracle run, and the budget needs fewer limb samples than the plain
     mixed path at the same tuning."""
     import torch
     from paper_2501_03322_amd import inputs, twk
@@ -366,6 +366,6 @@ def test_learned_path_on_evaluation_batch(ctx, oracle):
     for i in np.concatenate([rng.choice(fs, 30, replace=False), rng.choice(pt, 10, replace=False)]):
         k, j = divmod(int(i), c.nepochs)
         zx, zy = oracle.trajectory(c.u0[k], c.alpha[k], c.tau[j:j + 1])
-        rm = oracle.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], oracle.JUDGE_TOL,
-                               oracle.judge_cfg())[0][0]
+        rm = oracle.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], oracle.TIGHT_TOL,
+                               oracle.tight_cfg())[0][0]
         assert abs(mag[i] / rm - 1) <= GATE, (i, k, j, mag[i], rm)

@@ -139,7 +139,7 @@ def test_autotune(lc, oracle):
     for i in rng.choice(fs, min(40, fs.size), replace=False):
         k, j = divmod(int(i), c.nepochs)
         zx, zy = oracle.trajectory(c.u0[k], c.alpha[k], c.tau[j:j + 1])
-        rm = oracle.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], oracle.JUDGE_TOL,
-                               oracle.judge_cfg())[0][0]
+        rm = oracle.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], oracle.TIGHT_TOL,
+                               oracle.tight_cfg())[0][0]
         assert abs(mag[i] / rm - 1) <= 1e-4
     ctx.close()

@@ -58,3 +58,15 @@ def test_device_code_digest_covers_device_code_only():
     assert re.fullmatch(r"[0-9a-f]{64}", d)
     assert d != bench.lib_digest(twk.LIB_PATH)
     assert d == bench.device_code_digest(twk.LIB_PATH)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and a
+    message, before any GPU work."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--gpus must be 1" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
