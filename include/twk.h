@@ -111,7 +111,14 @@ int twk_finite_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *ze
  * (summed over annuli), flags.  Point-source-adequate epochs are answered
  * by the point value; all others by contour integration in one persistent
  * launch per chunk of parameter sets (a chunk holds at most 2^24 contour
- * tasks) fed by a device work queue. */
+ * tasks) fed by a device work queue.  Queued on the context's stream without
+ * waiting for it (except when the context's buffers must grow).
+ * Errors: TWK_EINVAL for nsets or nepochs < 0, nsets * nepochs * n_annuli
+ * above 2^48, tol <= 0 or non-finite, n_annuli outside 1..64 (or not 1
+ * without gamma), NULL pointers (when there is work) or unknown mode bits;
+ * TWK_ENOMLP for TWK_MODE_MLP without weights; TWK_ENOMEM / TWK_EDEVICE.
+ * Per-element parameters are not checked on the host: a non-finite source
+ * position returns NaN with TWK_FLAG_NONFINITE. */
 int twk_lightcurves(twk_ctx *ctx, int64_t nsets, const double *s, const double *q,
                     const double *u0, const double *alpha, const double *rho,
                     const double *gamma, int64_t nepochs, const double *tau, int32_t n_annuli,

@@ -837,6 +837,14 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
 
+// Largest accepted element count of a batch call (sets x epochs x annuli):
+// far beyond any device memory, and it keeps every size product in range.
+constexpr int64_t MAX_ELEMS = (int64_t)1 << 48;
+bool batch_size_ok(int64_t nsets, int64_t nepochs, int64_t na) {
+  return nsets >= 0 && nepochs >= 0 && (nepochs == 0 || nsets <= MAX_ELEMS / nepochs) &&
+         nsets * nepochs <= MAX_ELEMS / na;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1118,7 +1126,8 @@ int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q,
                     const double* alpha, const double* rho, const double* gamma, int64_t nepochs,
                     const double* tau, int32_t n_annuli, double tol, uint32_t mode, double* mag,
                     double* err, int32_t* ns, uint32_t* flags) {
-  if (!c || nsets < 0 || nepochs < 0 || !finite_pos(tol) || n_annuli < 1 || n_annuli > 64)
+  if (!c || !finite_pos(tol) || n_annuli < 1 || n_annuli > 64 ||
+      !batch_size_ok(nsets, nepochs, n_annuli))
     return TWK_EINVAL;
   int rc = check_mode(c, mode);
   if (rc) return rc;
@@ -1212,7 +1221,7 @@ int twk_kernel_times(twk_ctx* c, double* ms5) {
 int twk_features(twk_ctx* c, int64_t nsets, const double* s, const double* q, const double* u0,
                  const double* alpha, const double* rho, int64_t nepochs, const double* tau,
                  double tol, float* feat, double* mu_ps, int32_t* adequate) {
-  if (!c || nsets < 0 || nepochs < 0 || !finite_pos(tol)) return TWK_EINVAL;
+  if (!c || !finite_pos(tol) || !batch_size_ok(nsets, nepochs, 1)) return TWK_EINVAL;
   const int64_t n = nsets * nepochs;
   if (n == 0) return TWK_OK;
   if (!s || !q || !u0 || !alpha || !rho || !tau || !feat || !mu_ps || !adequate) return TWK_EINVAL;
@@ -1634,7 +1643,9 @@ int twk_autotune(twk_ctx* c, int64_t nsets, const double* s, const double* q, co
                  const double* alpha, const double* rho, const double* gamma, int64_t nepochs,
                  const double* tau, int32_t n_annuli, double tol, uint32_t mode, int32_t trials,
                  twk_tuning* best) {
-  if (!c || trials < 1 || trials > 100 || nsets < 1 || nepochs < 1) return TWK_EINVAL;
+  if (!c || trials < 1 || trials > 100 || nsets < 1 || nepochs < 1 ||
+      !batch_size_ok(nsets, nepochs, n_annuli > 0 ? n_annuli : 1))
+    return TWK_EINVAL;
   int rc = check_mode(c, mode);
   if (rc) return rc;
   HIP_TRY(c, hipSetDevice(c->device));

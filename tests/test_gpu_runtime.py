@@ -143,3 +143,24 @@ def test_autotune(lc, oracle):
                                oracle.tight_cfg())[0][0]
         assert abs(mag[i] / rm - 1) <= 1e-4
     ctx.close()
+
+
+def test_batch_size_limits():
+    """Element counts whose product would overflow (or exceed 2^48) are
+    refused before any device work; an empty batch is a no-op."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_03322_amd import twk
+    ctx = twk.Context(0, stream=torch.cuda.Stream())
+    f = ctx.lib.twk_lightcurves
+
+    def call(nsets, nepochs, na=1):
+        return f(ctx.h, nsets, None, None, None, None, None, None, nepochs, None, na, 1e-4, 0,
+                 None, None, None, None)
+    assert call(1 << 40, 1 << 30) == twk.EINVAL
+    assert call(1 << 62, 4) == twk.EINVAL
+    assert call(1 << 28, 1 << 20, 1) == twk.EINVAL  # 2^48 elements: allowed size, NULL arrays
+    assert call(-1, 10) == twk.EINVAL
+    assert call(0, 10) == twk.OK and call(10, 0) == twk.OK
+    ctx.close()
