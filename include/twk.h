@@ -75,7 +75,8 @@ const char *twk_strerror(int status);
 /* Point-source magnification (sum over real images of 1/|J|, Eq. jacobian)
  * of n sources at (zeta_x[i], zeta_y[i]), centre-of-mass frame.
  * Outputs (device, length n): mag; n_images (3 or 5); flags.
- * Errors: TWK_EINVAL if s <= 0, q <= 0, n < 0 or a pointer is NULL (n > 0). */
+ * Errors: TWK_EINVAL if s <= 0, q <= 0, n < 0 or n > 2^48, or a pointer is
+ * NULL (n > 0). */
 int twk_point_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *zeta_x,
                   const double *zeta_y, double *mag, int32_t *n_images, uint32_t *flags);
 
@@ -92,7 +93,7 @@ int twk_point_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *zet
  * sets each contour's starting grid (a multiple of 64, at most 512 uniform
  * samples and at most the tuned LDS capacity) and the queue runs sources
  * longest first; the stop rule and the tolerance are unchanged.
- * Errors: TWK_EINVAL for s, q, rho, tol <= 0 or non-finite, n < 0, NULL
+ * Errors: TWK_EINVAL for s, q, rho, tol <= 0 or non-finite, n < 0 or > 2^48, NULL
  * pointers or unknown mode bits; TWK_ENOMLP for TWK_MODE_MLP without
  * weights; TWK_ENOMEM / TWK_EDEVICE. */
 int twk_finite_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *zeta_x,
@@ -113,8 +114,8 @@ int twk_finite_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *ze
  * launch per chunk of parameter sets (a chunk holds at most 2^24 contour
  * tasks) fed by a device work queue.  Queued on the context's stream without
  * waiting for it (except when the context's buffers must grow).
- * Errors: TWK_EINVAL for nsets or nepochs < 0, nsets * nepochs * n_annuli
- * above 2^48, tol <= 0 or non-finite, n_annuli outside 1..64 (or not 1
+ * Errors: TWK_EINVAL for nsets or nepochs < 0, nepochs above 2^30,
+ * nsets * nepochs * n_annuli above 2^48, tol <= 0 or non-finite, n_annuli outside 1..64 (or not 1
  * without gamma), NULL pointers (when there is work) or unknown mode bits;
  * TWK_ENOMLP for TWK_MODE_MLP without weights; TWK_ENOMEM / TWK_EDEVICE.
  * Per-element parameters are not checked on the host: a non-finite source
@@ -215,7 +216,8 @@ int twk_autotune(twk_ctx *ctx, int64_t nsets, const double *s, const double *q,
  * (central differences at zeta +- rho, zeta +- i rho, floored at 1e-30);
  * mu_ps (device, f64) the point value; adequate (device, i32) the
  * point-source test's decision at tolerance tol.  Non-finite centres give
- * NaN features.  Errors: TWK_EINVAL for negative sizes, tol <= 0, NULL. */
+ * NaN features.  Errors: TWK_EINVAL for negative sizes, nepochs above 2^30,
+ * nsets * nepochs above 2^48, tol <= 0, NULL. */
 int twk_features(twk_ctx *ctx, int64_t nsets, const double *s, const double *q,
                  const double *u0, const double *alpha, const double *rho, int64_t nepochs,
                  const double *tau, double tol, float *feat, double *mu_ps, int32_t *adequate);
@@ -233,7 +235,8 @@ int twk_mlp_save(twk_ctx *ctx, const char *path);
 int twk_mlp_load(twk_ctx *ctx, const char *path);
 
 /* Inference on n rows: feat (device, [n][8] raw features) -> out (device,
- * [n][2] float32).  Asynchronous.  TWK_ENOMLP without weights. */
+ * [n][2] float32).  Asynchronous.  TWK_ENOMLP without weights; TWK_EINVAL
+ * for n < 0 or > 2^48 or NULL pointers (n > 0). */
 int twk_mlp_infer(twk_ctx *ctx, int64_t n, const float *feat, float *out);
 
 /* Loss and gradient on one batch of n (1..TWK_MLP_GRAD_MAX_ROWS) rows:

@@ -840,9 +840,12 @@ bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
 // Largest accepted element count of a batch call (sets x epochs x annuli):
 // far beyond any device memory, and it keeps every size product in range.
 constexpr int64_t MAX_ELEMS = (int64_t)1 << 48;
+// Elements of one launch of a one-lane-per-element kernel: the dispatch's
+// work-item count must stay below 2^32.
+constexpr int64_t LAUNCH_MAX = (int64_t)1 << 30;
 bool batch_size_ok(int64_t nsets, int64_t nepochs, int64_t na) {
-  return nsets >= 0 && nepochs >= 0 && (nepochs == 0 || nsets <= MAX_ELEMS / nepochs) &&
-         nsets * nepochs <= MAX_ELEMS / na;
+  return nsets >= 0 && nepochs >= 0 && nepochs <= LAUNCH_MAX &&
+         (nepochs == 0 || nsets <= MAX_ELEMS / nepochs) && nsets * nepochs <= MAX_ELEMS / na;
 }
 
 }  // namespace
@@ -934,14 +937,16 @@ int twk_last_hip_error(const twk_ctx* c) { return c ? c->last_err : 0; }
 
 int twk_point_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, const double* zy,
                   double* mag, int32_t* nimg, uint32_t* flags) {
-  if (!c || !finite_pos(s) || !finite_pos(q) || n < 0) return TWK_EINVAL;
+  if (!c || !finite_pos(s) || !finite_pos(q) || n < 0 || n > MAX_ELEMS) return TWK_EINVAL;
   if (n == 0) return TWK_OK;
   if (!zx || !zy || !mag || !nimg || !flags) return TWK_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
-  const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_point, dim3((unsigned)blocks), dim3(256), 0, c->stream, s, q, n, zx, zy, mag,
-                     nimg, flags);
-  HIP_TRY(c, hipGetLastError());
+  for (int64_t i0 = 0; i0 < n; i0 += LAUNCH_MAX) {
+    const int64_t m = std::min(LAUNCH_MAX, n - i0);
+    hipLaunchKernelGGL(k_point, dim3(blocks_for(m)), dim3(256), 0, c->stream, s, q, m, zx + i0,
+                       zy + i0, mag + i0, nimg + i0, flags + i0);
+    HIP_TRY(c, hipGetLastError());
+  }
   return TWK_OK;
 }
 
@@ -1048,7 +1053,8 @@ extern "C" {
 int twk_finite_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, const double* zy,
                    double rho, double tol, uint32_t mode, double* mag, double* err, int32_t* ns,
                    uint32_t* flags) {
-  if (!c || !finite_pos(s) || !finite_pos(q) || !finite_pos(rho) || !finite_pos(tol) || n < 0)
+  if (!c || !finite_pos(s) || !finite_pos(q) || !finite_pos(rho) || !finite_pos(tol) || n < 0 ||
+      n > MAX_ELEMS)
     return TWK_EINVAL;
   int rc = check_mode(c, mode);
   if (rc) return rc;
@@ -1226,9 +1232,14 @@ int twk_features(twk_ctx* c, int64_t nsets, const double* s, const double* q, co
   if (n == 0) return TWK_OK;
   if (!s || !q || !u0 || !alpha || !rho || !tau || !feat || !mu_ps || !adequate) return TWK_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
-  hipLaunchKernelGGL(k_feat, dim3(blocks_for(n)), dim3(256), 0, c->stream, nsets, s, q, u0, alpha,
-                     rho, nepochs, tau, tol, feat, mu_ps, adequate);
-  HIP_TRY(c, hipGetLastError());
+  const int64_t kc = std::max<int64_t>(1, LAUNCH_MAX / nepochs);  // sets per launch
+  for (int64_t k0 = 0; k0 < nsets; k0 += kc) {
+    const int64_t nk = std::min(kc, nsets - k0), o = k0 * nepochs;
+    hipLaunchKernelGGL(k_feat, dim3(blocks_for(nk * nepochs)), dim3(256), 0, c->stream, nk,
+                       s + k0, q + k0, u0 + k0, alpha + k0, rho + k0, nepochs, tau, tol,
+                       feat + o * 8, mu_ps + o, adequate + o);
+    HIP_TRY(c, hipGetLastError());
+  }
   return TWK_OK;
 }
 
@@ -1472,7 +1483,7 @@ int twk_mlp_load(twk_ctx* c, const char* path) {
 }
 
 int twk_mlp_infer(twk_ctx* c, int64_t n, const float* feat, float* out) {
-  if (!c || n < 0) return TWK_EINVAL;
+  if (!c || n < 0 || n > MAX_ELEMS) return TWK_EINVAL;
   if (!c->mlp_ready) return TWK_ENOMLP;
   if (n == 0) return TWK_OK;
   if (!feat || !out) return TWK_EINVAL;

@@ -63,6 +63,26 @@ def test_point_mag_parity(ctx, oracle):
         np.testing.assert_allclose(mag[ok], rmag[ok], rtol=1e-10)
 
 
+def test_point_mag_above_one_launch(ctx):
+    """More point sources than one launch of a one-lane-per-source kernel
+    takes (2^30 + 4000): the call splits into launches, and the tail of the
+    second launch equals the same sources in a call of their own."""
+    import torch
+    n = (1 << 30) + 4000
+    _log(f"point mag, n = {n}")
+    dev = torch.device("cuda", 0)
+    zx = torch.remainder(torch.arange(n, dtype=torch.float64, device=dev), 997.0) * 1e-3 - 0.5
+    zy = torch.full((n,), 0.013, dtype=torch.float64, device=dev)
+    mag, nimg, fl = ctx.point_mag(1.0, 1e-2, zx, zy)
+    torch.cuda.synchronize()
+    for lo in (0, (1 << 30) - 2000, n - 3000):
+        m2, n2, f2 = ctx.point_mag(1.0, 1e-2, zx[lo:lo + 3000].clone(), zy[lo:lo + 3000].clone())
+        assert torch.equal(mag[lo:lo + 3000], m2) and torch.equal(nimg[lo:lo + 3000], n2), lo
+    assert bool(torch.all(mag >= 1.0 - 1e-12))
+    del zx, zy, mag, nimg, fl
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_finite_mag_cases(ctx, oracle, mode):
     for (s, q, z, rho) in FS_CASES:

@@ -163,4 +163,7 @@ def test_batch_size_limits():
     assert call(1 << 28, 1 << 20, 1) == twk.EINVAL  # 2^48 elements: allowed size, NULL arrays
     assert call(-1, 10) == twk.EINVAL
     assert call(0, 10) == twk.OK and call(10, 0) == twk.OK
+    assert call(1, (1 << 30) + 1) == twk.EINVAL  # epochs of one set exceed one launch
+    assert ctx.lib.twk_point_mag(ctx.h, 1.0, 1e-3, (1 << 48) + 1, None, None, None, None,
+                                 None) == twk.EINVAL
     ctx.close()
