@@ -100,6 +100,24 @@ int twk_finite_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *ze
                    const double *zeta_y, double rho, double tol, uint32_t mode, double *mag,
                    double *err, int32_t *n_samples, uint32_t *flags);
 
+/* Finite-source magnification with a lens and source of its own per element
+ * (Sec. 2's problem statement, one instance per element): device arrays s,
+ * q, zeta_x, zeta_y, rho of length n.  This is the form for time-varying
+ * lenses -- orbital motion (s and the trajectory angle changing with time)
+ * or parallax (a displaced source trajectory): the caller evaluates s(t),
+ * q and the source position at each epoch, in the centre-of-mass frame of
+ * that epoch's lens.  Outputs, mode, tolerance and the adaptive refinement
+ * as for twk_finite_mag; elements may mix lenses freely in one persistent
+ * launch.  An element whose s, q or rho is not finite and positive is
+ * answered as a non-finite input (NaN, TWK_FLAG_NONFINITE).
+ * Errors: TWK_EINVAL for tol <= 0 or non-finite, n < 0 or > 2^48, NULL
+ * pointers (n > 0) or unknown mode bits; TWK_ENOMLP for TWK_MODE_MLP
+ * without weights; TWK_ENOMEM / TWK_EDEVICE. */
+int twk_finite_mag_each(twk_ctx *ctx, int64_t n, const double *s, const double *q,
+                        const double *zeta_x, const double *zeta_y, const double *rho, double tol,
+                        uint32_t mode, double *mag, double *err, int32_t *n_samples,
+                        uint32_t *flags);
+
 /* Batched light curves: nsets lenses/sources (device arrays s, q, u0,
  * alpha, rho, each of length nsets) times nepochs epochs tau (device array)
  * on straight trajectories zeta = (tau cos a - u0 sin a) + i (tau sin a +

@@ -342,6 +342,33 @@ __global__ __launch_bounds__(256) void k_prep(double s, double q, int64_t n, con
               cnt, nullptr, mag, err, ns, flags, active, tfeat);
 }
 
+// Per-element lens and source (time-varying lenses: the caller evaluates
+// s, q, rho and the source position at each epoch).  An element whose s, q
+// or rho is not finite and positive is answered as a non-finite input.
+__global__ __launch_bounds__(256) void k_prep_each(const double* ps, const double* pq, int64_t n,
+                                                   const double* zx, const double* zy,
+                                                   const double* prho, double tol, int all_fs,
+                                                   Task* tasks, long long* cnt, double* mag,
+                                                   double* err, int32_t* ns, uint32_t* flags,
+                                                   float* tfeat) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = i < n;
+  double s = 1.0, q = 1.0, rho = 1.0, x = 0.0, y = 0.0;
+  if (active) {
+    s = ps[i];
+    q = pq[i];
+    rho = prho[i];
+    x = zx[i];
+    y = zy[i];
+    if (!(s > 0.0 && s < 1e300 && q > 0.0 && q < 1e300 && rho > 0.0 && rho < 1e300)) {
+      s = q = rho = 1.0;
+      x = __builtin_nan("");
+    }
+  }
+  emit_source(i, s, q, x, y, rho, tol, all_fs != 0, 1, tasks, cnt, nullptr, mag, err, ns, flags,
+              active, tfeat);
+}
+
 // Magnification map: pixel (ix, iy) of an nx x ny grid over the box
 // [xc - w/2, xc + w/2] x [yc - h/2, yc + h/2], pixel centres, output index
 // iy * nx + ix (rows iy0 .. iy0 + nrows - 1 in this launch).
@@ -1079,6 +1106,42 @@ int twk_finite_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, 
       hipLaunchKernelGGL(k_prep, dim3(blocks_for(m)), dim3(256), 0, c->stream, s, q, m, zx + i0,
                          zy + i0, rho, tol, all_fs, c->tasks, c->cnt, mag + i0, err + i0, ns + i0,
                          flags + i0, tfeat);
+      HIP_TRY(c, hipGetLastError());
+      if ((r = contour_stage(c, i0 == 0, mixed, learned, m, tol, mag + i0, err + i0, ns + i0,
+                             flags + i0)))
+        return r;
+    }
+    return mark(c, 4, true);
+  });
+}
+
+int twk_finite_mag_each(twk_ctx* c, int64_t n, const double* s, const double* q,
+                        const double* zx, const double* zy, const double* rho, double tol,
+                        uint32_t mode, double* mag, double* err, int32_t* ns, uint32_t* flags) {
+  if (!c || !finite_pos(tol) || n < 0 || n > MAX_ELEMS) return TWK_EINVAL;
+  int rc = check_mode(c, mode);
+  if (rc) return rc;
+  if (n == 0) return TWK_OK;
+  if (!s || !q || !zx || !zy || !rho || !mag || !err || !ns || !flags) return TWK_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  const int64_t chunk = std::min<int64_t>(n, CHUNK_TASKS);
+  const bool learned = (mode & TWK_MODE_MLP) != 0;
+  if ((rc = ensure_fs(c, chunk))) return rc;
+  if (learned && (rc = ensure_learn(c, chunk))) return rc;
+  const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
+  const bool mixed = (mode & TWK_MODE_MIXED) != 0;
+  float* tfeat = learned ? learn_bufs(c).feat : nullptr;
+  CallKey key;
+  key.u(4).u((uint64_t)n).p(s).p(q).p(zx).p(zy).p(rho).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
+  return run_captured(c, tuning_key(key, c), [&]() -> int {
+    int r;
+    if ((r = mark(c, 0, true)) || (r = reset(c, false))) return r;
+    for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+      const int64_t m = std::min(chunk, n - i0);
+      if (i0 > 0 && (r = reset(c, true))) return r;
+      hipLaunchKernelGGL(k_prep_each, dim3(blocks_for(m)), dim3(256), 0, c->stream, s + i0, q + i0,
+                         m, zx + i0, zy + i0, rho + i0, tol, all_fs, c->tasks, c->cnt, mag + i0,
+                         err + i0, ns + i0, flags + i0, tfeat);
       HIP_TRY(c, hipGetLastError());
       if ((r = contour_stage(c, i0 == 0, mixed, learned, m, tol, mag + i0, err + i0, ns + i0,
                              flags + i0)))

@@ -28,7 +28,8 @@ FLAG_NONFINITE = 1 << 4
 FLAG_NEARDEGEN = 1 << 5
 
 EXPORTS = ("twk_create", "twk_destroy", "twk_sync", "twk_last_hip_error", "twk_strerror",
-           "twk_point_mag", "twk_finite_mag", "twk_lightcurves", "twk_last_stats",
+           "twk_point_mag", "twk_finite_mag", "twk_finite_mag_each", "twk_lightcurves",
+           "twk_last_stats",
            "twk_enable_timing", "twk_kernel_times", "twk_mag_map", "twk_features",
            "twk_mlp_set", "twk_mlp_get", "twk_mlp_save", "twk_mlp_load", "twk_mlp_infer",
            "twk_mlp_grad", "twk_mlp_train", "twk_get_tuning", "twk_set_tuning", "twk_autotune")
@@ -83,6 +84,8 @@ def load():
     L.twk_point_mag.argtypes = [_vp, C.c_double, C.c_double, C.c_int64, _vp, _vp, _vp, _vp, _vp]
     L.twk_finite_mag.argtypes = [_vp, C.c_double, C.c_double, C.c_int64, _vp, _vp, C.c_double,
                                  C.c_double, C.c_uint32, _vp, _vp, _vp, _vp]
+    L.twk_finite_mag_each.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_double,
+                                      C.c_uint32, _vp, _vp, _vp, _vp]
     L.twk_lightcurves.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int64, _vp,
                                   C.c_int32, C.c_double, C.c_uint32, _vp, _vp, _vp, _vp]
     L.twk_mag_map.argtypes = [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -201,6 +204,21 @@ class Context:
         self._check(self.lib.twk_finite_mag(self.h, s, q, n, _ptr(zx), _ptr(zy), rho, tol, mode,
                                             _ptr(mag), _ptr(err), _ptr(ns), _ptr(fl)),
                     "twk_finite_mag")
+        return out
+
+    def finite_mag_each(self, s, q, zx, zy, rho, tol, mode=MODE_FP64, out=None):
+        """Per-element lens and source: s, q, zx, zy, rho of equal length."""
+        s, q, zx, zy, rho = (_dev(a, self.device) for a in (s, q, zx, zy, rho))
+        n = zx.numel()
+        if not all(a.numel() == n for a in (s, q, zy, rho)):
+            raise ValueError("s, q, zx, zy and rho must have the same length")
+        if out is None:
+            out = self.alloc_out(n)
+        mag, err, ns, fl = out
+        self._check(self.lib.twk_finite_mag_each(self.h, n, _ptr(s), _ptr(q), _ptr(zx), _ptr(zy),
+                                                 _ptr(rho), tol, mode, _ptr(mag), _ptr(err),
+                                                 _ptr(ns), _ptr(fl)),
+                    "twk_finite_mag_each")
         return out
 
     def alloc_out(self, n):
