@@ -193,7 +193,8 @@ def test_features_parity(ctx, oracle):
 def test_learned_path_parity(ctx, oracle):
     """The learned budget only moves where contour integration starts:
     magnifications still meet the gate against the tight oracle run, on the
-    single light curve and near caustics, whatever the weights say."""
+    single light curve, near caustics and with a lens per element, whatever
+    the weights say."""
     from paper_2501_03322_amd import inputs, twk
     for seed, bias in ((21, 6.5), (22, 9.5)):
         p = _params(seed)
@@ -235,6 +236,19 @@ def test_learned_path_parity(ctx, oracle):
                                         oracle.tight_cfg())
         rel = np.abs(mag.cpu().numpy() / rm - 1)
         assert rel.max() <= GATE
+        # per-element lenses on the learned path: mixed lenses in one call
+        qs = 10.0 ** rng.uniform(-4.0, -2.0, 64)
+        ss = 10.0 ** rng.uniform(-0.2, 0.2, 64)
+        zz = np.array([pins.caustic(ss[i], qs[i], 256)[rng.integers(0, 256)] for i in range(64)])
+        zz = zz + rho * rng.uniform(0, 2, 64) * np.exp(2j * np.pi * rng.uniform(0, 1, 64))
+        rr = np.full(64, rho)
+        mag, err, ns, fl = ctx.finite_mag_each(ss, qs, zz.real.copy(), zz.imag.copy(), rr, 1e-4,
+                                               twk.MODE_MLP | twk.MODE_MIXED)
+        rm = np.array([oracle.finite_mag(ss[i], qs[i], [zz[i].real], [zz[i].imag], rho,
+                                         oracle.TIGHT_TOL, oracle.tight_cfg())[0][0]
+                       for i in range(64)])
+        rel = np.abs(mag.cpu().numpy() / rm - 1)
+        assert rel.max() <= GATE, (seed, rel.max(), int(rel.argmax()))
 
 
 def test_learned_batch_every_task_once(ctx, oracle):
