@@ -65,6 +65,24 @@ def test_graph_replay_bitwise(lc):
             assert torch.equal(got[0], ref2[0])
             stats = ctx.stats()
             assert stats["fs_tasks"] == int(((ref2[3] & 1) == 0).sum().item())
+        # per-element lenses replay the same way
+        rng = np.random.default_rng(4)
+        n = 3000
+        el = [torch.as_tensor(a, device=args[0].device) for a in (
+            10.0 ** rng.uniform(-0.3, 0.3, n), 10.0 ** rng.uniform(-4, -1, n),
+            rng.uniform(-1.0, 1.0, n), rng.uniform(-0.3, 0.3, n), 10.0 ** rng.uniform(-3, -2, n))]
+        ctx.set_tuning(graphs=0)
+        ref = [t.clone() for t in ctx.finite_mag_each(*el, 1e-4, twk.MODE_MIXED)]
+        ctx.set_tuning(graphs=1)
+        out = ctx.alloc_out(n)
+        for rep in range(3):
+            for t in out:
+                t.zero_()
+            ctx.finite_mag_each(*el, 1e-4, twk.MODE_MIXED, out=out)
+            ctx.sync()
+            for a, b in zip(out, ref):
+                assert torch.equal(a, b), ("each", rep)
+            torch.cuda.synchronize()
         # timing a replayed call: whole-call time only
         ctx.enable_timing(True)
         _run(ctx, args, twk.MODE_MIXED, tol=3e-4)
