@@ -27,7 +27,7 @@ FLAG_NEARDEGEN = 1 << 5
 class Cfg(C.Structure):
     _fields_ = [("tol", C.c_double), ("n0", C.c_int32), ("nnew", C.c_int32),
                 ("cap", C.c_int32), ("grow", C.c_int32), ("slope", C.c_int32),
-                ("kgap", C.c_double)]
+                ("kgap", C.c_double), ("cross_flip", C.c_int32)]
 
 
 _lib = None
@@ -58,6 +58,8 @@ def lib():
                                            C.c_double, C.POINTER(Cfg), _dp, _dp, _ip, _up,
                                            _dp, C.c_int32]
         L.twk_ref_trajectory.argtypes = [C.c_double, C.c_double, C.c_int64, _dp, _dp, _dp]
+        L.twk_ref_cross_piece.argtypes = [_dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_int32,
+                                          C.c_double, C.c_int32, _dp, _dp, _dp]
         L.twk_ref_ld_combine.argtypes = [C.c_double, C.c_int32, _dp, _dp]
         L.twk_ref_ps_adequate.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
                                           C.c_double, C.c_double, _ip, _dp]
@@ -66,7 +68,8 @@ def lib():
         for name in ("twk_ref_coeffs", "twk_ref_coeffs_conventional", "twk_ref_roots",
                      "twk_ref_images", "twk_ref_point_mag", "twk_ref_limb_derivs",
                      "twk_ref_finite_mag", "twk_ref_finite_trace", "twk_ref_trajectory",
-                     "twk_ref_ld_combine", "twk_ref_ps_adequate", "twk_ref_features"):
+                     "twk_ref_ld_combine", "twk_ref_ps_adequate", "twk_ref_features",
+                     "twk_ref_cross_piece"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -175,6 +178,18 @@ def finite_trace(s, q, zeta, rho, config, max_out=1 << 17):
                                       C.byref(config), C.byref(mag), C.byref(err), C.byref(ns),
                                       C.byref(fl), _d(th), max_out))
     return mag.value, err.value, ns.value, fl.value, th[:min(ns.value, max_out)]
+
+
+def cross_piece(zp, zm, dp, dm, wp, wm, kind, dth, flip=0):
+    """Chord + cross-caustic correction and errors of an interval in which a
+    pair is created (kind > 0) or destroyed (kind < 0): (dA, E, E2)."""
+    def c2(z):
+        return np.array([np.real(z), np.imag(z)], dtype=np.float64)
+    a, b, cp, cm = c2(zp), c2(zm), c2(dp), c2(dm)
+    dA, E, E2 = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().twk_ref_cross_piece(_d(a), _d(b), _d(cp), _d(cm), wp, wm, kind, dth, flip,
+                                     C.byref(dA), C.byref(E), C.byref(E2)))
+    return dA.value, E.value, E2.value
 
 
 def trajectory(u0, alpha, tau):

@@ -625,8 +625,50 @@ typedef struct {
   int anomaly;
 } piece_t;
 
+/* The piece of a pair created (kind > 0, boundary from the - image to the
+ * + image) or destroyed (kind < 0, from + to -) inside an interval of width
+ * dth, from the pair's positions, limb derivatives and z' ^ z'' at the
+ * sample where it exists: chord plus the cross-caustic correction
+ * (Sec. 2.3) and errors E1 + E2 + E3 (Sec. 2.5, Eq. area_cross).  flip
+ * (diagnostic only; 0 is the reading used): bit 0 negates the correction
+ * of a created pair, bit 1 that of a destroyed pair.  *E2 receives E2. */
+static void cross_piece(cplx zp, cplx zm, cplx dp, cplx dm, double wp,
+                        double wm, int kind, double dth, int flip,
+                        double *dA, double *E, double *E2out) {
+  double dth2 = dth * dth;
+  double dd = sqrt(fabs(dot(dp, dm)));
+  double sep = cabs(zp - zm);
+  double dtt = sep / dd;  /* effective step across the critical curve */
+  double dtt3 = dtt * dtt * dtt;
+  double dAp = (wp - wm) * dtt3 / 24.0;
+  if ((kind > 0 && (flip & 1)) || (kind < 0 && (flip & 2))) dAp = -dAp;
+  /* boundary runs from the - image to the + image where the pair is
+   * created, and from + to - where it is destroyed */
+  double chord = kind > 0 ? 0.5 * wedge(zm, zp) : 0.5 * wedge(zp, zm);
+  *dA = chord + dAp;
+  double E1 = fabs(wp + wm) * dtt3 / 48.0;
+  /* READING of the garbled cross-caustic E2: "-" for a pair created
+   * along +theta, "+" for a destroyed one. */
+  double sgn = kind > 0 ? 1.0 : -1.0;
+  double E2 = 1.5 * fabs(dot(zp - zm, dp - dm) - sgn * 2.0 * sep * dd) * dtt;
+  double E3 = 0.1 * fabs(dAp) * dth2;
+  *E = E1 + E2 + E3;
+  *E2out = E2;
+}
+
+int twk_ref_cross_piece(const double *zp, const double *zm, const double *dp,
+                        const double *dm, double wp, double wm, int32_t kind,
+                        double dth, int32_t flip, double *dA, double *E,
+                        double *E2) {
+  if (!zp || !zm || !dp || !dm || !dA || !E || !E2 || kind == 0)
+    return TWK_REF_EINVAL;
+  cross_piece(CMPLX(zp[0], zp[1]), CMPLX(zm[0], zm[1]), CMPLX(dp[0], dp[1]),
+              CMPLX(dm[0], dm[1]), wp, wm, kind, dth, flip, dA, E, E2);
+  return TWK_REF_OK;
+}
+
 static piece_t interval_piece(const sample_t *a, const sample_t *b,
-                              double dth) {
+                              double dth, int flip) {
   links_t lk;
   link_samples(a, b, &lk);
   piece_t out = {0.0, 0.0, 0, lk.anomaly};
@@ -652,25 +694,11 @@ static piece_t interval_piece(const sample_t *a, const sample_t *b,
   if (lk.kind != 0) {
     /* the created pair lives at b, the destroyed pair at a */
     const sample_t *c = lk.kind > 0 ? b : a;
-    cplx zp = c->im.z[lk.cp], zm = c->im.z[lk.cn];
-    cplx dp = c->dz[lk.cp], dm = c->dz[lk.cn];
-    double wp = c->w[lk.cp], wm = c->w[lk.cn];
-    double dd = sqrt(fabs(dot(dp, dm)));
-    double sep = cabs(zp - zm);
-    double dtt = sep / dd;  /* effective step across the critical curve */
-    double dtt3 = dtt * dtt * dtt;
-    double dAp = (wp - wm) * dtt3 / 24.0;
-    /* boundary runs from the - image to the + image where the pair is
-     * created, and from + to - where it is destroyed */
-    double chord = lk.kind > 0 ? 0.5 * wedge(zm, zp) : 0.5 * wedge(zp, zm);
-    out.dA += chord + dAp;
-    double E1 = fabs(wp + wm) * dtt3 / 48.0;
-    /* READING of the garbled cross-caustic E2: "-" for a pair created
-     * along +theta, "+" for a destroyed one. */
-    double sgn = lk.kind > 0 ? 1.0 : -1.0;
-    double E2 = 1.5 * fabs(dot(zp - zm, dp - dm) - sgn * 2.0 * sep * dd) * dtt;
-    double E3 = 0.1 * fabs(dAp) * dth2;
-    out.E += E1 + E2 + E3;
+    double dA, E, E2;
+    cross_piece(c->im.z[lk.cp], c->im.z[lk.cn], c->dz[lk.cp], c->dz[lk.cn],
+                c->w[lk.cp], c->w[lk.cn], lk.kind, dth, flip, &dA, &E, &E2);
+    out.dA += dA;
+    out.E += E;
     out.cross = 1;
   }
   return out;
@@ -835,6 +863,7 @@ void twk_ref_cfg_default(twk_ref_cfg *cfg, double tol) {
   cfg->grow = 0;
   cfg->slope = 1;
   cfg->kgap = 100.0;
+  cfg->cross_flip = 0;
 }
 
 static int contour(const lens_t *L, cplx yc, double rho, const twk_ref_cfg *cfg,
@@ -872,7 +901,7 @@ static int contour(const lens_t *L, cplx yc, double rho, const twk_ref_cfg *cfg,
       const sample_t *a = &sm[ord[i]];
       const sample_t *b = &sm[ord[(i + 1) % N]];
       double dth = (i + 1 < N ? b->theta : b->theta + 2.0 * PI_D) - a->theta;
-      piece_t pc = interval_piece(a, b, dth);
+      piece_t pc = interval_piece(a, b, dth, cfg->cross_flip);
       if (pc.anomaly) fl |= TWK_REF_FLAG_ANOMALY;
       nsum_add(&sa, pc.dA);
       Ei[i] = pc.E;
@@ -944,7 +973,9 @@ int twk_ref_finite_mag(double s, double q, int64_t n, const double *zx,
   if (cfg_in) cfg = *cfg_in;
   else twk_ref_cfg_default(&cfg, tol);
   cfg.tol = tol;
-  if (cfg.n0 < 4 || cfg.nnew < 1 || cfg.cap < cfg.n0) return TWK_REF_EINVAL;
+  if (cfg.n0 < 4 || cfg.nnew < 1 || cfg.cap < cfg.n0 || cfg.cross_flip < 0 ||
+      cfg.cross_flip > 3)
+    return TWK_REF_EINVAL;
   lens_t L = lens_make(s, q);
   for (int64_t i = 0; i < n; ++i) {
     if (!isfinite(zx[i]) || !isfinite(zy[i])) {

@@ -93,6 +93,9 @@ typedef struct {
   int32_t grow;  /* >0: new samples per round = max(nnew, N/grow)           */
   int32_t slope; /* 1: run the slope detector (Sec. 2.4.2)                  */
   double kgap;   /* residual-detector gap factor (default 100)              */
+  int32_t cross_flip; /* diagnostic, default 0 (the reading used): bit 0
+                         negates the cross-caustic correction of created
+                         pairs, bit 1 that of destroyed pairs              */
 } twk_ref_cfg;
 
 /* Defaults as the paper describes its own sampler: tol as given, 64 initial
@@ -114,6 +117,18 @@ int twk_ref_finite_trace(double s, double q, double zeta_x, double zeta_y,
                          double rho, const twk_ref_cfg *cfg, double *mag,
                          double *err, int32_t *n_samples, uint32_t *flags,
                          double *theta_out, int32_t max_out);
+
+/* Diagnostic: the piece of one interval in which an image pair is created
+ * (kind > 0) or destroyed (kind < 0), from the pair's positions zp, zm
+ * (+ and - parity), limb derivatives dp, dm (each as Re, Im) and
+ * z' ^ z'' values wp, wm at the sample where the pair exists; dth is the
+ * interval width.  Outputs: dA = chord + cross-caustic correction
+ * (Sec. 2.3), E = E1 + E2 + E3 and E2 alone (Sec. 2.5, Eq. area_cross).
+ * flip as in twk_ref_cfg.cross_flip. */
+int twk_ref_cross_piece(const double *zp, const double *zm, const double *dp,
+                        const double *dm, double wp, double wm, int32_t kind,
+                        double dth, int32_t flip, double *dA, double *E,
+                        double *E2);
 
 /* Source centres along straight trajectories: zeta = (tau cos a - u0 sin a)
  * + i (tau sin a + u0 cos a), centre-of-mass frame. */
