@@ -1,22 +1,34 @@
 #!/usr/bin/env python3
 """Throughput benchmark: finite-source binary-lens magnifications per second.
 
-Workload: the fit-style batch of 1024 lens/source parameter sets x 2000
-epochs (tau in [-1.5, 1.5]) with log10 s ~ U[-0.5,0.5], log10 q ~ U[-5,-1],
-alpha ~ U[0,2pi), u0 ~ U[-0.1,0.1], log10 rho ~ U[-4,-2] (seed 1), uniform
-source, relative tolerance 1e-4, answered in one call of twk_lightcurves:
-point-source test for every epoch, contour integration for the rest in one
-persistent launch.  A step is one such call over the whole batch; inputs
-are resident in device memory before timing starts.
+Headline workload: the high-cadence limb-darkened batch of 16384 lens/source
+parameter sets x 8000 epochs (tau in [-1.5, 1.5]) with log10 s ~
+U[-0.5,0.5], log10 q ~ U[-6,-1], alpha ~ U[0,2pi), u0 ~ U[-0.1,0.1], log10
+rho ~ U[-4,-2.5], linear limb darkening Gamma ~ U[0.3,0.6] over 10
+equal-area annuli (seed 4), relative tolerance 1e-4, answered in one call
+of twk_lightcurves: point-source test for every epoch, contour integration
+of every annulus of the rest by the persistent kernel, annulus combination.
+A step is one such call over the whole batch (131,072,000 magnifications);
+inputs are resident in device memory before timing starts.
 
-Paths timed (same call, mode bits differ): plain FP64 (no learned budget),
-+ mixed precision (FP32 bulk root iterations), + learned budget (the MLP's
-starting grid and longest-first queue).  The headline value is the learned
-+ mixed path; the others are reported beside it.
+Paths timed (same call, mode bits differ), each addition separately:
+plain FP64 (one kernel launch per refinement round over the list of
+unfinished sources, the paper's dispatch), + persistent kernel with a device
+queue, + mixed precision (FP32 bulk root iterations), + learned budget (the
+MLP's starting grid and longest-first queue).  The headline value is the
+learned + mixed + persistent path.  The fit-style batch of 1024 sets x 2000
+epochs (uniform source, seed 1) is reported beside it.
+
+After timing, the headline's results are checked against the FP64 oracle at
+a tight tolerance on the epochs where the headline and the plain path
+disagree most, where the error estimate is largest relative to the
+tolerance, on every cap- or anomaly-flagged epoch and on random epochs; the
+worst relative error is part of the JSON line and the run fails (exit 3)
+if an unflagged result misses the tolerance.
 
 Prints one JSON line with the value, the roofline of the dominant kernel
 (the persistent contour kernel, VALU-bound), and the CPU oracle timed on a
-bounded sample of the same workload.
+bounded sample of the same workload, on one core and on all cores.
 """
 import argparse
 import json
@@ -56,26 +68,36 @@ def flops_of(stats):
             stats["samples"] * F_SAMPLE + stats["intervals"] * F_INTERVAL)
 
 
-def run_path(ctx, dev, c, mode, steps, warmup, label):
+def device_args(c, dev):
     import torch
-    args = [torch.as_tensor(a, device=dev) for a in (c.s, c.q, c.u0, c.alpha, c.rho, c.tau)]
+    t = lambda a: torch.as_tensor(a, device=dev)
+    return dict(s=t(c.s), q=t(c.q), u0=t(c.u0), alpha=t(c.alpha), rho=t(c.rho), tau=t(c.tau),
+                gamma=None if c.gamma is None else t(c.gamma), n_annuli=c.n_annuli)
+
+
+def call(ctx, a, tol, mode, out):
+    return ctx.lightcurves(a["s"], a["q"], a["u0"], a["alpha"], a["rho"], a["tau"], tol, mode=mode,
+                           gamma=a["gamma"], n_annuli=a["n_annuli"], out=out)
+
+
+def run_path(ctx, a, c, mode, steps, warmup, label):
+    import torch
     out = ctx.alloc_out(c.nsets * c.nepochs)
     ctx.enable_timing(True)
     for w in range(warmup):
-        ctx.lightcurves(*args, c.tol, mode=mode, out=out)
+        call(ctx, a, c.tol, mode, out)
         ctx.sync()
         log(f"[{label}] warmup {w + 1}/{warmup} done")
-    fs_ms = []
-    tot_ms = []
-    mlp_ms = []
+    fs_ms, tot_ms, mlp_ms, ps_ms = [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        ctx.lightcurves(*args, c.tol, mode=mode, out=out)
+        call(ctx, a, c.tol, mode, out)
         kt = ctx.kernel_times()  # waits for this step
         fs_ms.append(kt["fs_ms"])
         tot_ms.append(kt["total_ms"])
         mlp_ms.append(kt["mlp_ms"])
+        ps_ms.append(kt["ps_ms"])
         if "graph" in label:  # a replayed call is timed as a whole
             log(f"[{label}] step {k + 1}/{steps}: {kt['total_ms']:.2f} ms")
         else:
@@ -86,39 +108,153 @@ def run_path(ctx, dev, c, mode, steps, warmup, label):
     wall = time.perf_counter() - t0
     st = ctx.stats()
     ctx.enable_timing(False)
-    fl = out[3].cpu().numpy()
-    ns = out[2].cpu().numpy()
-    nfs = ns[(fl & 1) == 0]
-    hist = {f"<= {b}": int(np.sum(nfs <= b)) for b in (64, 128, 256, 512, 1024, 2048, 4096)}
+    fl = out[3]
+    fs_frac = float(((fl & 1) == 0).double().mean().item())
     return dict(ms_per_step=1e3 * wall / steps, fs_kernel_ms=float(np.mean(fs_ms)),
-                event_ms=float(np.mean(tot_ms)), mlp_ms=float(np.mean(mlp_ms)), stats=st,
-                fs_fraction=float(np.mean((fl & 1) == 0)), mag=out[0],
-                samples_hist=hist, samples_max=int(nfs.max()) if nfs.size else 0)
+                event_ms=float(np.mean(tot_ms)), mlp_ms=float(np.mean(mlp_ms)),
+                ps_ms=float(np.mean(ps_ms)), stats=st, fs_fraction=fs_frac, out=out)
 
 
-def cpu_baseline(c, seconds, seed=11):
-    """The oracle as it stands: point-source test, else contour integration at
-    the same tolerance, one epoch after another on one core, over a seeded
-    random sample of the batch's epochs until the time budget is used."""
+def samples_histogram(out, n_annuli):
+    """Limb samples per contour task of the finite-source epochs (a limb-
+    darkened epoch reports the sum over its annuli: divided by n_annuli)."""
+    fl = out[3]
+    ns = out[2][(fl & 1) == 0].double() / n_annuli
+    hist = {f"<= {b}": int((ns <= b).sum().item()) for b in (64, 128, 256, 512, 1024, 2048, 4096)}
+    return hist, float(ns.max().item()) if ns.numel() else 0.0
+
+
+def cpu_count():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_epoch(c, i, tol, tight):
+    """The oracle's magnification of epoch i (set-major index): the point
+    value when its point-source test passes (tight=False only), else the
+    uniform disk or, with limb darkening, the annulus combination; tight=True
+    runs the contour at the oracle's tight tolerance, otherwise at the
+    stated one (annuli at half of it, as the library runs them)."""
     from oracle import ref
+    k, j = divmod(int(i), c.nepochs)
+    zx, zy = ref.trajectory(c.u0[k], c.alpha[k], c.tau[j:j + 1])
+    if not tight:
+        ok, mu = ref.ps_adequate(c.s[k], c.q[k], complex(zx[0], zy[0]), c.rho[k], tol)
+        if ok:
+            return mu
+    if c.gamma is None:
+        if tight:
+            return ref.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], ref.TIGHT_TOL, ref.tight_cfg())[0][0]
+        return ref.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], tol)[0][0]
+    na = c.n_annuli
+    mk = []
+    for a in range(1, na + 1):
+        r = c.rho[k] * np.sqrt(a / na)
+        if tight:
+            mk.append(ref.finite_mag(c.s[k], c.q[k], zx, zy, r, ref.TIGHT_TOL, ref.tight_cfg())[0][0])
+        else:
+            mk.append(ref.finite_mag(c.s[k], c.q[k], zx, zy, r, 0.5 * tol)[0][0])
+    return ref.ld_combine(c.gamma[k], np.array(mk))
+
+
+def cpu_baseline(c, seconds, threads, seed=11):
+    """The oracle as it stands: point-source test, else contour integration
+    at the same tolerance (limb-darkened epochs: every annulus at half of
+    it, then the annulus combination), one epoch after another, over a
+    seeded random sample of the batch's epochs until the time budget is
+    used; once on one thread and once on `threads` threads over disjoint
+    epochs (the oracle is reentrant and its calls release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
     rng = np.random.default_rng(seed)
     order = rng.permutation(c.nsets * c.nepochs)
+
+    def worker(start, stride, budget):
+        t0 = time.perf_counter()
+        done = 0
+        for i in order[start::stride]:
+            oracle_epoch(c, i, c.tol, tight=False)
+            done += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return done, time.perf_counter() - t0
+
+    d1, t1 = worker(0, 1, seconds)
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(lambda w: worker(w, threads, 0.5 * seconds), range(threads)))
+    dn = sum(r[0] for r in res)
+    tn = max(r[1] for r in res)
+    host = cpu_model()
+    return dict(value=d1 / t1, unit="magnifications/s", cores=1, kind="oracle",
+                sample=f"{d1} epochs drawn at random (seed {seed}) from the {c.nsets}x{c.nepochs} batch, "
+                       f"point-source test then contour integration at tol {c.tol} (limb darkening: "
+                       f"{c.n_annuli} annuli at tol/2, then the annulus combination), single thread, "
+                       f"{t1:.1f} s; host {host}",
+                all_cores={"value": dn / tn, "unit": "magnifications/s", "cores": threads,
+                           "sample": f"{dn} epochs of the same random order split over {threads} threads, "
+                                     f"{tn:.1f} s"},
+                host_cpu=host)
+
+
+def oracle_check(c, out, other_mag, tol, threads, k=24, flagged_max=48, seed=5):
+    """Tight-oracle check of the headline's results on the epochs where it
+    and another path disagree most, where err / (tol mu) is largest, every
+    cap- or anomaly-flagged epoch (up to flagged_max, most uncertain first)
+    and random epochs (half of them among finite-source epochs)."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    mag, err, ns, fl = out
+    sel = {}
+    if other_mag is not None:
+        d = (mag / other_mag - 1).abs().nan_to_num(0.0)
+        sel["largest_disagreement"] = torch.topk(d, k).indices.cpu().numpy()
+    ratio = (err / (tol * mag.abs())).nan_to_num(0.0)
+    sel["largest_err_over_tol"] = torch.topk(ratio, k).indices.cpu().numpy()
+    flagged = torch.nonzero((fl & 6) != 0).flatten()
+    nflag = int(flagged.numel())
+    if nflag:
+        r = ratio[flagged]
+        sel["cap_or_anomaly_flagged"] = flagged[torch.argsort(r, descending=True)[:flagged_max]].cpu().numpy()
+    rng = np.random.default_rng(seed)
+    n = mag.numel()
+    fs_idx = torch.nonzero((fl & 1) == 0).flatten()
+    rand = [rng.integers(0, n, k // 2)]
+    if fs_idx.numel():
+        rand.append(fs_idx[torch.as_tensor(rng.integers(0, fs_idx.numel(), k // 2),
+                                           device=fs_idx.device)].cpu().numpy())
+    sel["random"] = np.concatenate(rand)
+    idx = np.unique(np.concatenate(list(sel.values())))
+    gm = mag[torch.as_tensor(idx, device=mag.device)].cpu().numpy()
+    gf = fl[torch.as_tensor(idx, device=mag.device)].cpu().numpy()
     t0 = time.perf_counter()
-    done = 0
-    for i in order:
-        k, j = divmod(int(i), c.nepochs)
-        zx, zy = ref.trajectory(c.u0[k], c.alpha[k], c.tau[j:j + 1])
-        ok, mu = ref.ps_adequate(c.s[k], c.q[k], complex(zx[0], zy[0]), c.rho[k], c.tol)
-        if not ok:
-            ref.finite_mag(c.s[k], c.q[k], zx, zy, c.rho[k], c.tol)
-        done += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit="magnifications/s", cores=1, kind="oracle",
-                sample=f"{done} epochs drawn at random (seed {seed}) from the 1024x2000 batch, "
-                       f"point-source test then contour integration at tol {c.tol}, single thread, "
-                       f"{dt:.1f} s")
+    with ThreadPoolExecutor(threads) as ex:
+        ref = np.array(list(ex.map(lambda i: oracle_epoch(c, i, tol, tight=True), idx)))
+    rel = np.abs(gm / ref - 1)
+    by = {}
+    for name, ids in sel.items():
+        pos = np.searchsorted(idx, ids)
+        by[name] = {"epochs": int(ids.size), "max_rel_err": float(rel[pos].max())}
+    capped = (gf & 2) != 0
+    worst = int(np.argmax(np.where(capped, -1.0, rel)))
+    res = {"epochs_checked": int(idx.size), "flagged_epochs_in_batch": nflag,
+           "max_rel_err_vs_oracle": float(rel[~capped].max()) if (~capped).any() else None,
+           "max_rel_err_cap_flagged": float(rel[capped].max()) if capped.any() else None,
+           "worst_epoch": int(idx[worst]), "by_selection": by,
+           "oracle": f"tight oracle (tol {1e-6}) on {threads} threads, {time.perf_counter() - t0:.1f} s"}
+    return res
 
 
 WEIGHTS = os.path.join(HERE, "paper_2501_03322_amd", "weights", "mlp_budget.bin")
@@ -169,8 +305,8 @@ def pmc_summary(fetch_dir, write_dir):
     """HBM traffic of one contour-kernel launch from two counter runs.
     FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by
     what it reads for the 1 GiB device copies of the same run (the copy
-    reads and writes exactly 1 GiB), and the launch is the run's last
-    contour-kernel dispatch (the timed step)."""
+    reads and writes exactly 1 GiB), and the launch figure is the mean over
+    the run's contour-kernel dispatches (every call runs the same chunks)."""
     import csv
     import glob
 
@@ -191,14 +327,14 @@ def pmc_summary(fetch_dir, write_dir):
             raise SystemExit(f"{d}: no contour-kernel or copy dispatch with {counter}")
         kib = float(1 << 20)  # 1 GiB in KiB
         factor = kib / float(np.median(cp))
-        return fs[-1] * 1024.0 * factor, factor
+        return float(np.mean(fs)) * 1024.0 * factor, factor, len(fs)
 
-    fetch, ff = read(fetch_dir, "FETCH_SIZE")
-    write, wf = read(write_dir, "WRITE_SIZE")
+    fetch, ff, nf = read(fetch_dir, "FETCH_SIZE")
+    write, wf, nw = read(write_dir, "WRITE_SIZE")
     from paper_2501_03322_amd import twk
     return {"lib_sha256": lib_digest(twk.LIB_PATH),
             "device_code_sha256": device_code_digest(twk.LIB_PATH), "hbm_bytes_per_launch": fetch + write,
-            "fetch_bytes": fetch, "write_bytes": write,
+            "fetch_bytes": fetch, "write_bytes": write, "dispatches": [nf, nw],
             "fetch_copy_factor": ff, "write_copy_factor": wf}
 
 
@@ -206,11 +342,13 @@ def path_summary(n, r):
     st = r["stats"]
     fs_s = r["fs_kernel_ms"] * 1e-3
     return {"value": n / (r["ms_per_step"] * 1e-3), "ms_per_step": r["ms_per_step"],
-            "fs_kernel_ms": r["fs_kernel_ms"], "learned_stage_ms": r["mlp_ms"],
+            "fs_kernel_ms": r["fs_kernel_ms"], "point_pass_ms": r["ps_ms"],
+            "learned_stage_ms": r["mlp_ms"], "contour_launches": int(st["launches"]),
             "contour_mags_per_s": st["fs_tasks"] / fs_s,
             "limb_solves_per_s": st["samples"] / fs_s,
             "achieved_tflops": flops_of(st) / fs_s / 1e12,
-            "samples": int(st["samples"]), "fs_tasks": int(st["fs_tasks"])}
+            "samples": int(st["samples"]), "fs_tasks": int(st["fs_tasks"]),
+            "fs_fraction": r["fs_fraction"]}
 
 
 def main():
@@ -218,16 +356,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--path-steps", type=int, default=2,
+                    help="timed calls of each other path (after one warmup call)")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle check")
     ap.add_argument("--no-plain", action="store_true",
                     help="time only the headline path (for profiling runs)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 1024 x 2000 uniform-source batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (default launch parameters)")
     ap.add_argument("--no-graphs", action="store_true",
-                    help="issue every call eagerly instead of replaying a captured graph")
+                    help="skip the graph-replay timing of the headline path")
     ap.add_argument("--tune", metavar="LDS,WAVES,SHIFT",
                     help="fixed launch tuning (LDS capacity, waves per CU, budget shift) instead "
                          "of the autotuner, e.g. to profile the configuration a bench run chose")
@@ -256,9 +399,11 @@ def main():
         from paper_2501_03322_amd import train_mlp
         train_mlp.train(WEIGHTS, log=log)
     ctx.mlp_load(WEIGHTS)
-    c = inputs.batched_curves()
+    c = inputs.large_ld_curves()
     n = c.nsets * c.nepochs
-    log(f"workload: {c.nsets} sets x {c.nepochs} epochs = {n} magnifications, tol {c.tol}")
+    a = device_args(c, dev)
+    log(f"workload: {c.nsets} sets x {c.nepochs} epochs = {n} magnifications, {c.n_annuli} annuli, "
+        f"tol {c.tol}")
 
     head_mode = twk.MODE_MLP | twk.MODE_MIXED
     if args.tune:
@@ -266,41 +411,74 @@ def main():
         ctx.set_tuning(lds_cap=int(lds), waves_per_cu=int(waves), budget_shift=float(shift))
         log(f"fixed tuning: {ctx.get_tuning().as_dict()}")
     elif not args.no_tune:
+        # every 16th parameter set: the workload's distribution at 1/16 of its size
+        sub = c.subset(np.arange(0, c.nsets, 16))
         t0 = time.perf_counter()
-        tuned = ctx.autotune(c.s, c.q, c.u0, c.alpha, c.rho, c.tau, c.tol, mode=head_mode, trials=1)
-        log(f"autotuned on the workload in {time.perf_counter() - t0:.1f} s: {tuned.as_dict()}")
+        tuned = ctx.autotune(sub.s, sub.q, sub.u0, sub.alpha, sub.rho, sub.tau, sub.tol, mode=head_mode,
+                             gamma=sub.gamma, n_annuli=sub.n_annuli, trials=1)
+        log(f"autotuned on every 16th parameter set in {time.perf_counter() - t0:.1f} s: {tuned.as_dict()}")
     tuning = ctx.get_tuning().as_dict()
-    best = run_path(ctx, dev, c, head_mode, args.steps, args.warmup, "learned+mixed")
+    best = run_path(ctx, a, c, head_mode, args.steps, args.warmup, "learned+mixed")
     graph = None
     if not args.no_graphs:
         # the same path replayed from a captured graph (timed as whole calls)
         ctx.set_tuning(graphs=1)
-        g = run_path(ctx, dev, c, head_mode, args.steps, args.warmup, "learned+mixed, graph replay")
+        g = run_path(ctx, a, c, head_mode, args.path_steps, 1, "learned+mixed, graph replay")
         ctx.set_tuning(graphs=0)
         graph = {"ms_per_step": g["ms_per_step"], "event_ms": g["event_ms"],
                  "value": n / (g["ms_per_step"] * 1e-3),
-                 "bitwise_equal_to_eager": bool(torch.equal(g["mag"], best["mag"]))}
+                 "bitwise_equal_to_eager": bool(torch.equal(g["out"][0], best["out"][0]))}
+        del g
     others = {}
     if not args.no_plain:
-        others["mixed"] = run_path(ctx, dev, c, twk.MODE_MIXED, args.steps, args.warmup, "mixed")
-        others["plain_fp64"] = run_path(ctx, dev, c, twk.MODE_FP64, args.steps, args.warmup, "fp64")
-        for k, r in others.items():
-            rel = (best["mag"] / r["mag"] - 1).abs().max().item()
-            log(f"max relative difference learned+mixed vs {k} over the batch: {rel:.3g}")
-            r["max_rel_diff_vs_headline"] = rel
+        paths = [("mixed", twk.MODE_MIXED), ("fp64", twk.MODE_FP64)]
+        if hasattr(twk, "MODE_ROUNDS"):
+            paths.append(("plain_fp64_rounds", twk.MODE_FP64 | twk.MODE_ROUNDS))
+        for name, mode in paths:
+            others[name] = run_path(ctx, a, c, mode, args.path_steps, 1, name)
+            rel = (best["out"][0] / others[name]["out"][0] - 1).abs().max().item()
+            log(f"max relative difference learned+mixed vs {name} over the batch: {rel:.3g}")
+            others[name]["max_rel_diff_vs_headline"] = rel
+            if name != "plain_fp64_rounds" and "plain_fp64_rounds" in [p[0] for p in paths]:
+                others[name]["out"] = (others[name]["out"][0],)  # keep the values only
+
+    threads = cpu_count()
+    check = None
+    if not args.no_check:
+        plain = others.get("plain_fp64_rounds", others.get("fp64"))
+        log(f"oracle check of the headline results on {threads} threads")
+        check = oracle_check(c, best["out"], plain["out"][0] if plain else None, c.tol, threads)
+        log(f"oracle check: {json.dumps(check)}")
+
+    batch = None
+    if not args.no_batch:
+        cb = inputs.batched_curves()
+        ab = device_args(cb, dev)
+        nb = cb.nsets * cb.nepochs
+        batch = {"workload": "batched light curves: 1024 parameter sets x 2000 epochs, uniform source, "
+                             "tol 1e-4 (seed 1)", "paths": {}}
+        bpaths = [("learned+mixed", head_mode), ("fp64", twk.MODE_FP64)]
+        if hasattr(twk, "MODE_ROUNDS"):
+            bpaths.append(("plain_fp64_rounds", twk.MODE_FP64 | twk.MODE_ROUNDS))
+        for name, mode in bpaths:
+            r = run_path(ctx, ab, cb, mode, max(args.path_steps, 5), 1, f"batch {name}")
+            batch["paths"][name] = path_summary(nb, r)
+            del r
 
     if args.copy_probe:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1.0)
+        x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        x.fill_(1.0)
         for _ in range(3):
-            b.copy_(a)
+            y.copy_(x)
         torch.cuda.synchronize()
         log("copy probe: 3 x 1 GiB device-to-device copies done")
 
     st = best["stats"]
     flops = flops_of(st)
+    launches = max(int(st["launches"]), 1)
     achieved = flops / (best["fs_kernel_ms"] * 1e-3) / 1e12
+    hist, smax = samples_histogram(best["out"], c.n_annuli)
     out = {
         "metric": METRIC,
         "value": n / (best["ms_per_step"] * 1e-3),
@@ -314,33 +492,45 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "batched light curves: 1024 parameter sets x 2000 epochs, uniform source, "
-                               "tol 1e-4, one persistent launch (seed 1)",
-                   "nsets": c.nsets, "nepochs": c.nepochs, "tol": c.tol,
+        "config": {"workload": "high-cadence limb-darkened light curves: 16384 parameter sets x 8000 "
+                               "epochs, linear limb darkening over 10 annuli, tol 1e-4 (seed 4)",
+                   "nsets": c.nsets, "nepochs": c.nepochs, "n_annuli": c.n_annuli, "tol": c.tol,
                    "path": "learned budget + batched persistent + mixed precision"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
                      "traffic": measured_traffic(twk.LIB_PATH),
                      "kernel": f"k_fs<{tuning['lds_cap']}, mixed>",
-                     "flops_per_launch": flops, "kernel_ms": best["fs_kernel_ms"]},
+                     "launches_per_step": launches,
+                     "flops_per_launch": flops / launches,
+                     "kernel_ms_per_launch": best["fs_kernel_ms"] / launches},
         "work": {"fs_fraction": best["fs_fraction"], **{k: int(v) for k, v in st.items()},
-                 "samples_per_source_cumulative": best["samples_hist"],
-                 "samples_per_source_max": best["samples_max"]},
+                 "samples_per_contour_cumulative": hist, "samples_per_contour_max": smax},
         "paths": {"learned+mixed": path_summary(n, best)},
         "tuning": tuning,
         "graph_replay": graph,
+        "oracle_check": check,
         "paper_context": "the paper reports ~1e2 speedup of its GPU code (RTX 4090) over one CPU core "
                          "(EPYC 7H12, VBBL) on its own benchmarks; other hardware and workload",
     }
     for k, r in others.items():
         out["paths"][k] = path_summary(n, r)
         out["paths"][k]["max_rel_diff_vs_headline"] = r["max_rel_diff_vs_headline"]
-    if "plain_fp64" in others:
-        out["speedup_vs_plain_fp64"] = others["plain_fp64"]["ms_per_step"] / best["ms_per_step"]
+    for k in ("plain_fp64_rounds", "fp64"):
+        if k in others:
+            out["speedup_vs_plain"] = {"plain": k, "x": others[k]["ms_per_step"] / best["ms_per_step"]}
+            break
+    if batch is not None:
+        out["batch_1024x2000"] = batch
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle for about {args.cpu_seconds:.0f} s")
-        out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds)
+        log(f"cpu baseline: oracle for about {args.cpu_seconds:.0f} s on one thread, then "
+            f"{args.cpu_seconds / 2:.0f} s on {threads}")
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds, threads)
     print(json.dumps(out), flush=True)
+    if check is not None and check["max_rel_err_vs_oracle"] is not None and \
+            check["max_rel_err_vs_oracle"] > c.tol:
+        log(f"FAILED: an unflagged headline result misses the tolerance against the oracle "
+            f"({check['max_rel_err_vs_oracle']:.3g} > {c.tol})")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

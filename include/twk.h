@@ -51,6 +51,14 @@ extern "C" {
 #define TWK_MODE_MIXED (1u << 0)   /* FP32 bulk root iterations + FP64 polish  */
 #define TWK_MODE_MLP (1u << 2)     /* learned sample budget / FS predictor      */
 #define TWK_MODE_ALL_FS (1u << 3)  /* skip the point-source test: contour always */
+/* The paper's dispatch of the contour work (Secs. 3, 4.1) instead of the
+ * persistent kernel: sources in batches of up to 32768, one kernel launch
+ * per refinement round over the list of the batch's unfinished sources,
+ * whose records stay in global memory between launches; the host reads the
+ * list's length after every round (the call waits for the point-source
+ * pass and for each round; it is never captured in a graph).  Results are
+ * those of the persistent kernel (same rounds, same arithmetic). */
+#define TWK_MODE_ROUNDS (1u << 4)
 
 #define TWK_FLAG_POINT (1u << 0)
 #define TWK_FLAG_CAP (1u << 1)
@@ -158,18 +166,19 @@ int twk_mag_map(twk_ctx *ctx, double s, double q, double rho, double xc, double 
  * outgrew LDS (continued in global memory), out[2] = limb samples of the
  * returned results, out[3] = persistent waves launched, out[4] = FP32 root
  * sweeps, out[5] = FP64 root sweeps (one sweep updates all five roots of one
- * limb point), out[6] = intervals linked, out[7] = contour runs.
- * Synchronises the context's stream. */
+ * limb point), out[6] = intervals linked, out[7] = contour-kernel launches
+ * of the call (one per chunk; a call is split into chunks of at most 2^24
+ * contour tasks).  Synchronises the context's stream. */
 int twk_last_stats(twk_ctx *ctx, int64_t *out8);
 
 /* Per-kernel timing with HIP events on the context's stream (on != 0 to
  * enable).  After a finite-source call, twk_kernel_times writes (host
- * pointer ms[5], milliseconds): for the first chunk the point-source pass,
- * the learned stage (0 without TWK_MODE_MLP) and the contour kernel; then
- * the rest of the call and the whole call.  A call replayed from a captured
- * graph is timed as a whole: the three stage entries read 0 and the rest
- * and whole-call entries both hold the whole call.  Waits for the call.
- * Errors: TWK_EINVAL if timing is off. */
+ * pointer ms[5], milliseconds), each summed over the call's chunks: the
+ * point-source pass, the learned stage (0 without TWK_MODE_MLP) and the
+ * contour kernel; then the rest of the call and the whole call.  A call
+ * replayed from a captured graph is timed as a whole: the three stage
+ * entries read 0 and the rest and whole-call entries both hold the whole
+ * call.  Waits for the call.  Errors: TWK_EINVAL if timing is off. */
 int twk_enable_timing(twk_ctx *ctx, int on);
 int twk_kernel_times(twk_ctx *ctx, double *ms5);
 

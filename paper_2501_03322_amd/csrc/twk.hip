@@ -51,7 +51,7 @@ enum {
   C_NTASK = 0,     // tasks queued by the point-source pass
   C_HEAD = 1,      // queue head of the first FS pass
   C_NOVER = 2,     // tasks whose sorted arrays outgrew LDS
-  C_HEAD2 = 3,     // unused
+  C_NOUT = 3,      // round-by-round dispatch: sources left unfinished by a round
   C_SAMPLES = 4,   // limb samples of finished tasks
   C_SW32 = 5,      // FP32 root sweeps (5 roots each)
   C_SW64 = 6,      // FP64 root sweeps
@@ -612,6 +612,76 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES
   }
 }
 
+// Round-by-round dispatch (the paper's, Secs. 3, 4.1): one launch per
+// refinement round over the list of unfinished sources of a batch, one
+// wave per source.  list_in == null: the batch's first round (every source
+// b = block index starts); otherwise the sources listed.  A source that is
+// not finished is appended to list_out (count in *n_out).  Sources b of the
+// batch are tasks b0 + b (in the learned queue order when order is given);
+// each has its global slice b and its state rs[b].
+template <bool MIXED>
+__global__ __launch_bounds__(64) void k_fs_round(const Task* tasks, int64_t b0,
+                                                 const int32_t* order, const int32_t* tn0,
+                                                 const int32_t* list_in, int32_t* list_out,
+                                                 long long* n_out, RoundState* rs, char* slices,
+                                                 double tol, double* mag, double* err, int32_t* ns,
+                                                 uint32_t* flags) {
+  __shared__ int ivl[NNEW];
+  const int lane = threadIdx.x;
+  const bool fresh = list_in == nullptr;
+  const int b = fresh ? (int)blockIdx.x : list_in[blockIdx.x];
+  int64_t t = b0 + b;
+  if (order) t = order[t];
+  const Task task = tasks[t];
+  const int n0 = tn0 ? tn0[t] : NNEW;
+  const WaveMem<MIXED> m = wave_mem<MIXED>(slices, b);
+  FsOut o;
+  if (fs_round_step<MIXED>(task, tol, m, (lint*)ivl, lane, n0, &rs[b], fresh, &o)) {
+    if (lane == 0) {
+      mag[task.out] = o.mag;
+      err[task.out] = o.err;
+      ns[task.out] = o.n;
+      flags[task.out] = o.flags;
+    }
+  } else if (lane == 0) {
+    list_out[atomicAdd((unsigned long long*)n_out, 1ull)] = b;
+  }
+}
+
+// Work counters of a finished batch of the round-by-round dispatch: block
+// sums of the sources' totals, one atomic per counter and block.
+__global__ __launch_bounds__(256) void k_round_stats(const RoundState* rs, int64_t nb,
+                                                     long long* cnt) {
+  __shared__ double part[4][256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < nb) {
+    v[0] = rs[i].N;
+    v[1] = rs[i].sw32;
+    v[2] = rs[i].sw64;
+    v[3] = rs[i].nint;
+  }
+  for (int k = 0; k < 4; ++k) part[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int k = 0; k < 4; ++k) part[k][threadIdx.x] += part[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t runs = std::min<int64_t>(256, nb - (int64_t)blockIdx.x * 256);
+    atomicAdd((unsigned long long*)&cnt[C_SAMPLES], (unsigned long long)part[0][0]);
+    atomicAdd((unsigned long long*)&cnt[C_SW32], (unsigned long long)part[1][0]);
+    atomicAdd((unsigned long long*)&cnt[C_SW64], (unsigned long long)part[2][0]);
+    atomicAdd((unsigned long long*)&cnt[C_INTERVALS], (unsigned long long)part[3][0]);
+    atomicAdd((unsigned long long*)&cnt[C_RUNS], (unsigned long long)runs);
+  }
+}
+
+__global__ void k_zero_counter(long long* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ host
@@ -632,7 +702,12 @@ struct twk_ctx {
   char* ann = nullptr;  // [mag f64 | err f64 | ns i32 | flags u32] x (nfs * na)
   size_t ann_bytes = 0;
   bool timing = false;
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // per-stage timing: ev[0] and ev[1] bracket the call; chunk k of the call
+  // has ev[2 + 4k + j], j = before the point pass, after it, after the
+  // learned stage, after the contour kernel
+  std::vector<hipEvent_t> ev;
+  int64_t ev_chunks = 0;   // chunks whose stages the last timed call marked
+  int64_t last_chunks = 0; // contour-kernel launches of the last call
   // launch tuning of the contour stage, and graph replay
   twk_tuning tune{0, 128, 1.0f, 0};
   int occ[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // resident waves per CU [LDS cap][fp64, mixed]
@@ -650,6 +725,14 @@ struct twk_ctx {
   char* lt = nullptr;               // per task: features, outputs, n0, order
   size_t lt_bytes = 0;
   int64_t lt_cap = 0;
+  // round-by-round dispatch: per-source global slices, states and the two
+  // lists of unfinished sources of a batch
+  char* rslices = nullptr;
+  size_t rslices_bytes = 0;
+  char* rstate = nullptr;
+  size_t rstate_bytes = 0;
+  int32_t* rlist = nullptr;
+  size_t rlist_bytes = 0;
   // training
   char* tr = nullptr;
   size_t tr_bytes = 0;
@@ -849,18 +932,93 @@ int launch_fs(twk_ctx* c, bool mixed, bool learned, double tol, double* mag, dou
   return TWK_OK;
 }
 
+unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// Sources per batch of the round-by-round dispatch: each holds a global
+// slice for the method's 4096 samples (0.94 MB), so a batch takes 31 GB.
+constexpr int64_t ROUND_BATCH = 32768;
+
+// The paper's dispatch: the host reads the number of queued tasks, then
+// for each batch of sources launches one round after another over the list
+// of unfinished ones, reading the list's length after each round.
+int rounds_stage(twk_ctx* c, bool mixed, bool learned, double tol, double* mag, double* err,
+                 int32_t* ns, uint32_t* flags) {
+  long long ntask = 0, nout = 0;
+  HIP_TRY(c, hipMemcpyAsync(&ntask, &c->cnt[C_NTASK], 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (ntask <= 0) return TWK_OK;
+  const int64_t B = std::min<int64_t>(ntask, ROUND_BATCH);
+  int rc;
+  if ((rc = grow(c, (void**)&c->rslices, &c->rslices_bytes,
+                 (size_t)B * METHOD_CAP * kSlotBytesMax)) ||
+      (rc = grow(c, (void**)&c->rstate, &c->rstate_bytes, (size_t)B * sizeof(RoundState))) ||
+      (rc = grow(c, (void**)&c->rlist, &c->rlist_bytes, (size_t)2 * B * sizeof(int32_t))))
+    return rc;
+  const int32_t* order = learned ? learn_bufs(c).order : nullptr;
+  const int32_t* n0 = learned ? learn_bufs(c).n0 : nullptr;
+  RoundState* rs = (RoundState*)c->rstate;
+  for (int64_t b0 = 0; b0 < ntask; b0 += B) {
+    const int64_t nb = std::min<int64_t>(B, ntask - b0);
+    const int32_t* lin = nullptr;
+    int32_t* lout = c->rlist;
+    int64_t nin = nb;
+    while (nin > 0) {
+      hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, c->stream, &c->cnt[C_NOUT]);
+      if (mixed)
+        hipLaunchKernelGGL(k_fs_round<true>, dim3((unsigned)nin), dim3(64), 0, c->stream, c->tasks,
+                           b0, order, n0, lin, lout, &c->cnt[C_NOUT], rs, c->rslices, tol, mag, err,
+                           ns, flags);
+      else
+        hipLaunchKernelGGL(k_fs_round<false>, dim3((unsigned)nin), dim3(64), 0, c->stream,
+                           c->tasks, b0, order, n0, lin, lout, &c->cnt[C_NOUT], rs, c->rslices,
+                           tol, mag, err, ns, flags);
+      HIP_TRY(c, hipGetLastError());
+      HIP_TRY(c, hipMemcpyAsync(&nout, &c->cnt[C_NOUT], 8, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      nin = nout;
+      lin = lout;
+      lout = lout == c->rlist ? c->rlist + B : c->rlist;
+    }
+    hipLaunchKernelGGL(k_round_stats, dim3(blocks_for(nb)), dim3(256), 0, c->stream, rs, nb,
+                       c->cnt);
+    HIP_TRY(c, hipGetLastError());
+  }
+  return TWK_OK;
+}
+
 int reset(twk_ctx* c, bool queue_only) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, c->cnt, queue_only ? 1 : 0);
   HIP_TRY(c, hipGetLastError());
   return TWK_OK;
 }
 
-int mark(twk_ctx* c, int i, bool on) {
-  if (c->timing && on && !c->capturing) HIP_TRY(c, hipEventRecord(c->ev[i], c->stream));
+// Event j of chunk k (j = 0: before the point pass, 1: after it, 2: after
+// the learned stage, 3: after the contour kernel).
+int mark(twk_ctx* c, int64_t k, int j) {
+  if (c->timing && !c->capturing && k < c->ev_chunks)
+    HIP_TRY(c, hipEventRecord(c->ev[2 + 4 * k + j], c->stream));
   return TWK_OK;
 }
 
-unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+int mark_call(twk_ctx* c, int j) {
+  if (c->timing && !c->capturing) HIP_TRY(c, hipEventRecord(c->ev[j], c->stream));
+  return TWK_OK;
+}
+
+// Before issuing a call of `chunks` chunks: events for every stage of every
+// chunk (created here, outside any capture).
+int prepare_call(twk_ctx* c, int64_t chunks) {
+  c->last_chunks = chunks;
+  if (!c->timing) return TWK_OK;
+  const size_t need = 2 + 4 * (size_t)chunks;
+  while (c->ev.size() < need) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  c->ev_chunks = chunks;
+  return TWK_OK;
+}
 
 bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
 
@@ -940,9 +1098,11 @@ int twk_destroy(twk_ctx* c) {
   (void)hipFree(c->cnt);
   (void)hipFree(c->fs_epoch);
   (void)hipFree(c->ann);
+  (void)hipFree(c->rslices);
+  (void)hipFree(c->rstate);
+  (void)hipFree(c->rlist);
   drop_graphs(c);
-  for (int i = 0; i < 5; ++i)
-    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   (void)hipFree(c->mlp_p);
   (void)hipFree(c->mlp_frag);
   (void)hipFree(c->lt);
@@ -981,10 +1141,12 @@ int twk_point_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, c
 
 namespace {
 
-constexpr uint32_t KNOWN_MODES = TWK_MODE_MIXED | TWK_MODE_MLP | TWK_MODE_ALL_FS;
+constexpr uint32_t KNOWN_MODES = TWK_MODE_MIXED | TWK_MODE_MLP | TWK_MODE_ALL_FS | TWK_MODE_ROUNDS;
 
-// Identity of a call for graph replay: entry point, scalar arguments (as
-// bits), device pointers and tuning.
+// Identity of a call for graph replay: entry point (ORed with ROUNDS_KEY
+// for the round-by-round dispatch), scalar arguments (as bits), device
+// pointers and tuning.
+constexpr uint64_t ROUNDS_KEY = 1ull << 32;
 struct CallKey {
   uint64_t w[24] = {};
   int n = 0;
@@ -1010,20 +1172,21 @@ CallKey& tuning_key(CallKey& k, const twk_ctx* c) {
 // Issue the launch sequence of a call, or, with graph replay on, replay
 // the captured sequence of an identical earlier call (capturing it the
 // first time).  Nothing inside `issue` may allocate or synchronise.
-// With timing on, a replayed call is timed as a whole: events 0..3 before
-// the graph launch, 4 after it (the stage times read 0, the rest of the
-// call is the whole call).
+// With timing on, a replayed call is timed as a whole (the stage times
+// read 0, the rest of the call is the whole call).
 int launch_graph(twk_ctx* c, hipGraphExec_t ex) {
-  if (c->timing)
-    for (int i = 0; i < 4; ++i) HIP_TRY(c, hipEventRecord(c->ev[i], c->stream));
+  c->ev_chunks = 0;
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
   HIP_TRY(c, hipGraphLaunch(ex, c->stream));
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[4], c->stream));
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
   return TWK_OK;
 }
 
 template <class F>
 int run_captured(twk_ctx* c, const CallKey& key, F&& issue) {
-  if (!c->tune.graphs) return issue();
+  // the round-by-round dispatch reads counts on the host between launches
+  // and cannot be captured
+  if (!c->tune.graphs || (key.w[0] & ROUNDS_KEY)) return issue();
   for (int i = 0; i < c->n_graphs; ++i)
     if (std::memcmp(c->graphs[i].key, key.w, sizeof(key.w)) == 0)
       return launch_graph(c, c->graphs[i].exec);
@@ -1061,16 +1224,23 @@ int check_mode(twk_ctx* c, uint32_t mode) {
   return TWK_OK;
 }
 
-// After the point-source pass of one chunk: learned stage (if any), then
-// the contour kernel.  Events 1..3 bracket the first chunk's stages.
-int contour_stage(twk_ctx* c, bool first, bool mixed, bool learned, int64_t ntask_max,
-                  double tol, double* mag, double* err, int32_t* ns, uint32_t* flags) {
+// After the point-source pass of chunk k: learned stage (if any), then the
+// contour kernel, each bracketed by the chunk's stage events.
+int contour_stage(twk_ctx* c, int64_t k, uint32_t mode, int64_t ntask_max, double tol,
+                  double* mag, double* err, int32_t* ns, uint32_t* flags) {
   int rc;
-  if ((rc = mark(c, 1, first))) return rc;
+  const bool mixed = (mode & TWK_MODE_MIXED) != 0, learned = (mode & TWK_MODE_MLP) != 0;
+  if ((rc = mark(c, k, 1))) return rc;
   if (learned && (rc = learned_stage(c, ntask_max))) return rc;
-  if ((rc = mark(c, 2, first))) return rc;
-  if ((rc = launch_fs(c, mixed, learned, tol, mag, err, ns, flags))) return rc;
-  return mark(c, 3, first);
+  if ((rc = mark(c, k, 2))) return rc;
+  if (mode & TWK_MODE_ROUNDS) rc = rounds_stage(c, mixed, learned, tol, mag, err, ns, flags);
+  else rc = launch_fs(c, mixed, learned, tol, mag, err, ns, flags);
+  if (rc) return rc;
+  return mark(c, k, 3);
+}
+
+uint64_t entry_key(int id, uint32_t mode) {
+  return (uint64_t)id | ((mode & TWK_MODE_ROUNDS) ? ROUNDS_KEY : 0ull);
 }
 
 }  // namespace
@@ -1093,25 +1263,26 @@ int twk_finite_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, 
   if ((rc = ensure_fs(c, chunk))) return rc;
   if (learned && (rc = ensure_learn(c, chunk))) return rc;
   const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
-  const bool mixed = (mode & TWK_MODE_MIXED) != 0;
   float* tfeat = learned ? learn_bufs(c).feat : nullptr;
   CallKey key;
-  key.u(1).d(s).d(q).u((uint64_t)n).p(zx).p(zy).d(rho).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
+  key.u(entry_key(1, mode)).d(s).d(q).u((uint64_t)n).p(zx).p(zy).d(rho).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
+  if ((rc = prepare_call(c, (n + chunk - 1) / chunk))) return rc;
   return run_captured(c, tuning_key(key, c), [&]() -> int {
     int r;
-    if ((r = mark(c, 0, true)) || (r = reset(c, false))) return r;
+    if ((r = mark_call(c, 0)) || (r = reset(c, false))) return r;
     for (int64_t i0 = 0; i0 < n; i0 += chunk) {
       const int64_t m = std::min(chunk, n - i0);
       if (i0 > 0 && (r = reset(c, true))) return r;
+      if ((r = mark(c, i0 / chunk, 0))) return r;
       hipLaunchKernelGGL(k_prep, dim3(blocks_for(m)), dim3(256), 0, c->stream, s, q, m, zx + i0,
                          zy + i0, rho, tol, all_fs, c->tasks, c->cnt, mag + i0, err + i0, ns + i0,
                          flags + i0, tfeat);
       HIP_TRY(c, hipGetLastError());
-      if ((r = contour_stage(c, i0 == 0, mixed, learned, m, tol, mag + i0, err + i0, ns + i0,
+      if ((r = contour_stage(c, i0 / chunk, mode, m, tol, mag + i0, err + i0, ns + i0,
                              flags + i0)))
         return r;
     }
-    return mark(c, 4, true);
+    return mark_call(c, 1);
   });
 }
 
@@ -1129,25 +1300,26 @@ int twk_finite_mag_each(twk_ctx* c, int64_t n, const double* s, const double* q,
   if ((rc = ensure_fs(c, chunk))) return rc;
   if (learned && (rc = ensure_learn(c, chunk))) return rc;
   const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
-  const bool mixed = (mode & TWK_MODE_MIXED) != 0;
   float* tfeat = learned ? learn_bufs(c).feat : nullptr;
   CallKey key;
-  key.u(4).u((uint64_t)n).p(s).p(q).p(zx).p(zy).p(rho).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
+  key.u(entry_key(4, mode)).u((uint64_t)n).p(s).p(q).p(zx).p(zy).p(rho).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
+  if ((rc = prepare_call(c, (n + chunk - 1) / chunk))) return rc;
   return run_captured(c, tuning_key(key, c), [&]() -> int {
     int r;
-    if ((r = mark(c, 0, true)) || (r = reset(c, false))) return r;
+    if ((r = mark_call(c, 0)) || (r = reset(c, false))) return r;
     for (int64_t i0 = 0; i0 < n; i0 += chunk) {
       const int64_t m = std::min(chunk, n - i0);
       if (i0 > 0 && (r = reset(c, true))) return r;
+      if ((r = mark(c, i0 / chunk, 0))) return r;
       hipLaunchKernelGGL(k_prep_each, dim3(blocks_for(m)), dim3(256), 0, c->stream, s + i0, q + i0,
                          m, zx + i0, zy + i0, rho + i0, tol, all_fs, c->tasks, c->cnt, mag + i0,
                          err + i0, ns + i0, flags + i0, tfeat);
       HIP_TRY(c, hipGetLastError());
-      if ((r = contour_stage(c, i0 == 0, mixed, learned, m, tol, mag + i0, err + i0, ns + i0,
+      if ((r = contour_stage(c, i0 / chunk, mode, m, tol, mag + i0, err + i0, ns + i0,
                              flags + i0)))
         return r;
     }
-    return mark(c, 4, true);
+    return mark_call(c, 1);
   });
 }
 
@@ -1169,25 +1341,26 @@ int twk_mag_map(twk_ctx* c, double s, double q, double rho, double xc, double yc
   if ((rc = ensure_fs(c, rows * nx))) return rc;
   if (learned && (rc = ensure_learn(c, rows * nx))) return rc;
   const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
-  const bool mixed = (mode & TWK_MODE_MIXED) != 0;
   float* tfeat = learned ? learn_bufs(c).feat : nullptr;
   CallKey key;
-  key.u(2).d(s).d(q).d(rho).d(xc).d(yc).d(width).d(height).u((uint64_t)nx).u((uint64_t)ny).d(tol)
+  key.u(entry_key(2, mode)).d(s).d(q).d(rho).d(xc).d(yc).d(width).d(height).u((uint64_t)nx).u((uint64_t)ny).d(tol)
       .u(mode).p(mag).p(err).p(ns).p(flags);
+  if ((rc = prepare_call(c, (ny + rows - 1) / rows))) return rc;
   return run_captured(c, tuning_key(key, c), [&]() -> int {
     int r;
-    if ((r = mark(c, 0, true)) || (r = reset(c, false))) return r;
+    if ((r = mark_call(c, 0)) || (r = reset(c, false))) return r;
     for (int64_t y0 = 0; y0 < ny; y0 += rows) {
       const int64_t nr = std::min<int64_t>(rows, ny - y0);
       if (y0 > 0 && (r = reset(c, true))) return r;
+      if ((r = mark(c, y0 / rows, 0))) return r;
       hipLaunchKernelGGL(k_map, dim3(blocks_for(nr * nx)), dim3(256), 0, c->stream, s, q, rho, xc,
                          yc, width, height, nx, ny, y0, nr, tol, all_fs, c->tasks, c->cnt, mag, err,
                          ns, flags, tfeat);
       HIP_TRY(c, hipGetLastError());
-      if ((r = contour_stage(c, y0 == 0, mixed, learned, nr * nx, tol, mag, err, ns, flags)))
+      if ((r = contour_stage(c, y0 / rows, mode, nr * nx, tol, mag, err, ns, flags)))
         return r;
     }
-    return mark(c, 4, true);
+    return mark_call(c, 1);
   });
 }
 
@@ -1215,29 +1388,30 @@ int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q,
   if (ld && (rc = ensure_ld(c, chunk_n, na))) return rc;
   const AnnBufs ab = ld ? ann_bufs(c, chunk_n * na) : AnnBufs{nullptr, nullptr, nullptr, nullptr};
   const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
-  const bool mixed = (mode & TWK_MODE_MIXED) != 0;
   float* tfeat = learned ? learn_bufs(c).feat : nullptr;
   // The limb-darkened value is a weighted difference of the annulus values,
   // which roughly doubles their relative error: annuli run at tol / 2.
   const double tol_fs = ld ? 0.5 * tol : tol;
   CallKey key;
-  key.u(3).u((uint64_t)nsets).p(s).p(q).p(u0).p(alpha).p(rho).p(gamma).u((uint64_t)nepochs).p(tau)
+  key.u(entry_key(3, mode)).u((uint64_t)nsets).p(s).p(q).p(u0).p(alpha).p(rho).p(gamma).u((uint64_t)nepochs).p(tau)
       .u((uint64_t)n_annuli).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
+  if ((rc = prepare_call(c, (nsets + chunk_sets - 1) / chunk_sets))) return rc;
   return run_captured(c, tuning_key(key, c), [&]() -> int {
     int r;
-    if ((r = mark(c, 0, true)) || (r = reset(c, false))) return r;
+    if ((r = mark_call(c, 0)) || (r = reset(c, false))) return r;
     for (int64_t k0 = 0; k0 < nsets; k0 += chunk_sets) {
       const int64_t nk = std::min(chunk_sets, nsets - k0);
       const int64_t o = k0 * nepochs;
       if (k0 > 0 && (r = reset(c, true))) return r;
+      if ((r = mark(c, k0 / chunk_sets, 0))) return r;
       hipLaunchKernelGGL(k_lc, dim3(blocks_for(lc_lanes(nk, nepochs))), dim3(256), 0, c->stream, nk,
                          s + k0, q + k0, u0 + k0, alpha + k0, rho + k0, nepochs, tau, tol, all_fs,
                          na, c->tasks, c->cnt, c->fs_epoch, mag + o, err + o, ns + o, flags + o,
                          tfeat);
       HIP_TRY(c, hipGetLastError());
-      if (ld) r = contour_stage(c, k0 == 0, mixed, learned, nk * nepochs * na, tol_fs, ab.mag,
+      if (ld) r = contour_stage(c, k0 / chunk_sets, mode, nk * nepochs * na, tol_fs, ab.mag,
                                 ab.err, ab.ns, ab.flags);
-      else r = contour_stage(c, k0 == 0, mixed, learned, nk * nepochs, tol_fs, mag + o, err + o,
+      else r = contour_stage(c, k0 / chunk_sets, mode, nk * nepochs, tol_fs, mag + o, err + o,
                              ns + o, flags + o);
       if (r) return r;
       if (ld) {
@@ -1247,7 +1421,7 @@ int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q,
         HIP_TRY(c, hipGetLastError());
       }
     }
-    return mark(c, 4, true);
+    return mark_call(c, 1);
   });
 }
 
@@ -1263,26 +1437,37 @@ int twk_last_stats(twk_ctx* c, int64_t* out8) {
   out8[4] = h[C_SW32];
   out8[5] = h[C_SW64];
   out8[6] = h[C_INTERVALS];
-  out8[7] = h[C_RUNS];
+  out8[7] = c->last_chunks;
   return TWK_OK;
 }
 
 int twk_enable_timing(twk_ctx* c, int on) {
   if (!c) return TWK_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
-  if (on && !c->ev[0])
-    for (int i = 0; i < 5; ++i) HIP_TRY(c, hipEventCreate(&c->ev[i]));
+  while (on && c->ev.size() < 2) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
   c->timing = on != 0;
+  c->ev_chunks = 0;
   return TWK_OK;
 }
 
 int twk_kernel_times(twk_ctx* c, double* ms5) {
   if (!c || !ms5 || !c->timing) return TWK_EINVAL;
-  HIP_TRY(c, hipEventSynchronize(c->ev[4]));
-  float v[4], t = 0.f;
-  for (int i = 0; i < 4; ++i) HIP_TRY(c, hipEventElapsedTime(&v[i], c->ev[i], c->ev[i + 1]));
-  HIP_TRY(c, hipEventElapsedTime(&t, c->ev[0], c->ev[4]));
-  for (int i = 0; i < 4; ++i) ms5[i] = v[i];
+  HIP_TRY(c, hipEventSynchronize(c->ev[1]));
+  double st[3] = {0.0, 0.0, 0.0};
+  for (int64_t k = 0; k < c->ev_chunks; ++k)
+    for (int j = 0; j < 3; ++j) {
+      float v = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&v, c->ev[2 + 4 * k + j], c->ev[2 + 4 * k + j + 1]));
+      st[j] += v;
+    }
+  float t = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&t, c->ev[0], c->ev[1]));
+  for (int j = 0; j < 3; ++j) ms5[j] = st[j];
+  ms5[3] = t - st[0] - st[1] - st[2];
   ms5[4] = t;
   return TWK_OK;
 }

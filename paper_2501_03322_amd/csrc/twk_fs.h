@@ -963,21 +963,29 @@ struct FsState {
   bool suspects;  // some sample may hold a misjudged ghost pair
 };
 
-// Rounds of the contour integration on the sorted arrays S.  Returns true
-// when the source is finished, false when the next round would outgrow S
-// (only the LDS copy can be outgrown): the caller moves the sorted arrays to
-// the wave's global slice and continues there.
-template <int LCAP, bool MIXED, class Sorted, class R>
-__device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 yc, double tol,
-                                          const R& m, FsLds<LCAP, MIXED>& L, const Sorted& S,
-                                          int lane, int n0, FsState& st) {
+typedef TWK_LDS_AS int lint;
+
+// How fs_rounds returned: the source is finished (stop test met, cap or no
+// placeable sample); the next round would outgrow the LDS copy of the
+// sorted arrays (the caller moves them to the wave's global slice and
+// continues there); or the round limit was reached (round-by-round
+// dispatch: the state is saved and the source continues in a later launch).
+enum { FS_DONE = 0, FS_OUTGROWN = 1, FS_PAUSED = 2 };
+
+// Rounds of the contour integration on the sorted arrays S, at most
+// max_rounds of them (negative: no limit).  ivl: the wave's LDS array of
+// NNEW interval indices of the round's new samples.
+template <bool MIXED, class Sorted, class R>
+__device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc, double tol,
+                                         const R& m, lint* ivl, const Sorted& S, int lane,
+                                         int n0, FsState& st, int max_rounds = -1) {
   const double rho = T.rho;
   // state in locals (written back once) so that it stays in registers
   int N = st.N;
   double Ahi = st.Ahi, Alo = st.Alo, A = st.A, E = st.E;
   uint32_t fl = st.fl, sw32 = st.sw32, sw64 = st.sw64, nint = st.nint;
   bool suspects = st.suspects;
-  bool outgrown = false;
+  bool outgrown = false, paused = false;
   // One round per iteration.  The first n0 samples form the uniform grid
   // theta = 2 pi i / n0, laid down 64 at a time: round r adds the phase
   // offset r / (n0 / 64) of the base grid theta_j = 2 pi j / 64 (whose
@@ -998,7 +1006,7 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
       if (N > 0) {
         // the new sample follows the r samples of base interval j
         iv = lane * r + r - 1;
-        L.ivl[rank] = iv;
+        ivl[rank] = iv;
       }
     } else {
       // error total and total tolerance-subtracted weight
@@ -1066,7 +1074,7 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
       mcount = __popcll(mask);
       if (mcount == 0) { fl |= F_CAP; break; }
       rank = __popcll(mask & ((1ull << lane) - 1ull));
-      if (valid) L.ivl[rank] = iv;
+      if (valid) ivl[rank] = iv;
     }
     // solve the new samples: the centre roots start the first round, later
     // samples start from the nearer neighbour's roots advanced along z'
@@ -1094,7 +1102,7 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
     // merge: old position p moves up by #(new samples in intervals < p);
     // strips from the top so that no unread entry is overwritten
     if (N > 0) {
-      const int myivl = lane < mcount ? L.ivl[lane] : 0x7fffffff;
+      const int myivl = lane < mcount ? ivl[lane] : 0x7fffffff;
       for (int base = ((N - 1) / WAVE) * WAVE; base >= 0; base -= WAVE) {
         const int p = base + lane;
         int sh = 0;  // number of r with ivl[r] < p (ivl ascending), 0..64
@@ -1125,7 +1133,7 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
     double dAold = 0.0;
     if (valid) {
       P = N == 0 ? lane : iv + 1 + rank;
-      first = N > 0 && (rank == 0 || L.ivl[rank - 1] != iv);
+      first = N > 0 && (rank == 0 || ivl[rank - 1] != iv);
       if (first) dAold = dA_at(m, S.sl[P - 1]);
     }
     lane_sync<Sorted>();
@@ -1170,24 +1178,42 @@ __device__ __forceinline__ bool fs_rounds(const Task& T, const Lens& lens, c64 y
     }
     lane_sync<Sorted>();
     if (suspects && slope_pass(m, S, N, lane, &Ahi, &Alo, &nint)) fl |= F_SLOPE;
+    if (--max_rounds == 0) {
+      paused = true;
+      break;
+    }
   }
   st = FsState{N, Ahi, Alo, A, E, fl, sw32, sw64, nint, suspects};
-  return !outgrown;
+  return outgrown ? FS_OUTGROWN : (paused ? FS_PAUSED : FS_DONE);
 }
 
 // Continuation of a source that outgrew its LDS copy (rare: kept out of
 // line).  Arguments and state go by value so that nothing of the hot path
 // has its address taken.
-template <int LCAP, bool MIXED>
+template <bool MIXED>
 __device__ __attribute__((noinline)) FsState fs_rounds_spilled(Task T, double tol,
-                                                               WaveMem<MIXED> m,
-                                                               FsLds<LCAP, MIXED>& L, int lane,
-                                                               FsState st) {
+                                                               WaveMem<MIXED> m, lint* ivl,
+                                                               int lane, FsState st) {
   const Lens lens = make_lens(T.s, T.q);
   const c64 yc = cz(T.zx - lens.z2, T.zy);
   const SortedG<MIXED> S{m.sth, m.sE, m.ssl, METHOD_CAP};
-  fs_rounds<LCAP, MIXED>(T, lens, yc, tol, m.G, L, S, lane, 0, st);
+  fs_rounds<MIXED>(T, lens, yc, tol, m.G, ivl, S, lane, 0, st);
   return st;
+}
+
+// Output of a finished source from its final state.
+__device__ __forceinline__ FsOut fs_output(const Task& T, const FsState& st, bool spilled) {
+  FsOut o;
+  const double area = PI_64 * T.rho * T.rho;
+  o.mag = st.A / area;
+  o.err = st.E / area;
+  o.n = st.N;
+  o.flags = wave_or(st.fl);
+  o.spilled = spilled;
+  o.sweeps32 = wave_sum((double)st.sw32);
+  o.sweeps64 = wave_sum((double)st.sw64);
+  o.intervals = wave_sum((double)st.nint);
+  return o;
 }
 
 // One source: rounds on the LDS copies of the records and sorted arrays;
@@ -1205,7 +1231,7 @@ __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem<MIXED
   const RecL<MIXED> R{(ldouble*)L.root, (lcorr_t<MIXED>*)L.dz, (lcorr_t<MIXED>*)L.w, (ldouble*)L.dA,
                (luint32*)L.meta, LCAP};
   bool spilled = false;
-  if (!fs_rounds<LCAP, MIXED>(T, lens, yc, tol, R, L, S, lane, n0, st)) {
+  if (fs_rounds<MIXED>(T, lens, yc, tol, R, (lint*)L.ivl, S, lane, n0, st) == FS_OUTGROWN) {
     for (int p = lane; p < st.N; p += WAVE) {
       gm.sth[p] = S.th[p];
       gm.sE[p] = S.E[p];
@@ -1221,20 +1247,68 @@ __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem<MIXED
       meta_at(gm.G, p) = meta_at(R, p);
     }
     __syncthreads();
-    st = fs_rounds_spilled<LCAP, MIXED>(T, tol, gm, L, lane, st);
+    st = fs_rounds_spilled<MIXED>(T, tol, gm, (lint*)L.ivl, lane, st);
     spilled = true;
   }
-  FsOut o;
-  const double area = PI_64 * T.rho * T.rho;
-  o.mag = st.A / area;
-  o.err = st.E / area;
-  o.n = st.N;
-  o.flags = wave_or(st.fl);
-  o.spilled = spilled;
-  o.sweeps32 = wave_sum((double)st.sw32);
-  o.sweeps64 = wave_sum((double)st.sw64);
-  o.intervals = wave_sum((double)st.nint);
-  return o;
+  return fs_output(T, st, spilled);
+}
+
+// ------------------------------------------------------- round-by-round dispatch
+// The paper's dispatch (Secs. 3, 4.1): one kernel launch per refinement
+// round, over the list of sources not yet finished; a source's records and
+// sorted arrays live in its global slice, and its running totals here,
+// between launches.
+struct RoundState {
+  double Ahi, Alo, A, E;
+  double sw32, sw64, nint;  // work of the rounds so far (wave totals)
+  int N;
+  uint32_t fl;              // OR of the lanes' flags so far
+  int suspects;
+  int done;
+};
+
+// One round of one source.  fresh: the source starts (its first round lays
+// down the first 64 samples of the uniform grid of n0).  Returns true when
+// the source is finished, with its output in *o; otherwise its state is
+// saved in *rs for the next launch.
+template <bool MIXED>
+__device__ bool fs_round_step(const Task& T, double tol_stated, const WaveMem<MIXED>& gm,
+                              lint* ivl, int lane, int n0, RoundState* rs, bool fresh, FsOut* o) {
+  const double tol = tol_stated * TOL_SAFETY;
+  const Lens lens = make_lens(T.s, T.q);
+  const c64 yc = cz(T.zx - lens.z2, T.zy);
+  FsState st{0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, false};
+  double base32 = 0.0, base64 = 0.0, baseint = 0.0;
+  if (!fresh) {
+    const RoundState r = *rs;
+    st = FsState{r.N, r.Ahi, r.Alo, r.A, r.E, r.fl, 0u, 0u, 0u, r.suspects != 0};
+    base32 = r.sw32;
+    base64 = r.sw64;
+    baseint = r.nint;
+  }
+  const SortedG<MIXED> S{gm.sth, gm.sE, gm.ssl, METHOD_CAP};
+  const int how = fs_rounds<MIXED>(T, lens, yc, tol, gm.G, ivl, S, lane, n0, st, 1);
+  FsOut out = fs_output(T, st, true);
+  out.sweeps32 += base32;
+  out.sweeps64 += base64;
+  out.intervals += baseint;
+  if (lane == 0) {
+    RoundState r;
+    r.Ahi = st.Ahi;
+    r.Alo = st.Alo;
+    r.A = st.A;
+    r.E = st.E;
+    r.sw32 = out.sweeps32;
+    r.sw64 = out.sweeps64;
+    r.nint = out.intervals;
+    r.N = st.N;
+    r.fl = out.flags;
+    r.suspects = st.suspects ? 1 : 0;
+    r.done = how != FS_PAUSED;
+    *rs = r;
+  }
+  *o = out;
+  return how != FS_PAUSED;
 }
 
 }  // namespace twk

@@ -19,6 +19,7 @@ MODE_FP64 = 0
 MODE_MIXED = 1 << 0
 MODE_MLP = 1 << 2
 MODE_ALL_FS = 1 << 3
+MODE_ROUNDS = 1 << 4
 
 FLAG_POINT = 1 << 0
 FLAG_CAP = 1 << 1
@@ -173,7 +174,7 @@ class Context:
         out = (C.c_int64 * 8)()
         self._check(self.lib.twk_last_stats(self.h, out), "twk_last_stats")
         return dict(fs_tasks=out[0], spilled=out[1], samples=out[2], waves=out[3],
-                    sweeps32=out[4], sweeps64=out[5], intervals=out[6], runs=out[7])
+                    sweeps32=out[4], sweeps64=out[5], intervals=out[6], launches=out[7])
 
     def enable_timing(self, on=True):
         self._check(self.lib.twk_enable_timing(self.h, 1 if on else 0), "twk_enable_timing")

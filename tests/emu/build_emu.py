@@ -19,11 +19,13 @@ def build(kgap=None, lcap=None) -> str:
     lib = os.path.join(OUT_DIR, name)
     defs = ([] if kgap is None else [f"-DTWK_KGAP={kgap!r}"]) + \
         ([] if lcap is None else [f"-DEMU_LCAP={int(lcap)}"])
-    cmd = ["g++", "-std=c++20", "-O2", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
+    cmd = ["g++", "-std=c++20", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
            "-I", os.path.join(HERE, "include")] + defs + ["-o", lib + ".tmp",
                                                         os.path.join(HERE, "engine_emu.cpp")]
+    tmp = f"{lib}.tmp{os.getpid()}"
+    cmd[cmd.index(lib + ".tmp")] = tmp
     subprocess.run(cmd, check=True)
-    os.replace(lib + ".tmp", lib)
+    os.replace(tmp, lib)
     return lib
 
 

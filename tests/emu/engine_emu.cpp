@@ -4,7 +4,6 @@
 // Test infrastructure only: the product library never uses it.
 #include <hip/hip_runtime.h>
 
-#include <thread>
 #include <vector>
 
 #include "../../paper_2501_03322_amd/csrc/twk_fs.h"
@@ -19,23 +18,63 @@ namespace {
 constexpr int LCAP = EMU_LCAP;
 
 template <bool MIXED>
+struct WaveJob {
+  const Task* T;
+  double tol;
+  int n0;
+  WaveMem<MIXED> m;
+  FsLds<LCAP, MIXED>* lds;
+  FsOut* out;
+  // round-by-round dispatch
+  RoundState* rs;
+  bool fresh;
+  bool done;
+};
+
+template <bool MIXED>
+void lane_source(int l, void* p) {
+  auto* j = (WaveJob<MIXED>*)p;
+  FsOut o = fs_source<LCAP, MIXED>(*j->T, j->tol, j->m, *j->lds, l, j->n0);
+  if (l == 0) *j->out = o;
+}
+
+template <bool MIXED>
+void lane_round(int l, void* p) {
+  auto* j = (WaveJob<MIXED>*)p;
+  FsOut o;
+  const bool d = fs_round_step<MIXED>(*j->T, j->tol, j->m, (lint*)j->lds->ivl, l, j->n0, j->rs,
+                                      j->fresh, &o);
+  if (l == 0) {
+    j->done = d;
+    if (d) *j->out = o;
+  }
+}
+
+template <bool MIXED>
 void run_wave_t(const Task& T, double tol, int n0, FsOut* out) {
   std::vector<char> scratch((size_t)METHOD_CAP * kSlotBytesMax);
-  const WaveMem<MIXED> m = wave_mem<MIXED>(scratch.data(), 0);
   auto* lds = new FsLds<LCAP, MIXED>();
-  hip_emu::Wave wave;
-  hip_emu::g_wave = &wave;
-  std::vector<std::thread> th;
-  for (int l = 0; l < hip_emu::kLanes; ++l) {
-    th.emplace_back([&, l] {
-      hip_emu::t_lane = l;
-      FsOut o = fs_source<LCAP, MIXED>(T, tol, m, *lds, l, n0);
-      if (l == 0) *out = o;
-    });
-  }
-  for (auto& t : th) t.join();
-  hip_emu::g_wave = nullptr;
+  WaveJob<MIXED> j{&T, tol, n0, wave_mem<MIXED>(scratch.data(), 0), lds, out, nullptr, false, false};
+  hip_emu::run_wave(&lane_source<MIXED>, &j);
   delete lds;
+}
+
+// The round-by-round dispatch: one emulated launch per round until the
+// source is finished; returns the number of launches.
+template <bool MIXED>
+int run_rounds_t(const Task& T, double tol, int n0, FsOut* out) {
+  std::vector<char> scratch((size_t)METHOD_CAP * kSlotBytesMax);
+  auto* lds = new FsLds<LCAP, MIXED>();
+  RoundState rs{};
+  WaveJob<MIXED> j{&T, tol, n0, wave_mem<MIXED>(scratch.data(), 0), lds, out, &rs, true, false};
+  int launches = 0;
+  while (!j.done) {
+    hip_emu::run_wave(&lane_round<MIXED>, &j);
+    j.fresh = false;
+    ++launches;
+  }
+  delete lds;
+  return launches;
 }
 
 void run_wave(const Task& T, double tol, bool mixed, int n0, FsOut* out) {
@@ -76,6 +115,35 @@ int emu_finite_mag(double s, double q, double zx, double zy, double rho, double 
     sweeps[1] = o.sweeps64;
     sweeps[2] = o.intervals;
   }
+  return 0;
+}
+
+// The same source by the round-by-round dispatch (one emulated launch per
+// refinement round, records in the global slice between launches).
+int emu_finite_mag_rounds(double s, double q, double zx, double zy, double rho, double tol,
+                          int mixed, double* mag, double* err, int* nsamp, unsigned* flags,
+                          double* sweeps, int* launches) {
+  const Lens L = make_lens(s, q);
+  Images im;
+  int it;
+  solve_point_cold(L, cz(zx - L.z2, zy), im, it);
+  Task T;
+  T.out = 0;
+  T.s = s;
+  T.q = q;
+  T.rho = rho;
+  T.zx = zx;
+  T.zy = zy;
+  for (int k = 0; k < 5; ++k) T.roots[k] = im.z[k];
+  FsOut o;
+  *launches = mixed ? run_rounds_t<true>(T, tol, NNEW, &o) : run_rounds_t<false>(T, tol, NNEW, &o);
+  *mag = o.mag;
+  *err = o.err;
+  *nsamp = o.n;
+  *flags = o.flags;
+  sweeps[0] = o.sweeps32;
+  sweeps[1] = o.sweeps64;
+  sweeps[2] = o.intervals;
   return 0;
 }
 

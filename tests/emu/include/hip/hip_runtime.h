@@ -1,14 +1,17 @@
 // CPU emulation of the few HIP device features the contour engine uses, so
 // that the unmodified device code can be compiled with g++ and run on the
 // CPU for debugging and testing (test infrastructure only).  One wavefront
-// is emulated by 64 std::threads in lockstep: every cross-lane operation
-// (shuffle, ballot, barrier) is a rendezvous of all 64 threads.
+// is emulated by 64 cooperative fibers on one thread, run round-robin:
+// every cross-lane operation (shuffle, ballot, barrier) is a rendezvous at
+// which a lane yields to the next, so all 64 lanes have written before any
+// reads.  The fibers switch stacks with a minimal x86-64 register switch
+// (callee-saved registers and the stack pointer), no system call.
 #pragma once
-#include <barrier>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <cstdio>
+#include <cstdlib>
 
 #define __device__
 #define __host__
@@ -23,30 +26,122 @@
 #define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt((double)(x)))
 #define __builtin_amdgcn_exp2f(x) std::exp2((float)(x))
 
+// emu_switch(save, to): push the callee-saved registers, store the stack
+// pointer in *save, load `to` and pop the registers saved there.
+// emu_start: first code of a fiber; calls r13(r12) (never returns).
+asm(R"(
+.text
+.globl emu_switch
+.type emu_switch, @function
+emu_switch:
+  pushq %rbp
+  pushq %rbx
+  pushq %r12
+  pushq %r13
+  pushq %r14
+  pushq %r15
+  movq %rsp, (%rdi)
+  movq %rsi, %rsp
+  popq %r15
+  popq %r14
+  popq %r13
+  popq %r12
+  popq %rbx
+  popq %rbp
+  ret
+.size emu_switch, .-emu_switch
+.globl emu_start
+.type emu_start, @function
+emu_start:
+  movq %r12, %rdi
+  call *%r13
+  ud2
+.size emu_start, .-emu_start
+)");
+extern "C" void emu_switch(void** save, void* to);
+extern "C" void emu_start();
+
 namespace hip_emu {
 constexpr int kLanes = 64;
+constexpr size_t kStack = 1 << 20;
 struct Wave {
-  std::barrier<> bar{kLanes};
   alignas(16) unsigned char buf[kLanes][8];
   uint64_t ballot_bits[kLanes];
+  void* lane_sp[kLanes];
+  void* main_sp = nullptr;
+  bool done[kLanes];
+  char* stacks = nullptr;
 };
 inline Wave* g_wave = nullptr;
-inline thread_local int t_lane = 0;
+inline int t_lane = 0;
+
+// Rendezvous: hand over to the scheduler, which runs the next lane.
+inline void yield() { emu_switch(&g_wave->lane_sp[t_lane], g_wave->main_sp); }
+
+struct LaneArg {
+  void (*fn)(int, void*);
+  void* ctx;
+};
+inline LaneArg g_lane_arg;
+
+inline void lane_entry(void*) {
+  const int l = t_lane;
+  g_lane_arg.fn(l, g_lane_arg.ctx);
+  g_wave->done[l] = true;
+  emu_switch(&g_wave->lane_sp[l], g_wave->main_sp);  // never resumed
+  std::abort();
+}
+
+// Run fn(lane, ctx) on 64 fibers in lockstep until every lane returns.
+inline void run_wave(void (*fn)(int, void*), void* ctx) {
+  Wave* w = new Wave();
+  w->stacks = (char*)std::aligned_alloc(64, kStack * kLanes);
+  g_wave = w;
+  g_lane_arg = LaneArg{fn, ctx};
+  for (int l = 0; l < kLanes; ++l) {
+    w->done[l] = false;
+    // initial frame: r15 r14 r13 r12 rbx rbp, then the return address into
+    // emu_start; 16-byte alignment at the call inside emu_start
+    uint64_t* top = (uint64_t*)(w->stacks + kStack * (l + 1));
+    uint64_t* sp = top - 9;
+    sp[0] = 0;                               // r15
+    sp[1] = 0;                               // r14
+    sp[2] = (uint64_t)(void*)&lane_entry;    // r13: function
+    sp[3] = 0;                               // r12: argument
+    sp[4] = 0;                               // rbx
+    sp[5] = 0;                               // rbp
+    sp[6] = (uint64_t)(void*)&emu_start;     // return address
+    w->lane_sp[l] = sp;
+  }
+  int live = kLanes;
+  while (live > 0) {
+    live = 0;
+    for (int l = 0; l < kLanes; ++l) {
+      if (w->done[l]) continue;
+      t_lane = l;
+      emu_switch(&w->main_sp, w->lane_sp[l]);
+      if (!w->done[l]) ++live;
+    }
+  }
+  g_wave = nullptr;
+  std::free(w->stacks);
+  delete w;
+}
 }  // namespace hip_emu
 
-inline void __syncthreads() { hip_emu::g_wave->bar.arrive_and_wait(); }
-// The emulated lanes are threads: a wave barrier must synchronise them too.
-inline void __builtin_amdgcn_wave_barrier() { hip_emu::g_wave->bar.arrive_and_wait(); }
+inline void __syncthreads() { hip_emu::yield(); }
+// The emulated lanes are fibers: a wave barrier is a rendezvous too.
+inline void __builtin_amdgcn_wave_barrier() { hip_emu::yield(); }
 
 template <class T>
 inline T __hip_emu_exchange(T v, int src) {
   static_assert(sizeof(T) <= 8, "8-byte lanes");
   auto& W = *hip_emu::g_wave;
   std::memcpy(W.buf[hip_emu::t_lane], &v, sizeof(T));
-  W.bar.arrive_and_wait();
+  hip_emu::yield();
   T r;
   std::memcpy(&r, W.buf[src & (hip_emu::kLanes - 1)], sizeof(T));
-  W.bar.arrive_and_wait();
+  hip_emu::yield();
   return r;
 }
 template <class T>
@@ -63,10 +158,10 @@ inline T __shfl_xor(T v, int m, int = 64) { return __hip_emu_exchange(v, hip_emu
 inline unsigned long long __ballot(int pred) {
   auto& W = *hip_emu::g_wave;
   W.ballot_bits[hip_emu::t_lane] = pred ? 1ull : 0ull;
-  W.bar.arrive_and_wait();
+  hip_emu::yield();
   unsigned long long m = 0;
   for (int i = 0; i < hip_emu::kLanes; ++i) m |= W.ballot_bits[i] << i;
-  W.bar.arrive_and_wait();
+  hip_emu::yield();
   return m;
 }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
