@@ -148,7 +148,9 @@ def oracle_epoch(c, i, tol, tight):
     value when its point-source test passes (tight=False only), else the
     uniform disk or, with limb darkening, the annulus combination; tight=True
     runs the contour at the oracle's tight tolerance, otherwise at the
-    stated one (annuli at half of it, as the library runs them)."""
+    stated one (every annulus at it: with the intensity falling outward the
+    combination's relative error is at most the largest annulus error, and
+    the library runs the annuli so)."""
     from oracle import ref
     k, j = divmod(int(i), c.nepochs)
     zx, zy = ref.trajectory(c.u0[k], c.alpha[k], c.tau[j:j + 1])
@@ -167,14 +169,14 @@ def oracle_epoch(c, i, tol, tight):
         if tight:
             mk.append(ref.finite_mag(c.s[k], c.q[k], zx, zy, r, ref.TIGHT_TOL, ref.tight_cfg())[0][0])
         else:
-            mk.append(ref.finite_mag(c.s[k], c.q[k], zx, zy, r, 0.5 * tol)[0][0])
+            mk.append(ref.finite_mag(c.s[k], c.q[k], zx, zy, r, tol)[0][0])
     return ref.ld_combine(c.gamma[k], np.array(mk))
 
 
 def cpu_baseline(c, seconds, threads, seed=11):
     """The oracle as it stands: point-source test, else contour integration
-    at the same tolerance (limb-darkened epochs: every annulus at half of
-    it, then the annulus combination), one epoch after another, over a
+    at the same tolerance (limb-darkened epochs: every annulus, then the
+    annulus combination), one epoch after another, over a
     seeded random sample of the batch's epochs until the time budget is
     used; once on one thread and once on `threads` threads over disjoint
     epochs (the oracle is reentrant and its calls release the GIL)."""
@@ -201,7 +203,7 @@ def cpu_baseline(c, seconds, threads, seed=11):
     return dict(value=d1 / t1, unit="magnifications/s", cores=1, kind="oracle",
                 sample=f"{d1} epochs drawn at random (seed {seed}) from the {c.nsets}x{c.nepochs} batch, "
                        f"point-source test then contour integration at tol {c.tol} (limb darkening: "
-                       f"{c.n_annuli} annuli at tol/2, then the annulus combination), single thread, "
+                       f"{c.n_annuli} annuli, then the annulus combination), single thread, "
                        f"{t1:.1f} s; host {host}",
                 all_cores={"value": dn / tn, "unit": "magnifications/s", "cores": threads,
                            "sample": f"{dn} epochs of the same random order split over {threads} threads, "

@@ -98,9 +98,10 @@ int twk_point_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *zet
  * mode: TWK_MODE_FP64 or TWK_MODE_MIXED; without TWK_MODE_ALL_FS the
  * point-source test may return the point value (flag bit 0).  With
  * TWK_MODE_MLP the learned budget (weights from twk_mlp_set/load/train)
- * sets each contour's starting grid (a multiple of 64, at most 512 uniform
- * samples and at most the tuned LDS capacity) and the queue runs sources
- * longest first; the stop rule and the tolerance are unchanged.
+ * predicts each contour's sample count and the queue runs contours longest
+ * predicted first; the sampling of a contour is unchanged (it starts from
+ * the 64 uniform samples of the paper's schedule), so the results are
+ * bit-identical to those of the same call without TWK_MODE_MLP.
  * Errors: TWK_EINVAL for s, q, rho, tol <= 0 or non-finite, n < 0 or > 2^48, NULL
  * pointers or unknown mode bits; TWK_ENOMLP for TWK_MODE_MLP without
  * weights; TWK_ENOMEM / TWK_EDEVICE. */
@@ -184,8 +185,8 @@ int twk_kernel_times(twk_ctx *ctx, double *ms5);
 
 /* ------------------------------------------------------------------------
  * Launch tuning of the contour stage and graph replay.  None of these
- * change the arithmetic of a source except budget_shift (which moves the
- * learned starting grid; results stay within the tolerance).
+ * change the arithmetic of a source: results are bit-identical under any
+ * tuning.
  * ---------------------------------------------------------------------- */
 typedef struct {
   int32_t waves_per_cu; /* resident contour waves per CU: the persistent grid is
@@ -195,8 +196,8 @@ typedef struct {
   int32_t lds_cap;      /* limb samples a source keeps in LDS (sorted arrays and
                            sample records) before continuing in global memory:
                            64, 128 or 256 */
-  float budget_shift;   /* learned path: starting grid from 2^(predicted log2 N -
-                           budget_shift), in [-2, 4] */
+  float budget_shift;   /* in [-2, 4]; no effect (the learned budget no longer
+                           sets a starting grid; kept for the layout) */
   int32_t graphs;       /* 1: capture each call's launch sequence in a hipGraph and
                            replay it when an identical call (same arguments and
                            pointers) repeats; needs a created (non-null) stream */
@@ -210,10 +211,10 @@ int twk_get_tuning(twk_ctx *ctx, twk_tuning *out);
 int twk_set_tuning(twk_ctx *ctx, const twk_tuning *t);
 /* Autotuner: times twk_lightcurves on this batch (a representative sample
  * of the workload; arguments as for twk_lightcurves) for every LDS capacity
- * and four persistent grid sizes each, then, with TWK_MODE_MLP, six budget
- * shifts, taking the fastest of `trials` (1..100) calls per candidate; the
- * best tuning is left in the context (graphs setting unchanged) and copied
- * to *best (may be NULL).  Synchronous; allocates its own output buffers. */
+ * and four persistent grid sizes each, taking the fastest of `trials`
+ * (1..100) calls per candidate; the best tuning is left in the context
+ * (graphs setting unchanged) and copied to *best (may be NULL).
+ * Synchronous; allocates its own output buffers. */
 int twk_autotune(twk_ctx *ctx, int64_t nsets, const double *s, const double *q,
                  const double *u0, const double *alpha, const double *rho,
                  const double *gamma, int64_t nepochs, const double *tau, int32_t n_annuli,

@@ -193,7 +193,7 @@ typedef struct {
   cplx z[5];        /* lens-2 frame; real images first, ghosts last */
   cplx R[5];        /* residuals in the same order              */
   double J[5];      /* Jacobians in the same order               */
-  int par[5];       /* parity sign(J) for the real images        */
+  int par[5];       /* parity (+1, -1) of the real images          */
   double margin;    /* second-largest |R| over the noise level  */
   uint32_t flags;
 } images_t;
@@ -273,18 +273,29 @@ static void classify(const lens_t *L, cplx y, const cplx r[5], double kgap,
     for (int k = 0; k < 5; ++k) order[m++] = k;
     out->n = 5;
   }
-  int psum = 0;
   for (int k = 0; k < 5; ++k) {
     int i = order[k];
     out->z[k] = r[i];
     out->R[k] = R[i];
     cplx fp = fprime(L, r[i]);
     out->J[k] = 1.0 - creal(fp * conj(fp));
-    out->par[k] = out->J[k] > 0.0 ? 1 : -1;
-    if (k < out->n) psum += out->par[k];
   }
-  /* Parity sum of the real images is -1 (Sec. 2.3). */
-  if (psum != -1) out->flags |= TWK_REF_FLAG_ANOMALY;
+  /* Parity.  The parity sum of the real images is -1 (Sec. 2.3): one
+   * positive image of three, two of five.  READING: the positive images
+   * are the (n - 1)/2 real images of largest J.  This is sign(J) whenever
+   * sign(J) obeys the sum; where it does not, an image of the pair that is
+   * merging on the critical curve has |J| below the rounding of its
+   * near-double root, and the rank assigns the pair one image of each
+   * parity.  Such a correction is flagged near-degenerate. */
+  int npos = (out->n - 1) / 2, nsign = 0;
+  for (int k = 0; k < 5; ++k) {
+    int above = 0;
+    for (int m2 = 0; m2 < out->n; ++m2)
+      if (out->J[m2] > out->J[k] || (out->J[m2] == out->J[k] && m2 < k)) ++above;
+    out->par[k] = (k < out->n && above < npos) ? 1 : -1;
+    if (k < out->n && out->J[k] > 0.0) ++nsign;
+  }
+  if (nsign != npos) out->flags |= TWK_REF_FLAG_NEARDEGEN;
 }
 
 /* Near the critical curve a real image is a near-double root of the
@@ -855,6 +866,9 @@ static void sample_at(const lens_t *L, cplx yc, double rho, double theta,
   sm->demote[0] = sm->demote[1] = -1;
 }
 
+/* Narrowest interval of limb angle that is refined further. */
+#define THETA_FLOOR 1e-9
+
 void twk_ref_cfg_default(twk_ref_cfg *cfg, double tol) {
   cfg->tol = tol;
   cfg->n0 = 64;
@@ -875,10 +889,11 @@ static int contour(const lens_t *L, cplx yc, double rho, const twk_ref_cfg *cfg,
   int *ord2 = (int *)malloc(sizeof(int) * (size_t)cap);
   double *wcum = (double *)malloc(sizeof(double) * ((size_t)cap + 1));
   double *Ei = (double *)malloc(sizeof(double) * (size_t)cap);
+  double *Wi = (double *)malloc(sizeof(double) * (size_t)cap);
   double *newth = (double *)malloc(sizeof(double) * (size_t)cap);
   int *newiv = (int *)malloc(sizeof(int) * (size_t)cap);
-  if (!sm || !ord || !ord2 || !wcum || !Ei || !newth || !newiv) {
-    free(sm); free(ord); free(ord2); free(wcum); free(Ei); free(newth); free(newiv);
+  if (!sm || !ord || !ord2 || !wcum || !Ei || !Wi || !newth || !newiv) {
+    free(sm); free(ord); free(ord2); free(wcum); free(Ei); free(Wi); free(newth); free(newiv);
     return TWK_REF_ENOMEM;
   }
   uint32_t fl = 0;
@@ -905,6 +920,7 @@ static int contour(const lens_t *L, cplx yc, double rho, const twk_ref_cfg *cfg,
       if (pc.anomaly) fl |= TWK_REF_FLAG_ANOMALY;
       nsum_add(&sa, pc.dA);
       Ei[i] = pc.E;
+      Wi[i] = dth;
       se += pc.E;
     }
     A = sa.sum + sa.comp;
@@ -914,11 +930,14 @@ static int contour(const lens_t *L, cplx yc, double rho, const twk_ref_cfg *cfg,
     if (cfg->grow > 0 && N / cfg->grow > nnew) nnew = N / cfg->grow;
     if (N + nnew > cap) nnew = cap - N;
     if (nnew <= 0) { fl |= TWK_REF_FLAG_CAP; break; }
-    /* tolerance-subtracted weights and their cumulative sum */
+    /* tolerance-subtracted weights and their cumulative sum; an interval
+     * narrower than THETA_FLOOR gets no new sample (READING: there the pair
+     * merging on the critical curve is closer than its roots can be
+     * resolved in binary64, and its pieces are rounding noise) */
     double avg = tol * fabs(A) / N;
     wcum[0] = 0.0;
     for (int i = 0; i < N; ++i) {
-      double w = Ei[i] - avg;
+      double w = Wi[i] > THETA_FLOOR ? Ei[i] - avg : 0.0;
       wcum[i + 1] = wcum[i] + (w > 0.0 ? w : 0.0);
     }
     double W = wcum[N];
@@ -958,7 +977,7 @@ static int contour(const lens_t *L, cplx yc, double rho, const twk_ref_cfg *cfg,
   if (theta_out) {
     for (int i = 0; i < N && i < max_out; ++i) theta_out[i] = sm[ord[i]].theta;
   }
-  free(sm); free(ord); free(ord2); free(wcum); free(Ei); free(newth); free(newiv);
+  free(sm); free(ord); free(ord2); free(wcum); free(Ei); free(Wi); free(newth); free(newiv);
   return TWK_REF_OK;
 }
 

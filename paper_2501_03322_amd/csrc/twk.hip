@@ -44,7 +44,6 @@ namespace {
 // before continuing in global memory: one persistent-kernel instantiation
 // per choice; the tuning picks one.
 constexpr int LDS_CAPS[3] = {64, 128, 256};
-constexpr int BUDGET_MAX = 512;  // largest learned starting grid
 
 // Counters in device memory (int64 each).
 enum {
@@ -198,15 +197,19 @@ __device__ inline PsResult point_source_pass(const Lens& L, c64 yc, double rho, 
 // statistic, - with five and X the pair statistic), and log10 of
 // rho |grad mu_ps| / mu_ps from central differences over the stencil,
 // floored at 1e-30.
+// rho: the radius of the stencil the point pass used; rho_f: the radius of
+// the disk the features describe (an annulus contour of a limb-darkened
+// source is a uniform disk of its own radius; the gradient term scales with
+// the radius).
 __device__ inline void ps_features(double s, double q, double zx, double zy, double rho,
-                                   const PsResult& ps, float* f) {
-  const double grad = 0.5 * sqrt(ps.gx * ps.gx + ps.gy * ps.gy);
-  const double prox = ps.n == 3 ? log10(1.0 + ps.ghost0 / rho) : -log10(1.0 + ps.pair0 / rho);
+                                   double rho_f, const PsResult& ps, float* f) {
+  const double grad = 0.5 * sqrt(ps.gx * ps.gx + ps.gy * ps.gy) * (rho_f / rho);
+  const double prox = ps.n == 3 ? log10(1.0 + ps.ghost0 / rho_f) : -log10(1.0 + ps.pair0 / rho_f);
   f[0] = (float)s;
   f[1] = (float)log10(q);
   f[2] = (float)zx;
   f[3] = (float)zy;
-  f[4] = (float)log10(rho);
+  f[4] = (float)log10(rho_f);
   f[5] = (float)log10(ps.mu);
   f[6] = (float)prox;
   f[7] = (float)log10(fmax(grad / ps.mu, 1e-30));
@@ -265,7 +268,8 @@ __device__ inline int64_t queue_push(bool push, int count, long long* counter) {
 // source of the same lens to start from; on return the centre roots of this
 // source (and *warm says whether there are any).
 __device__ inline void emit_source(int64_t out, double s, double q, double zx, double zy,
-                                   double rho, double tol, bool all_fs, int na, Task* tasks,
+                                   double rho, double tol, double tol_fs, bool all_fs, int na,
+                                   Task* tasks,
                                    long long* cnt, int64_t* fs_epoch, double* mag, double* err,
                                    int32_t* ns, uint32_t* flags, bool active, float* tfeat,
                                    c64* carry = nullptr, bool* warm = nullptr) {
@@ -313,6 +317,7 @@ __device__ inline void emit_source(int64_t out, double s, double q, double zx, d
     t.q = q;
     t.zx = zx;
     t.zy = zy;
+    t.tol = tol_fs;
 #pragma unroll
     for (int k = 0; k < 5; ++k) t.roots[k] = ps.roots[k];
     for (int k = 0; k < na; ++k) {
@@ -321,12 +326,13 @@ __device__ inline void emit_source(int64_t out, double s, double q, double zx, d
       tasks[slot + k] = t;
     }
     if (tfeat) {
-      // every annulus of a limb-darkened epoch shares the epoch's features
-      float f[8];
-      ps_features(s, q, zx, zy, rho, ps, f);
-      for (int k = 0; k < na; ++k)
+      // the features of each contour: those of a uniform disk of its radius
+      for (int k = 0; k < na; ++k) {
+        float f[8];
+        ps_features(s, q, zx, zy, rho, na > 1 ? rho * sqrt((double)(k + 1) / na) : rho, ps, f);
 #pragma unroll
         for (int j = 0; j < 8; ++j) tfeat[(slot + k) * 8 + j] = f[j];
+      }
     }
   }
 }
@@ -338,7 +344,7 @@ __global__ __launch_bounds__(256) void k_prep(double s, double q, int64_t n, con
                                               uint32_t* flags, float* tfeat) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = i < n;
-  emit_source(i, s, q, active ? zx[i] : 0.0, active ? zy[i] : 0.0, rho, tol, all_fs != 0, 1, tasks,
+  emit_source(i, s, q, active ? zx[i] : 0.0, active ? zy[i] : 0.0, rho, tol, tol, all_fs != 0, 1, tasks,
               cnt, nullptr, mag, err, ns, flags, active, tfeat);
 }
 
@@ -365,7 +371,7 @@ __global__ __launch_bounds__(256) void k_prep_each(const double* ps, const doubl
       x = __builtin_nan("");
     }
   }
-  emit_source(i, s, q, x, y, rho, tol, all_fs != 0, 1, tasks, cnt, nullptr, mag, err, ns, flags,
+  emit_source(i, s, q, x, y, rho, tol, tol, all_fs != 0, 1, tasks, cnt, nullptr, mag, err, ns, flags,
               active, tfeat);
 }
 
@@ -388,7 +394,7 @@ __global__ __launch_bounds__(256) void k_map(double s, double q, double rho, dou
     zy = yc - 0.5 * h + (iy + 0.5) * (h / ny);
     out = iy * nx + ix;
   }
-  emit_source(out, s, q, zx, zy, rho, tol, all_fs != 0, 1, tasks, cnt, nullptr, mag, err, ns,
+  emit_source(out, s, q, zx, zy, rho, tol, tol, all_fs != 0, 1, tasks, cnt, nullptr, mag, err, ns,
               flags, active, tfeat);
 }
 
@@ -401,9 +407,27 @@ constexpr int LC_RUN = 4;
 __host__ __device__ inline int64_t lc_lanes(int64_t nsets, int64_t nep) {
   return nsets * ((nep + LC_RUN - 1) / LC_RUN);
 }
+// Relative tolerance of each annulus contour of a limb-darkened epoch.  The
+// combination is sum_k (I_k - I_{k+1}) x_k mu_k + I_na x_na mu_na over the
+// nested disks (x_k = k/na of the squared radius, I_{na+1} = 0).  When the
+// intensity falls outward (Gamma >= 0) every weight is non-negative, so the
+// combination's relative error is at most the largest relative error of the
+// mu_k: the annuli run at the stated tolerance.  For limb brightening
+// (Gamma < 0) the weights alternate in sign and the error grows by at most
+// 2 I_na / I_1 - 1 (the combination is at least I_1 times the total flux):
+// the annuli run at the tolerance divided by that factor.
+__device__ inline double annulus_tol(double tol, double G, int na) {
+  if (!(G < 0.0)) return tol;
+  const double x1 = 1.0 / na, xl = (na - 1.0) / na;
+  const double i1 = 1.0 - G + G * (1.0 - pow(1.0 - x1, 1.5)) / x1;
+  const double il = 1.0 - G + G * pow(1.0 - xl, 1.5) / (1.0 - xl);
+  const double f = 2.0 * il / i1 - 1.0;
+  return i1 > 0.0 && f > 1.0 ? tol / f : tol;
+}
+
 __global__ __launch_bounds__(256) void k_lc(int64_t nsets, const double* ps, const double* pq,
                                             const double* pu0, const double* pal,
-                                            const double* prho, int64_t nep,
+                                            const double* prho, const double* pgam, int64_t nep,
                                             const double* tau, double tol, int all_fs, int na,
                                             Task* tasks, long long* cnt, int64_t* fs_epoch,
                                             double* mag, double* err, int32_t* ns,
@@ -412,13 +436,14 @@ __global__ __launch_bounds__(256) void k_lc(int64_t nsets, const double* ps, con
   const int64_t runs = (nep + LC_RUN - 1) / LC_RUN;
   const bool lane_on = i < nsets * runs;
   const int64_t k = lane_on ? i / runs : 0, j0 = lane_on ? (i - k * runs) * LC_RUN : 0;
-  double s = 1.0, q = 1.0, rho = 1.0, u0 = 0.0, sa = 0.0, ca = 1.0;
+  double s = 1.0, q = 1.0, rho = 1.0, u0 = 0.0, sa = 0.0, ca = 1.0, tol_fs = tol;
   if (lane_on) {
     s = ps[k];
     q = pq[k];
     rho = prho[k];
     u0 = pu0[k];
     sincos(pal[k], &sa, &ca);
+    if (na > 1) tol_fs = annulus_tol(tol, pgam[k], na);
   }
   c64 carry[5];
   bool warm = false;
@@ -432,7 +457,7 @@ __global__ __launch_bounds__(256) void k_lc(int64_t nsets, const double* ps, con
       zx = t * ca - u0 * sa;
       zy = t * sa + u0 * ca;
     }
-    emit_source(k * nep + j, s, q, zx, zy, rho, tol, all_fs != 0, na, tasks, cnt, fs_epoch, mag,
+    emit_source(k * nep + j, s, q, zx, zy, rho, tol, tol_fs, all_fs != 0, na, tasks, cnt, fs_epoch, mag,
                 err, ns, flags, active, tfeat, carry, &warm);
   }
 }
@@ -497,35 +522,29 @@ __global__ __launch_bounds__(256) void k_feat(int64_t nsets, const double* ps, c
   }
   const PsResult r = point_source_pass(L, cz(zx - L.z2, zy), prho[k], tol, true, true, true);
   float f[8];
-  ps_features(ps[k], pq[k], zx, zy, prho[k], r, f);
+  ps_features(ps[k], pq[k], zx, zy, prho[k], prho[k], r, f);
 #pragma unroll
   for (int c = 0; c < 8; ++c) feat[i * 8 + c] = f[c];
   mu[i] = r.mu;
   adequate[i] = r.adequate ? 1 : 0;
 }
 
-// Learned budget of each queued task from the predicted log2 sample count
-// (lowered by `shift` so that the uniform start rarely overshoots): the
-// starting grid n0 is the largest multiple of 64 not above 2^(l2 - shift),
-// within [64, BUDGET_MAX]; tasks are also counted into classes
-// floor(l2) - 6.  Counts are gathered per block in LDS and added to the
-// global class counters with one atomic per class and block.
+// Learned budget: each queued task is counted into the class floor(l2) - 6
+// of its predicted log2 sample count l2 (7 classes, 2^6 .. >= 2^12
+// samples); the classes set the queue order.  The prediction does not
+// change how a contour is sampled: every contour starts from the paper's
+// 64 uniform samples.  Counts are gathered per block in LDS and added to
+// the global class counters with one atomic per class and block.
 __device__ inline int budget_class(float l2) {
   return min(max((int)floorf(l2) - 6, 0), NBUCKET - 1);
 }
 
-__global__ __launch_bounds__(256) void k_budget(long long* cnt, const float* out, int32_t* tn0,
-                                                float shift) {
+__global__ __launch_bounds__(256) void k_budget(long long* cnt, const float* out) {
   __shared__ int hist[NBUCKET];
   if (threadIdx.x < NBUCKET) hist[threadIdx.x] = 0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt[C_NTASK]) {
-    const float l2 = out[2 * i];
-    const float want = exp2f(fminf(fmaxf(l2 - shift, 6.0f), 9.0f));
-    tn0[i] = min(max(((int)want / 64) * 64, 64), BUDGET_MAX);
-    atomicAdd(&hist[budget_class(l2)], 1);
-  }
+  if (i < cnt[C_NTASK]) atomicAdd(&hist[budget_class(out[2 * i])], 1);
   __syncthreads();
   if (threadIdx.x < NBUCKET && hist[threadIdx.x] > 0)
     atomicAdd((unsigned long long*)&cnt[C_BUCKET + threadIdx.x],
@@ -569,12 +588,12 @@ template <int LCAP, bool MIXED>
 #define TWK_FS_WAVES_PER_EU 2
 #endif
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES_PER_EU))) void k_fs(
-    const Task* tasks, const long long* ntask, long long* head, double tol, char* scratch,
-    double* mag, double* err, int32_t* ns, uint32_t* flags, long long* cnt, const int32_t* order,
-    const int32_t* tn0) {
+    const Task* tasks, const long long* ntask, long long* head, char* slices,
+    double* mag, double* err, int32_t* ns, uint32_t* flags, long long* cnt,
+    const int32_t* order) {
   __shared__ FsLds<LCAP, MIXED> lds;
   const int lane = threadIdx.x;
-  const WaveMem<MIXED> m = wave_mem<MIXED>(scratch, blockIdx.x);
+  const WaveMem<MIXED> m = wave_mem<MIXED>(slices, blockIdx.x);
   const long long n = *ntask;
   unsigned long long w_samples = 0, w_sw32 = 0, w_sw64 = 0, w_int = 0, w_runs = 0, w_over = 0;
   for (;;) {
@@ -584,8 +603,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES
     if (t >= n) break;
     if (order) t = order[t];
     const Task task = tasks[t];
-    const int n0 = tn0 ? min(tn0[t], LCAP) : NNEW;
-    const FsOut o = fs_source<LCAP, MIXED>(task, tol, m, lds, lane, n0);
+    const FsOut o = fs_source<LCAP, MIXED>(task, task.tol, m, lds, lane, NNEW);
     if (lane == 0) {
       mag[task.out] = o.mag;
       err[task.out] = o.err;
@@ -621,10 +639,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES
 // each has its global slice b and its state rs[b].
 template <bool MIXED>
 __global__ __launch_bounds__(64) void k_fs_round(const Task* tasks, int64_t b0,
-                                                 const int32_t* order, const int32_t* tn0,
-                                                 const int32_t* list_in, int32_t* list_out,
+                                                 const int32_t* order, const int32_t* list_in,
+                                                 int32_t* list_out,
                                                  long long* n_out, RoundState* rs, char* slices,
-                                                 double tol, double* mag, double* err, int32_t* ns,
+                                                 double* mag, double* err, int32_t* ns,
                                                  uint32_t* flags) {
   __shared__ int ivl[NNEW];
   const int lane = threadIdx.x;
@@ -633,10 +651,9 @@ __global__ __launch_bounds__(64) void k_fs_round(const Task* tasks, int64_t b0,
   int64_t t = b0 + b;
   if (order) t = order[t];
   const Task task = tasks[t];
-  const int n0 = tn0 ? tn0[t] : NNEW;
   const WaveMem<MIXED> m = wave_mem<MIXED>(slices, b);
   FsOut o;
-  if (fs_round_step<MIXED>(task, tol, m, (lint*)ivl, lane, n0, &rs[b], fresh, &o)) {
+  if (fs_round_step<MIXED>(task, task.tol, m, (lint*)ivl, lane, NNEW, &rs[b], fresh, &o)) {
     if (lane == 0) {
       mag[task.out] = o.mag;
       err[task.out] = o.err;
@@ -690,8 +707,8 @@ struct twk_ctx {
   hipStream_t stream = nullptr;
   int n_cu = 0;
   int last_err = 0;
-  char* scratch = nullptr;
-  size_t scratch_bytes = 0;
+  char* slices = nullptr;  // the persistent waves' global slices
+  size_t slices_bytes = 0;
   Task* tasks = nullptr;
   int64_t task_cap = 0;
   long long* cnt = nullptr;
@@ -722,7 +739,7 @@ struct twk_ctx {
   float* mlp_p = nullptr;           // float32 master parameters
   mlp::bf16x8* mlp_frag = nullptr;  // packed inference operands
   bool mlp_ready = false;
-  char* lt = nullptr;               // per task: features, outputs, n0, order
+  char* lt = nullptr;               // per task: features, outputs, queue order
   size_t lt_bytes = 0;
   int64_t lt_cap = 0;
   // round-by-round dispatch: per-source global slices, states and the two
@@ -830,7 +847,7 @@ int ensure_fs(twk_ctx* c, int64_t ntask_max) {
   c->task_cap = (int64_t)(have / sizeof(Task));
   c->waves = fs_waves(c);
   const size_t need = (size_t)c->waves * METHOD_CAP * kSlotBytesMax;
-  return grow(c, (void**)&c->scratch, &c->scratch_bytes, need);
+  return grow(c, (void**)&c->slices, &c->slices_bytes, need);
 }
 
 int ensure_ld(twk_ctx* c, int64_t nfs_max, int na) {
@@ -862,7 +879,6 @@ AnnBufs ann_bufs(twk_ctx* c, int64_t n) {
 struct LearnBufs {
   float* feat;    // [cap x 8]
   float* out;     // [cap x 2]
-  int32_t* n0;    // [cap]
   int32_t* order; // [cap]
 };
 
@@ -870,8 +886,7 @@ LearnBufs learn_bufs(twk_ctx* c) {
   LearnBufs b;
   b.feat = (float*)c->lt;
   b.out = b.feat + 8 * c->lt_cap;
-  b.n0 = (int32_t*)(b.out + 2 * c->lt_cap);
-  b.order = b.n0 + c->lt_cap;
+  b.order = (int32_t*)(b.out + 2 * c->lt_cap);
   return b;
 }
 
@@ -894,8 +909,7 @@ int learned_stage(twk_ctx* c, int64_t ntask_max) {
                      c->mlp_p, c->mlp_frag, (int64_t)0, &c->cnt[C_NTASK], b.feat, b.out);
   HIP_TRY(c, hipGetLastError());
   const unsigned g = (unsigned)((ntask_max + 255) / 256);
-  hipLaunchKernelGGL(k_budget, dim3(g), dim3(256), 0, c->stream, c->cnt, b.out, b.n0,
-                     c->tune.budget_shift);
+  hipLaunchKernelGGL(k_budget, dim3(g), dim3(256), 0, c->stream, c->cnt, b.out);
   HIP_TRY(c, hipGetLastError());
   hipLaunchKernelGGL(k_place, dim3(g), dim3(256), 0, c->stream, c->cnt, b.out, b.order);
   HIP_TRY(c, hipGetLastError());
@@ -903,30 +917,29 @@ int learned_stage(twk_ctx* c, int64_t ntask_max) {
 }
 
 template <int LCAP>
-void launch_fs_cap(twk_ctx* c, bool mixed, double tol, double* mag, double* err, int32_t* ns,
-                   uint32_t* flags, const int32_t* order, const int32_t* n0) {
+void launch_fs_cap(twk_ctx* c, bool mixed, double* mag, double* err, int32_t* ns,
+                   uint32_t* flags, const int32_t* order) {
   // the persistent grid: the tuned waves per CU, at most what the launched
   // kernel can keep resident
   const int ci = cap_index(LCAP);
   const int waves = std::min(c->waves, c->occ[ci][mixed ? 1 : 0] * c->n_cu);
   if (mixed)
     hipLaunchKernelGGL((k_fs<LCAP, true>), dim3(waves), dim3(64), 0, c->stream, c->tasks,
-                       &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
-                       c->cnt, order, n0);
+                       &c->cnt[C_NTASK], &c->cnt[C_HEAD], c->slices, mag, err, ns, flags,
+                       c->cnt, order);
   else
     hipLaunchKernelGGL((k_fs<LCAP, false>), dim3(waves), dim3(64), 0, c->stream, c->tasks,
-                       &c->cnt[C_NTASK], &c->cnt[C_HEAD], tol, c->scratch, mag, err, ns, flags,
-                       c->cnt, order, n0);
+                       &c->cnt[C_NTASK], &c->cnt[C_HEAD], c->slices, mag, err, ns, flags,
+                       c->cnt, order);
 }
 
-int launch_fs(twk_ctx* c, bool mixed, bool learned, double tol, double* mag, double* err,
+int launch_fs(twk_ctx* c, bool mixed, bool learned, double* mag, double* err,
               int32_t* ns, uint32_t* flags) {
   const int32_t* order = learned ? learn_bufs(c).order : nullptr;
-  const int32_t* n0 = learned ? learn_bufs(c).n0 : nullptr;
   switch (c->tune.lds_cap) {
-    case 64: launch_fs_cap<64>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
-    case 256: launch_fs_cap<256>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
-    default: launch_fs_cap<128>(c, mixed, tol, mag, err, ns, flags, order, n0); break;
+    case 64: launch_fs_cap<64>(c, mixed, mag, err, ns, flags, order); break;
+    case 256: launch_fs_cap<256>(c, mixed, mag, err, ns, flags, order); break;
+    default: launch_fs_cap<128>(c, mixed, mag, err, ns, flags, order); break;
   }
   HIP_TRY(c, hipGetLastError());
   return TWK_OK;
@@ -941,7 +954,7 @@ constexpr int64_t ROUND_BATCH = 32768;
 // The paper's dispatch: the host reads the number of queued tasks, then
 // for each batch of sources launches one round after another over the list
 // of unfinished ones, reading the list's length after each round.
-int rounds_stage(twk_ctx* c, bool mixed, bool learned, double tol, double* mag, double* err,
+int rounds_stage(twk_ctx* c, bool mixed, bool learned, double* mag, double* err,
                  int32_t* ns, uint32_t* flags) {
   long long ntask = 0, nout = 0;
   HIP_TRY(c, hipMemcpyAsync(&ntask, &c->cnt[C_NTASK], 8, hipMemcpyDeviceToHost, c->stream));
@@ -955,7 +968,6 @@ int rounds_stage(twk_ctx* c, bool mixed, bool learned, double tol, double* mag, 
       (rc = grow(c, (void**)&c->rlist, &c->rlist_bytes, (size_t)2 * B * sizeof(int32_t))))
     return rc;
   const int32_t* order = learned ? learn_bufs(c).order : nullptr;
-  const int32_t* n0 = learned ? learn_bufs(c).n0 : nullptr;
   RoundState* rs = (RoundState*)c->rstate;
   for (int64_t b0 = 0; b0 < ntask; b0 += B) {
     const int64_t nb = std::min<int64_t>(B, ntask - b0);
@@ -966,12 +978,12 @@ int rounds_stage(twk_ctx* c, bool mixed, bool learned, double tol, double* mag, 
       hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, c->stream, &c->cnt[C_NOUT]);
       if (mixed)
         hipLaunchKernelGGL(k_fs_round<true>, dim3((unsigned)nin), dim3(64), 0, c->stream, c->tasks,
-                           b0, order, n0, lin, lout, &c->cnt[C_NOUT], rs, c->rslices, tol, mag, err,
-                           ns, flags);
+                           b0, order, lin, lout, &c->cnt[C_NOUT], rs, c->rslices, mag, err, ns,
+                           flags);
       else
         hipLaunchKernelGGL(k_fs_round<false>, dim3((unsigned)nin), dim3(64), 0, c->stream,
-                           c->tasks, b0, order, n0, lin, lout, &c->cnt[C_NOUT], rs, c->rslices,
-                           tol, mag, err, ns, flags);
+                           c->tasks, b0, order, lin, lout, &c->cnt[C_NOUT], rs, c->rslices,
+                           mag, err, ns, flags);
       HIP_TRY(c, hipGetLastError());
       HIP_TRY(c, hipMemcpyAsync(&nout, &c->cnt[C_NOUT], 8, hipMemcpyDeviceToHost, c->stream));
       HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1093,7 +1105,7 @@ int twk_destroy(twk_ctx* c) {
   if (!c) return TWK_EINVAL;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(c->scratch);
+  (void)hipFree(c->slices);
   (void)hipFree(c->tasks);
   (void)hipFree(c->cnt);
   (void)hipFree(c->fs_epoch);
@@ -1226,15 +1238,15 @@ int check_mode(twk_ctx* c, uint32_t mode) {
 
 // After the point-source pass of chunk k: learned stage (if any), then the
 // contour kernel, each bracketed by the chunk's stage events.
-int contour_stage(twk_ctx* c, int64_t k, uint32_t mode, int64_t ntask_max, double tol,
-                  double* mag, double* err, int32_t* ns, uint32_t* flags) {
+int contour_stage(twk_ctx* c, int64_t k, uint32_t mode, int64_t ntask_max, double* mag,
+                  double* err, int32_t* ns, uint32_t* flags) {
   int rc;
   const bool mixed = (mode & TWK_MODE_MIXED) != 0, learned = (mode & TWK_MODE_MLP) != 0;
   if ((rc = mark(c, k, 1))) return rc;
   if (learned && (rc = learned_stage(c, ntask_max))) return rc;
   if ((rc = mark(c, k, 2))) return rc;
-  if (mode & TWK_MODE_ROUNDS) rc = rounds_stage(c, mixed, learned, tol, mag, err, ns, flags);
-  else rc = launch_fs(c, mixed, learned, tol, mag, err, ns, flags);
+  if (mode & TWK_MODE_ROUNDS) rc = rounds_stage(c, mixed, learned, mag, err, ns, flags);
+  else rc = launch_fs(c, mixed, learned, mag, err, ns, flags);
   if (rc) return rc;
   return mark(c, k, 3);
 }
@@ -1278,8 +1290,7 @@ int twk_finite_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, 
                          zy + i0, rho, tol, all_fs, c->tasks, c->cnt, mag + i0, err + i0, ns + i0,
                          flags + i0, tfeat);
       HIP_TRY(c, hipGetLastError());
-      if ((r = contour_stage(c, i0 / chunk, mode, m, tol, mag + i0, err + i0, ns + i0,
-                             flags + i0)))
+      if ((r = contour_stage(c, i0 / chunk, mode, m, mag + i0, err + i0, ns + i0, flags + i0)))
         return r;
     }
     return mark_call(c, 1);
@@ -1315,8 +1326,7 @@ int twk_finite_mag_each(twk_ctx* c, int64_t n, const double* s, const double* q,
                          m, zx + i0, zy + i0, rho + i0, tol, all_fs, c->tasks, c->cnt, mag + i0,
                          err + i0, ns + i0, flags + i0, tfeat);
       HIP_TRY(c, hipGetLastError());
-      if ((r = contour_stage(c, i0 / chunk, mode, m, tol, mag + i0, err + i0, ns + i0,
-                             flags + i0)))
+      if ((r = contour_stage(c, i0 / chunk, mode, m, mag + i0, err + i0, ns + i0, flags + i0)))
         return r;
     }
     return mark_call(c, 1);
@@ -1357,7 +1367,7 @@ int twk_mag_map(twk_ctx* c, double s, double q, double rho, double xc, double yc
                          yc, width, height, nx, ny, y0, nr, tol, all_fs, c->tasks, c->cnt, mag, err,
                          ns, flags, tfeat);
       HIP_TRY(c, hipGetLastError());
-      if ((r = contour_stage(c, y0 / rows, mode, nr * nx, tol, mag, err, ns, flags)))
+      if ((r = contour_stage(c, y0 / rows, mode, nr * nx, mag, err, ns, flags)))
         return r;
     }
     return mark_call(c, 1);
@@ -1389,9 +1399,6 @@ int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q,
   const AnnBufs ab = ld ? ann_bufs(c, chunk_n * na) : AnnBufs{nullptr, nullptr, nullptr, nullptr};
   const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
   float* tfeat = learned ? learn_bufs(c).feat : nullptr;
-  // The limb-darkened value is a weighted difference of the annulus values,
-  // which roughly doubles their relative error: annuli run at tol / 2.
-  const double tol_fs = ld ? 0.5 * tol : tol;
   CallKey key;
   key.u(entry_key(3, mode)).u((uint64_t)nsets).p(s).p(q).p(u0).p(alpha).p(rho).p(gamma).u((uint64_t)nepochs).p(tau)
       .u((uint64_t)n_annuli).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
@@ -1405,14 +1412,15 @@ int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q,
       if (k0 > 0 && (r = reset(c, true))) return r;
       if ((r = mark(c, k0 / chunk_sets, 0))) return r;
       hipLaunchKernelGGL(k_lc, dim3(blocks_for(lc_lanes(nk, nepochs))), dim3(256), 0, c->stream, nk,
-                         s + k0, q + k0, u0 + k0, alpha + k0, rho + k0, nepochs, tau, tol, all_fs,
+                         s + k0, q + k0, u0 + k0, alpha + k0, rho + k0, ld ? gamma + k0 : nullptr,
+                         nepochs, tau, tol, all_fs,
                          na, c->tasks, c->cnt, c->fs_epoch, mag + o, err + o, ns + o, flags + o,
                          tfeat);
       HIP_TRY(c, hipGetLastError());
-      if (ld) r = contour_stage(c, k0 / chunk_sets, mode, nk * nepochs * na, tol_fs, ab.mag,
-                                ab.err, ab.ns, ab.flags);
-      else r = contour_stage(c, k0 / chunk_sets, mode, nk * nepochs, tol_fs, mag + o, err + o,
-                             ns + o, flags + o);
+      if (ld) r = contour_stage(c, k0 / chunk_sets, mode, nk * nepochs * na, ab.mag, ab.err, ab.ns,
+                                ab.flags);
+      else r = contour_stage(c, k0 / chunk_sets, mode, nk * nepochs, mag + o, err + o, ns + o,
+                             flags + o);
       if (r) return r;
       if (ld) {
         hipLaunchKernelGGL(k_ld, dim3(blocks_for(nk * nepochs)), dim3(256), 0, c->stream, c->cnt,
@@ -1950,7 +1958,7 @@ int twk_autotune(twk_ctx* c, int64_t nsets, const double* s, const double* q, co
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     rc = hip_fail(c, hipGetLastError());
   } else {
-    // persistent grid and LDS capacity, then (learned path) the budget shift
+    // persistent grid and LDS capacity
     for (int ci = 0; ci < 3 && rc == TWK_OK; ++ci) {
       int mx = 0;
       if ((rc = max_waves(LDS_CAPS[ci], &mx)) != TWK_OK) break;
@@ -1961,18 +1969,6 @@ int twk_autotune(twk_ctx* c, int64_t nsets, const double* s, const double* q, co
         last = w;
         cur.lds_cap = LDS_CAPS[ci];
         cur.waves_per_cu = w;
-        double ms;
-        if ((rc = measure(cur, &ms)) == TWK_OK && ms < best_ms) {
-          best_ms = ms;
-          top = cur;
-        }
-      }
-    }
-    if (rc == TWK_OK && (mode & TWK_MODE_MLP)) {
-      const float shifts[6] = {0.0f, 0.5f, 1.0f, 1.5f, 2.0f, 3.0f};
-      cur = top;
-      for (int i = 0; i < 6 && rc == TWK_OK; ++i) {
-        cur.budget_shift = shifts[i];
         double ms;
         if ((rc = measure(cur, &ms)) == TWK_OK && ms < best_ms) {
           best_ms = ms;

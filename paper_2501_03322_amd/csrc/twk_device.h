@@ -432,16 +432,31 @@ __device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 
   im.flags = 0;
   if (margin > KGAP / 30.0 && margin < KGAP * 30.0) im.flags |= F_NEARDEGEN;
   if (ghosts && fabs(ra - rb) > 0.1 * ra) im.flags |= F_ANOMALY;
+  // Parity: the parity sum of the real images is -1 (Sec. 2.3), one
+  // positive image of three, two of five; the positive ones are the
+  // (n - 1)/2 real images of largest J.  That is sign(J) whenever sign(J)
+  // obeys the sum; where it does not, the pair merging on the critical curve
+  // has |J| below the rounding of its near-double root and the rank gives
+  // the pair one image of each parity (flagged near-degenerate).
   // Order the roots: positive-parity real images, negative-parity real
   // images, ghosts (stable bubble sort on a 0/1/2 key; static indices).
-  int key[5];
+  const int nreal = ghosts ? 3 : 5, npos_want = ghosts ? 1 : 2;
+  int key[5], nsign = 0;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     im.J[k] = J[k];
     im.z[k] = r[k];
     const bool g = ghosts && (k == a || k == b);
-    key[k] = g ? 2 : (im.J[k] > 0.0 ? 0 : 1);
+    int above = 0;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const bool gm = ghosts && (m == a || m == b);
+      if (m != k && !gm && (J[m] > J[k] || (J[m] == J[k] && m < k))) ++above;
+    }
+    key[k] = g ? 2 : (above < npos_want ? 0 : 1);
+    if (!g && J[k] > 0.0) ++nsign;
   }
+  if (nsign != npos_want) im.flags |= F_NEARDEGEN;
 #pragma unroll
   for (int pass = 0; pass < 4; ++pass) {
 #pragma unroll
@@ -458,13 +473,8 @@ __device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 
       key[i + 1] = sw ? k0 : k1;
     }
   }
-  im.n = ghosts ? 3 : 5;
-  int npos = 0;
-#pragma unroll
-  for (int k = 0; k < 5; ++k) npos += key[k] == 0 ? 1 : 0;
-  im.par = (1u << npos) - 1u;
-  // Parity sum of the real images is -1 (Sec. 2.3): 1 positive of 3, 2 of 5.
-  if (2 * npos - im.n != -1) im.flags |= F_ANOMALY;
+  im.n = nreal;
+  im.par = (1u << npos_want) - 1u;
 }
 
 // Roots -> polished roots, residuals and classification.

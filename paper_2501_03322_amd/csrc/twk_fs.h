@@ -46,10 +46,11 @@ constexpr double PI_64 = 3.141592653589793;
 
 // A finite-source task: everything a wave needs, resolved by the pass that
 // queued it.  roots: the five roots at the source centre (lens-2 frame),
-// used to warm-start the first limb samples.
+// used to warm-start the first limb samples; tol: the relative tolerance
+// this contour must meet.
 struct Task {
   int64_t out;  // index into the output arrays
-  double s, q, rho, zx, zy;
+  double s, q, rho, zx, zy, tol;
   c64 roots[5];
 };
 
@@ -965,6 +966,23 @@ struct FsState {
 
 typedef TWK_LDS_AS int lint;
 
+// Narrowest interval of limb angle that is refined further.  Near the limb
+// angle where an image pair merges on the critical curve, the pair's
+// separation falls as the square root of the angular distance; below about
+// 1e-9 rad it is under the rounding of the near-double roots in binary64,
+// so the classification and the pieces there are noise, and sampling into
+// them only adds noise.
+constexpr double THETA_FLOOR = 1e-9;
+
+// Tolerance-subtracted weight of the interval starting at sorted position
+// p of N (error e): zero for intervals narrower than THETA_FLOOR.
+template <class Sorted>
+__device__ __forceinline__ double interval_weight(const Sorted& S, int p, int N, double e,
+                                                  double avg) {
+  const double w = (p + 1 < N ? S.th[p + 1] : S.th[0] + TWO_PI) - S.th[p];
+  return w > THETA_FLOOR ? fmax(e - avg, 0.0) : 0.0;
+}
+
 // How fs_rounds returned: the source is finished (stop test met, cap or no
 // placeable sample); the next round would outgrow the LDS copy of the
 // sorted arrays (the caller moves them to the wave's global slice and
@@ -1009,14 +1027,15 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
         ivl[rank] = iv;
       }
     } else {
-      // error total and total tolerance-subtracted weight
+      // error total and total tolerance-subtracted weight (intervals
+      // narrower than THETA_FLOOR weigh nothing)
       A = Ahi + Alo;
       const double avg = tol * fabs(A) / N;
       double es = 0.0, ws = 0.0;
       for (int p = lane; p < N; p += WAVE) {
         const double e = S.E[p];
         es += e;
-        ws += fmax(e - avg, 0.0);
+        ws += interval_weight(S, p, N, e, avg);
       }
       E = wave_sum(es);
       if (E <= tol * fabs(A)) break;
@@ -1037,7 +1056,7 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
       double carry = 0.0;
       for (int base = 0; base < N; base += WAVE) {
         const int p = base + lane;
-        const double w = p < N ? fmax(S.E[p] - avg, 0.0) : 0.0;
+        const double w = p < N ? interval_weight(S, p, N, (double)S.E[p], avg) : 0.0;
         const double inc = wave_incl_scan(w, lane);
         const double tot = readlane_f64(inc, WAVE - 1);
         const bool mine = !found && lane < nnew && u < carry + tot;

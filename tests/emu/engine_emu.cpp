@@ -102,6 +102,7 @@ int emu_finite_mag(double s, double q, double zx, double zy, double rho, double 
   T.rho = rho;
   T.zx = zx;
   T.zy = zy;
+  T.tol = tol;
   for (int k = 0; k < 5; ++k) T.roots[k] = im.z[k];
   FsOut o;
   if (n0 < 64 || n0 > LCAP || n0 % 64) return -1;
@@ -134,6 +135,7 @@ int emu_finite_mag_rounds(double s, double q, double zx, double zy, double rho, 
   T.rho = rho;
   T.zx = zx;
   T.zy = zy;
+  T.tol = tol;
   for (int k = 0; k < 5; ++k) T.roots[k] = im.z[k];
   FsOut o;
   *launches = mixed ? run_rounds_t<true>(T, tol, NNEW, &o) : run_rounds_t<false>(T, tol, NNEW, &o);
