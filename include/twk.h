@@ -127,6 +127,26 @@ int twk_finite_mag_each(twk_ctx *ctx, int64_t n, const double *s, const double *
                         uint32_t mode, double *mag, double *err, int32_t *n_samples,
                         uint32_t *flags);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * twk_finite_mag without any allocation.  Same arguments, results and
+ * errors as twk_finite_mag, bit-identical results, for modes TWK_MODE_FP64
+ * or TWK_MODE_MIXED, optionally with TWK_MODE_ALL_FS.  Its scratch (work
+ * counters, the task queue and the global slices of the persistent waves)
+ * is a fixed device array of 129 MB compiled into the library, of which
+ * each device holds one copy until the process ends; its address on a
+ * device is looked up when the first context is created there.  Limits:
+ * n <= 65536 sources per call (TWK_EINVAL above), at most 128 persistent
+ * waves; the learned budget (TWK_MODE_MLP) and TWK_MODE_ROUNDS are refused
+ * with TWK_EINVAL.  Issues only kernel launches on the context's stream (no
+ * memset, no synchronisation), so it may be captured.  Every call on one
+ * device shares that device's array: calls that overlap on a device (other
+ * streams, other contexts or threads) race and must be serialised by the
+ * caller.  It does not update twk_last_stats or the stage timing. */
+int twk_finite_mag_noalloc(twk_ctx *ctx, double s, double q, int64_t n, const double *zeta_x,
+                           const double *zeta_y, double rho, double tol, uint32_t mode,
+                           double *mag, double *err, int32_t *n_samples, uint32_t *flags);
+
 /* Batched light curves: nsets lenses/sources (device arrays s, q, u0,
  * alpha, rho, each of length nsets) times nepochs epochs tau (device array)
  * on straight trajectories zeta = (tau cos a - u0 sin a) + i (tau sin a +

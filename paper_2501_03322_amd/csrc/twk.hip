@@ -29,6 +29,7 @@
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/twk.h"
@@ -699,6 +700,44 @@ __global__ void k_zero_counter(long long* p) {
   if (threadIdx.x == 0) *p = 0;
 }
 
+// Scratch of twk_finite_mag_noalloc, which allocates nothing: counters,
+// the task queue of at most NOALLOC_MAX_N sources and the global slices of
+// at most NOALLOC_WAVES persistent waves (129 MB).  Each device the
+// library runs on holds its own copy until the process ends.
+constexpr int64_t NOALLOC_MAX_N = 65536;
+constexpr int NOALLOC_WAVES = 128;
+constexpr size_t NOALLOC_TASK_OFF = 256;
+constexpr size_t NOALLOC_SLICE_OFF = NOALLOC_TASK_OFF + (size_t)NOALLOC_MAX_N * sizeof(Task);
+constexpr size_t NOALLOC_BYTES =
+    NOALLOC_SLICE_OFF + (size_t)NOALLOC_WAVES * METHOD_CAP * kSlotBytesMax;
+static_assert(C_NCOUNTERS * sizeof(long long) <= NOALLOC_TASK_OFF, "counters fit");
+static_assert(NOALLOC_SLICE_OFF % 256 == 0, "slices aligned");
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+// This device's address of `scratch` (host code must not pass the array's
+// name to a kernel: that is a host-side stand-in).  Looked up once per
+// device, with the device current, by the first context created on it.
+std::mutex g_noalloc_mu;
+char* g_noalloc[64] = {};
+
+int noalloc_address(int device, char** out) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (device < 0 || device >= 64) return TWK_EDEVICE;
+  if (!g_noalloc[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return TWK_EDEVICE;
+    }
+    g_noalloc[device] = (char*)p;
+  }
+  *out = g_noalloc[device];
+  return TWK_OK;
+}
 }  // namespace
 
 // ------------------------------------------------------------------ host
@@ -709,6 +748,7 @@ struct twk_ctx {
   int last_err = 0;
   char* slices = nullptr;  // the persistent waves' global slices
   size_t slices_bytes = 0;
+  char* noalloc = nullptr;  // this device's address of the file-scope scratch array
   Task* tasks = nullptr;
   int64_t task_cap = 0;
   long long* cnt = nullptr;
@@ -1097,6 +1137,11 @@ int twk_create(twk_ctx** out, int device, void* stream) {
     delete c;
     return TWK_ENOMEM;
   }
+  if (noalloc_address(device, &c->noalloc) != TWK_OK) {
+    (void)hipFree(c->cnt);
+    delete c;
+    return TWK_EDEVICE;
+  }
   *out = c;
   return TWK_OK;
 }
@@ -1331,6 +1376,57 @@ int twk_finite_mag_each(twk_ctx* c, int64_t n, const double* s, const double* q,
     }
     return mark_call(c, 1);
   });
+}
+
+}  // extern "C"
+
+namespace {
+template <int LCAP>
+void launch_noalloc_fs(twk_ctx* c, bool mixed, long long* cnt, Task* tasks, char* sl,
+                       double* mag, double* err, int32_t* ns, uint32_t* flags) {
+  const int ci = cap_index(LCAP);
+  const int waves = std::min(NOALLOC_WAVES, c->occ[ci][mixed ? 1 : 0] * c->n_cu);
+  if (mixed)
+    hipLaunchKernelGGL((k_fs<LCAP, true>), dim3(waves), dim3(64), 0, c->stream, tasks,
+                       &cnt[C_NTASK], &cnt[C_HEAD], sl, mag, err, ns, flags, cnt,
+                       (const int32_t*)nullptr);
+  else
+    hipLaunchKernelGGL((k_fs<LCAP, false>), dim3(waves), dim3(64), 0, c->stream, tasks,
+                       &cnt[C_NTASK], &cnt[C_HEAD], sl, mag, err, ns, flags, cnt,
+                       (const int32_t*)nullptr);
+}
+}  // namespace
+
+extern "C" {
+
+int twk_finite_mag_noalloc(twk_ctx* c, double s, double q, int64_t n, const double* zx,
+                           const double* zy, double rho, double tol, uint32_t mode, double* mag,
+                           double* err, int32_t* ns, uint32_t* flags) {
+  if (!c || !finite_pos(s) || !finite_pos(q) || !finite_pos(rho) || !finite_pos(tol) || n < 0 ||
+      n > NOALLOC_MAX_N || (mode & ~(TWK_MODE_MIXED | TWK_MODE_ALL_FS)))
+    return TWK_EINVAL;
+  if (n == 0) return TWK_OK;
+  if (!zx || !zy || !mag || !err || !ns || !flags) return TWK_EINVAL;
+  if (!c->noalloc) return TWK_EDEVICE;
+  HIP_TRY(c, hipSetDevice(c->device));
+  long long* cnt = (long long*)c->noalloc;
+  Task* tasks = (Task*)(c->noalloc + NOALLOC_TASK_OFF);
+  char* sl = c->noalloc + NOALLOC_SLICE_OFF;
+  const bool mixed = (mode & TWK_MODE_MIXED) != 0;
+  const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
+  // the counters start at zero by a kernel (no memset node if captured)
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, cnt, 0);
+  HIP_TRY(c, hipGetLastError());
+  hipLaunchKernelGGL(k_prep, dim3(blocks_for(n)), dim3(256), 0, c->stream, s, q, n, zx, zy, rho, tol,
+                     all_fs, tasks, cnt, mag, err, ns, flags, (float*)nullptr);
+  HIP_TRY(c, hipGetLastError());
+  switch (c->tune.lds_cap) {
+    case 64: launch_noalloc_fs<64>(c, mixed, cnt, tasks, sl, mag, err, ns, flags); break;
+    case 256: launch_noalloc_fs<256>(c, mixed, cnt, tasks, sl, mag, err, ns, flags); break;
+    default: launch_noalloc_fs<128>(c, mixed, cnt, tasks, sl, mag, err, ns, flags); break;
+  }
+  HIP_TRY(c, hipGetLastError());
+  return TWK_OK;
 }
 
 int twk_mag_map(twk_ctx* c, double s, double q, double rho, double xc, double yc, double width,

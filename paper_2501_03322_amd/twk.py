@@ -29,7 +29,8 @@ FLAG_NONFINITE = 1 << 4
 FLAG_NEARDEGEN = 1 << 5
 
 EXPORTS = ("twk_create", "twk_destroy", "twk_sync", "twk_last_hip_error", "twk_strerror",
-           "twk_point_mag", "twk_finite_mag", "twk_finite_mag_each", "twk_lightcurves",
+           "twk_point_mag", "twk_finite_mag", "twk_finite_mag_each", "twk_finite_mag_noalloc",
+           "twk_lightcurves",
            "twk_last_stats",
            "twk_enable_timing", "twk_kernel_times", "twk_mag_map", "twk_features",
            "twk_mlp_set", "twk_mlp_get", "twk_mlp_save", "twk_mlp_load", "twk_mlp_infer",
@@ -85,6 +86,7 @@ def load():
     L.twk_point_mag.argtypes = [_vp, C.c_double, C.c_double, C.c_int64, _vp, _vp, _vp, _vp, _vp]
     L.twk_finite_mag.argtypes = [_vp, C.c_double, C.c_double, C.c_int64, _vp, _vp, C.c_double,
                                  C.c_double, C.c_uint32, _vp, _vp, _vp, _vp]
+    L.twk_finite_mag_noalloc.argtypes = L.twk_finite_mag.argtypes
     L.twk_finite_mag_each.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_double,
                                       C.c_uint32, _vp, _vp, _vp, _vp]
     L.twk_lightcurves.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int64, _vp,
@@ -205,6 +207,20 @@ class Context:
         self._check(self.lib.twk_finite_mag(self.h, s, q, n, _ptr(zx), _ptr(zy), rho, tol, mode,
                                             _ptr(mag), _ptr(err), _ptr(ns), _ptr(fl)),
                     "twk_finite_mag")
+        return out
+
+    def finite_mag_noalloc(self, s, q, zx, zy, rho, tol, mode=MODE_FP64, out=None):
+        """twk_finite_mag without any allocation by the library (its scratch
+        is a fixed device array): at most 65536 sources per call."""
+        zx = _dev(zx, self.device)
+        zy = _dev(zy, self.device)
+        n = zx.numel()
+        if out is None:
+            out = self.alloc_out(n)
+        mag, err, ns, fl = out
+        self._check(self.lib.twk_finite_mag_noalloc(self.h, s, q, n, _ptr(zx), _ptr(zy), rho, tol,
+                                                    mode, _ptr(mag), _ptr(err), _ptr(ns), _ptr(fl)),
+                    "twk_finite_mag_noalloc")
         return out
 
     def finite_mag_each(self, s, q, zx, zy, rho, tol, mode=MODE_FP64, out=None):
