@@ -28,7 +28,8 @@ if an unflagged result misses the tolerance.
 
 Prints one JSON line with the value, the roofline of the dominant kernel
 (the persistent contour kernel, VALU-bound), and the CPU oracle timed on a
-bounded sample of the same workload, on one core and on all cores.
+bounded sample of the same workload, on one core and on all cores, and the
+multi-core CPU backend of the method on whole light curves of it.
 """
 import argparse
 import json
@@ -211,6 +212,21 @@ def cpu_baseline(c, seconds, threads, seed=11):
                 host_cpu=host)
 
 
+def cpu_backend_rate(c, threads, nsets=16, seed=12):
+    """The multi-core CPU backend of the method (libtwk_cpu.so) on a seeded
+    subsample of whole light curves of the workload, on `threads` threads."""
+    from paper_2501_03322_amd import cpu
+    sub = c.subset(np.random.default_rng(seed).choice(c.nsets, nsets, replace=False))
+    t0 = time.perf_counter()
+    cpu.lightcurves(sub.s, sub.q, sub.u0, sub.alpha, sub.rho, sub.tau, sub.tol, gamma=sub.gamma,
+                    n_annuli=sub.n_annuli, threads=threads)
+    dt = time.perf_counter() - t0
+    n = sub.nsets * sub.nepochs
+    return {"value": n / dt, "unit": "magnifications/s", "cores": threads,
+            "sample": f"{nsets} parameter sets drawn at random (seed {seed}) x {sub.nepochs} epochs "
+                      f"({n} magnifications), {dt:.1f} s"}
+
+
 def oracle_check(c, out, other_mag, tol, threads, k=24, flagged_max=48, seed=5):
     """Tight-oracle check of the headline's results on the epochs where it
     and another path disagree most, where err / (tol mu) is largest, every
@@ -319,6 +335,14 @@ def pmc_summary(fetch_dir, write_dir):
                 for r in csv.DictReader(fh):
                     if r["Counter_Name"] == counter:
                         rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        # rocprofv3's default database output (rocpd, SQLite)
+        for f in glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True):
+            import sqlite3
+            db = sqlite3.connect(f)
+            for did, name, v in db.execute("select dispatch_id, kernel_name, value from counters_collection "
+                                           "where counter_name = ?", (counter,)):
+                rows.append((int(did), name, float(v)))
+            db.close()
         per = {}
         for did, name, v in rows:
             per.setdefault(did, [name, 0.0])[1] += v
@@ -527,6 +551,8 @@ def main():
         log(f"cpu baseline: oracle for about {args.cpu_seconds:.0f} s on one thread, then "
             f"{args.cpu_seconds / 2:.0f} s on {threads}")
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds, threads)
+        log(f"cpu backend of the method on {threads} threads")
+        out["cpu_baseline"]["cpu_backend"] = cpu_backend_rate(c, threads)
     print(json.dumps(out), flush=True)
     if check is not None and check["max_rel_err_vs_oracle"] is not None and \
             check["max_rel_err_vs_oracle"] > c.tol:

@@ -21,13 +21,30 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-I", os.path.join(ROOT, "include")]
 
 
+# The multi-core CPU backend (plain C++17 and threads; no HIP).
+CPU_LIB = os.path.join(HERE, "libtwk_cpu.so")
+CPU_SRC = os.path.join(HERE, "cpu", "twk_cpu.cpp")
+CPU_FLAGS = ["-O3", "-std=c++17", "-march=x86-64-v2", "-fPIC", "-shared", "-pthread", "-Wall",
+             "-Wextra", "-I", os.path.join(ROOT, "include")]
+
+
 def build(verbose: bool = False, extra=None) -> str:
     cmd = [HIPCC] + FLAGS + (extra or []) + SRC + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    build_cpu(verbose)
     return LIB
+
+
+def build_cpu(verbose: bool = False) -> str:
+    cmd = ["g++"] + CPU_FLAGS + [CPU_SRC, "-o", CPU_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(CPU_LIB + ".tmp", CPU_LIB)
+    return CPU_LIB
 
 
 if __name__ == "__main__":

@@ -30,6 +30,17 @@ def test_library_exports_every_declared_symbol():
     assert set(twk.EXPORTS) <= set(_declared("twk.h"))
 
 
+def test_cpu_backend_exports_every_declared_symbol():
+    from paper_2501_03322_amd import build, cpu
+    if not os.path.exists(cpu.LIB_PATH):
+        build.build_cpu()
+    lib = ctypes.CDLL(cpu.LIB_PATH)
+    names = _declared("twk_cpu.h")
+    assert names == ["twk_cpu_finite_mag", "twk_cpu_lightcurves"]
+    for name in names:
+        assert hasattr(lib, name), name
+
+
 def test_strerror_without_gpu():
     from paper_2501_03322_amd import twk
     if not os.path.exists(twk.LIB_PATH):
