@@ -46,6 +46,10 @@ extern "C" {
 #define TWK_ENOMEM (-3)  /* device allocation failed                        */
 #define TWK_ENOMLP (-4)  /* TWK_MODE_MLP requested without loaded weights   */
 
+/* Forms of the quintic's coefficients (twk_coefficients). */
+#define TWK_COEF_REFINED 0      /* Sec. 2.2, Eq. method-transformed (the method's) */
+#define TWK_COEF_CONVENTIONAL 1 /* Sec. 2.2, Eq. lens-poly-orig (comparator only)  */
+
 /* Mode bits for the finite-source calls. */
 #define TWK_MODE_FP64 0u           /* FP64 root iterations                     */
 #define TWK_MODE_MIXED (1u << 0)   /* FP32 bulk root iterations + FP64 polish  */
@@ -59,6 +63,15 @@ extern "C" {
  * pass and for each round; it is never captured in a graph).  Results are
  * those of the persistent kernel (same rounds, same arithmetic). */
 #define TWK_MODE_ROUNDS (1u << 4)
+/* Comparator, for accuracy comparisons only (not the method): every limb
+ * point solves the quintic with the conventional coefficients of Sec. 2.2
+ * (Eq. lens-poly-orig, in which terms of order 1 and of order q cancel for
+ * small q; Fig. 1) and classifies its roots as older codes do: real when
+ * the lens-equation residual is below a fixed absolute 1e-6 (Einstein
+ * radii), no lens-equation polish, no slope detector, parity from sign(J).
+ * FP64 only (TWK_EINVAL with TWK_MODE_MIXED or TWK_MODE_MLP); every source
+ * is integrated (as with TWK_MODE_ALL_FS) by the round-by-round dispatch. */
+#define TWK_MODE_CONVENTIONAL (1u << 5)
 
 #define TWK_FLAG_POINT (1u << 0)
 #define TWK_FLAG_CAP (1u << 1)
@@ -87,6 +100,17 @@ const char *twk_strerror(int status);
  * NULL (n > 0). */
 int twk_point_mag(twk_ctx *ctx, double s, double q, int64_t n, const double *zeta_x,
                   const double *zeta_y, double *mag, int32_t *n_images, uint32_t *flags);
+
+/* Coefficients c0..c5 of the quintic sum_k c_k eta^k = 0 whose roots are
+ * the image positions in the lens-2 frame (eta = z - s/(1+q)), for n source
+ * positions (zeta_x[i], zeta_y[i]) in the centre-of-mass frame: form
+ * TWK_COEF_REFINED (Sec. 2.2, Eq. method-transformed, as every limb point
+ * of the method assembles them) or TWK_COEF_CONVENTIONAL (Eq.
+ * lens-poly-orig, the comparator's).  Output (device, [n][12] doubles):
+ * Re, Im of c0, ..., c5.  Errors: TWK_EINVAL for s, q <= 0 or
+ * non-finite, n < 0 or > 2^48, an unknown form, NULL pointers (n > 0). */
+int twk_coefficients(twk_ctx *ctx, double s, double q, int64_t n, const double *zeta_x,
+                     const double *zeta_y, int32_t form, double *c12);
 
 /* Finite-source magnification of n uniform disks of radius rho centred at
  * (zeta_x[i], zeta_y[i]) by adaptive contour integration (Secs. 2.3-2.5, 3):
@@ -158,7 +182,7 @@ int twk_finite_mag_noalloc(twk_ctx *ctx, double s, double q, int64_t n, const do
  * Outputs (device, length nsets*nepochs, set-major): mag, err, n_samples
  * (summed over annuli), flags.  Point-source-adequate epochs are answered
  * by the point value; all others by contour integration in one persistent
- * launch per chunk of parameter sets (a chunk holds at most 2^24 contour
+ * launch per chunk of parameter sets (a chunk holds at most 2^26 contour
  * tasks) fed by a device work queue.  Queued on the context's stream without
  * waiting for it (except when the context's buffers must grow).
  * Errors: TWK_EINVAL for nsets or nepochs < 0, nepochs above 2^30,
@@ -188,7 +212,7 @@ int twk_mag_map(twk_ctx *ctx, double s, double q, double rho, double xc, double 
  * returned results, out[3] = persistent waves launched, out[4] = FP32 root
  * sweeps, out[5] = FP64 root sweeps (one sweep updates all five roots of one
  * limb point), out[6] = intervals linked, out[7] = contour-kernel launches
- * of the call (one per chunk; a call is split into chunks of at most 2^24
+ * of the call (one per chunk; a call is split into chunks of at most 2^26
  * contour tasks).  Synchronises the context's stream. */
 int twk_last_stats(twk_ctx *ctx, int64_t *out8);
 

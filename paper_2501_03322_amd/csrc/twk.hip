@@ -199,9 +199,7 @@ __device__ inline PsResult point_source_pass(const Lens& L, c64 yc, double rho, 
 // rho |grad mu_ps| / mu_ps from central differences over the stencil,
 // floored at 1e-30.
 // rho: the radius of the stencil the point pass used; rho_f: the radius of
-// the disk the features describe (an annulus contour of a limb-darkened
-// source is a uniform disk of its own radius; the gradient term scales with
-// the radius).
+// the disk the features describe (the gradient term scales with it).
 __device__ inline void ps_features(double s, double q, double zx, double zy, double rho,
                                    double rho_f, const PsResult& ps, float* f) {
   const double grad = 0.5 * sqrt(ps.gx * ps.gx + ps.gy * ps.gy) * (rho_f / rho);
@@ -243,6 +241,25 @@ __global__ __launch_bounds__(256) void k_point(double s, double q, int64_t n, co
   mag[i] = point_mag(im);
   nimg[i] = im.n;
   flags[i] = im.flags;
+}
+
+// Coefficients of the quintic (lens-2 frame, c0..c5 as Re, Im) of n source
+// positions: the refined form of the method, or (conventional != 0) the
+// conventional form the comparator uses.
+__global__ __launch_bounds__(256) void k_coef(double s, double q, int64_t n, const double* zx,
+                                              const double* zy, int conventional, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Lens L = make_lens(s, q);
+  const c64 y = cz(zx[i] - L.z2, zy[i]);
+  c64 c[6];
+  if (conventional) coefficients_conventional(L, y, c);
+  else coefficients(L, y, c);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    out[12 * i + 2 * k] = c[k].x;
+    out[12 * i + 2 * k + 1] = c[k].y;
+  }
 }
 
 // Append `count` entries per calling lane (0 or a lane-uniform k) to a
@@ -327,13 +344,13 @@ __device__ inline void emit_source(int64_t out, double s, double q, double zx, d
       tasks[slot + k] = t;
     }
     if (tfeat) {
-      // the features of each contour: those of a uniform disk of its radius
-      for (int k = 0; k < na; ++k) {
-        float f[8];
-        ps_features(s, q, zx, zy, rho, na > 1 ? rho * sqrt((double)(k + 1) / na) : rho, ps, f);
+      // features of the source (a limb-darkened epoch: of its outer disk,
+      // one row per epoch, shared by its annulus contours)
+      float f[8];
+      ps_features(s, q, zx, zy, rho, rho, ps, f);
+      const int64_t row = na > 1 ? first_out / na : slot;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) tfeat[(slot + k) * 8 + j] = f[j];
-      }
+      for (int j = 0; j < 8; ++j) tfeat[row * 8 + j] = f[j];
     }
   }
 }
@@ -540,12 +557,19 @@ __device__ inline int budget_class(float l2) {
   return min(max((int)floorf(l2) - 6, 0), NBUCKET - 1);
 }
 
-__global__ __launch_bounds__(256) void k_budget(long long* cnt, const float* out) {
+// Inference row of task i: its own, or (limb darkening, na > 1) its
+// epoch's, whose annulus contours have outputs epoch * na + k.
+__device__ __forceinline__ int64_t task_row(const Task* tasks, int64_t i, int na) {
+  return na > 1 ? tasks[i].out / na : i;
+}
+
+__global__ __launch_bounds__(256) void k_budget(long long* cnt, const float* out, const Task* tasks,
+                                                int na) {
   __shared__ int hist[NBUCKET];
   if (threadIdx.x < NBUCKET) hist[threadIdx.x] = 0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt[C_NTASK]) atomicAdd(&hist[budget_class(out[2 * i])], 1);
+  if (i < cnt[C_NTASK]) atomicAdd(&hist[budget_class(out[2 * task_row(tasks, i, na)])], 1);
   __syncthreads();
   if (threadIdx.x < NBUCKET && hist[threadIdx.x] > 0)
     atomicAdd((unsigned long long*)&cnt[C_BUCKET + threadIdx.x],
@@ -555,7 +579,8 @@ __global__ __launch_bounds__(256) void k_budget(long long* cnt, const float* out
 // Longest first: class 6 (largest predicted count) leads the queue order.
 // Each block reserves one range per class (one global atomic per class)
 // and places its tasks at LDS-assigned ranks inside it.
-__global__ __launch_bounds__(256) void k_place(long long* cnt, const float* out, int32_t* order) {
+__global__ __launch_bounds__(256) void k_place(long long* cnt, const float* out, const Task* tasks,
+                                               int na, int32_t* order) {
   __shared__ int hist[NBUCKET];
   __shared__ long long base[NBUCKET];
   if (threadIdx.x < NBUCKET) hist[threadIdx.x] = 0;
@@ -564,7 +589,7 @@ __global__ __launch_bounds__(256) void k_place(long long* cnt, const float* out,
   const bool on = i < cnt[C_NTASK];
   int b = 0, rank = 0;
   if (on) {
-    b = budget_class(out[2 * i]);
+    b = budget_class(out[2 * task_row(tasks, i, na)]);
     rank = atomicAdd(&hist[b], 1);
   }
   __syncthreads();
@@ -638,7 +663,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES
 // not finished is appended to list_out (count in *n_out).  Sources b of the
 // batch are tasks b0 + b (in the learned queue order when order is given);
 // each has its global slice b and its state rs[b].
-template <bool MIXED>
+template <bool MIXED, bool CONV>
 __global__ __launch_bounds__(64) void k_fs_round(const Task* tasks, int64_t b0,
                                                  const int32_t* order, const int32_t* list_in,
                                                  int32_t* list_out,
@@ -654,7 +679,7 @@ __global__ __launch_bounds__(64) void k_fs_round(const Task* tasks, int64_t b0,
   const Task task = tasks[t];
   const WaveMem<MIXED> m = wave_mem<MIXED>(slices, b);
   FsOut o;
-  if (fs_round_step<MIXED>(task, task.tol, m, (lint*)ivl, lane, NNEW, &rs[b], fresh, &o)) {
+  if (fs_round_step<MIXED, CONV>(task, task.tol, m, (lint*)ivl, lane, NNEW, &rs[b], fresh, &o)) {
     if (lane == 0) {
       mag[task.out] = o.mag;
       err[task.out] = o.err;
@@ -876,8 +901,9 @@ int cap_index(int lds_cap) {
 
 int fs_waves(const twk_ctx* c) { return c->tune.waves_per_cu * c->n_cu; }
 
-// Task records per chunk of a call: bounds the queue memory (128 B each).
-constexpr int64_t CHUNK_TASKS = (int64_t)1 << 24;
+// Task records per chunk of a call: bounds the queue memory (136 B each,
+// 9 GB at most).  Fewer, larger chunks pay fewer launch tails.
+constexpr int64_t CHUNK_TASKS = (int64_t)1 << 26;
 
 int ensure_fs(twk_ctx* c, int64_t ntask_max) {
   int rc;
@@ -943,15 +969,17 @@ int ensure_learn(twk_ctx* c, int64_t ntask_max) {
 // predict every queued task's sample count, set its starting grid, and
 // order the queue longest first.  Grids cover the chunk's task capacity;
 // threads beyond the device-side task count return at once.
-int learned_stage(twk_ctx* c, int64_t ntask_max) {
+int learned_stage(twk_ctx* c, int64_t ntask_max, int na) {
   const LearnBufs b = learn_bufs(c);
   hipLaunchKernelGGL(mlp::k_infer, dim3(c->n_cu), dim3(64 * mlp::INFER_WAVES), 0, c->stream,
-                     c->mlp_p, c->mlp_frag, (int64_t)0, &c->cnt[C_NTASK], b.feat, b.out);
+                     c->mlp_p, c->mlp_frag, (int64_t)0, &c->cnt[na > 1 ? C_NFS : C_NTASK], b.feat,
+                     b.out);
   HIP_TRY(c, hipGetLastError());
   const unsigned g = (unsigned)((ntask_max + 255) / 256);
-  hipLaunchKernelGGL(k_budget, dim3(g), dim3(256), 0, c->stream, c->cnt, b.out);
+  hipLaunchKernelGGL(k_budget, dim3(g), dim3(256), 0, c->stream, c->cnt, b.out, c->tasks, na);
   HIP_TRY(c, hipGetLastError());
-  hipLaunchKernelGGL(k_place, dim3(g), dim3(256), 0, c->stream, c->cnt, b.out, b.order);
+  hipLaunchKernelGGL(k_place, dim3(g), dim3(256), 0, c->stream, c->cnt, b.out, c->tasks, na,
+                     b.order);
   HIP_TRY(c, hipGetLastError());
   return TWK_OK;
 }
@@ -994,7 +1022,7 @@ constexpr int64_t ROUND_BATCH = 32768;
 // The paper's dispatch: the host reads the number of queued tasks, then
 // for each batch of sources launches one round after another over the list
 // of unfinished ones, reading the list's length after each round.
-int rounds_stage(twk_ctx* c, bool mixed, bool learned, double* mag, double* err,
+int rounds_stage(twk_ctx* c, bool mixed, bool learned, bool conv, double* mag, double* err,
                  int32_t* ns, uint32_t* flags) {
   long long ntask = 0, nout = 0;
   HIP_TRY(c, hipMemcpyAsync(&ntask, &c->cnt[C_NTASK], 8, hipMemcpyDeviceToHost, c->stream));
@@ -1016,14 +1044,18 @@ int rounds_stage(twk_ctx* c, bool mixed, bool learned, double* mag, double* err,
     int64_t nin = nb;
     while (nin > 0) {
       hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, c->stream, &c->cnt[C_NOUT]);
-      if (mixed)
-        hipLaunchKernelGGL(k_fs_round<true>, dim3((unsigned)nin), dim3(64), 0, c->stream, c->tasks,
-                           b0, order, lin, lout, &c->cnt[C_NOUT], rs, c->rslices, mag, err, ns,
-                           flags);
+      if (conv)
+        hipLaunchKernelGGL((k_fs_round<false, true>), dim3((unsigned)nin), dim3(64), 0, c->stream,
+                           c->tasks, b0, order, lin, lout, &c->cnt[C_NOUT], rs, c->rslices, mag, err,
+                           ns, flags);
+      else if (mixed)
+        hipLaunchKernelGGL((k_fs_round<true, false>), dim3((unsigned)nin), dim3(64), 0, c->stream,
+                           c->tasks, b0, order, lin, lout, &c->cnt[C_NOUT], rs, c->rslices, mag, err,
+                           ns, flags);
       else
-        hipLaunchKernelGGL(k_fs_round<false>, dim3((unsigned)nin), dim3(64), 0, c->stream,
-                           c->tasks, b0, order, lin, lout, &c->cnt[C_NOUT], rs, c->rslices,
-                           mag, err, ns, flags);
+        hipLaunchKernelGGL((k_fs_round<false, false>), dim3((unsigned)nin), dim3(64), 0, c->stream,
+                           c->tasks, b0, order, lin, lout, &c->cnt[C_NOUT], rs, c->rslices, mag, err,
+                           ns, flags);
       HIP_TRY(c, hipGetLastError());
       HIP_TRY(c, hipMemcpyAsync(&nout, &c->cnt[C_NOUT], 8, hipMemcpyDeviceToHost, c->stream));
       HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1194,11 +1226,29 @@ int twk_point_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, c
   return TWK_OK;
 }
 
+int twk_coefficients(twk_ctx* c, double s, double q, int64_t n, const double* zx, const double* zy,
+                     int32_t form, double* c12) {
+  if (!c || !finite_pos(s) || !finite_pos(q) || n < 0 || n > MAX_ELEMS ||
+      (form != TWK_COEF_REFINED && form != TWK_COEF_CONVENTIONAL))
+    return TWK_EINVAL;
+  if (n == 0) return TWK_OK;
+  if (!zx || !zy || !c12) return TWK_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  for (int64_t i0 = 0; i0 < n; i0 += LAUNCH_MAX) {
+    const int64_t m = std::min(LAUNCH_MAX, n - i0);
+    hipLaunchKernelGGL(k_coef, dim3(blocks_for(m)), dim3(256), 0, c->stream, s, q, m, zx + i0,
+                       zy + i0, form == TWK_COEF_CONVENTIONAL ? 1 : 0, c12 + 12 * i0);
+    HIP_TRY(c, hipGetLastError());
+  }
+  return TWK_OK;
+}
+
 }  // extern "C"
 
 namespace {
 
-constexpr uint32_t KNOWN_MODES = TWK_MODE_MIXED | TWK_MODE_MLP | TWK_MODE_ALL_FS | TWK_MODE_ROUNDS;
+constexpr uint32_t KNOWN_MODES =
+    TWK_MODE_MIXED | TWK_MODE_MLP | TWK_MODE_ALL_FS | TWK_MODE_ROUNDS | TWK_MODE_CONVENTIONAL;
 
 // Identity of a call for graph replay: entry point (ORed with ROUNDS_KEY
 // for the round-by-round dispatch), scalar arguments (as bits), device
@@ -1277,28 +1327,33 @@ int run_captured(twk_ctx* c, const CallKey& key, F&& issue) {
 // Mode bits: unknown bits are rejected; the learned budget needs weights.
 int check_mode(twk_ctx* c, uint32_t mode) {
   if (mode & ~KNOWN_MODES) return TWK_EINVAL;
+  if ((mode & TWK_MODE_CONVENTIONAL) && (mode & (TWK_MODE_MIXED | TWK_MODE_MLP))) return TWK_EINVAL;
   if ((mode & TWK_MODE_MLP) && !c->mlp_ready) return TWK_ENOMLP;
   return TWK_OK;
 }
 
 // After the point-source pass of chunk k: learned stage (if any), then the
 // contour kernel, each bracketed by the chunk's stage events.
-int contour_stage(twk_ctx* c, int64_t k, uint32_t mode, int64_t ntask_max, double* mag,
+int contour_stage(twk_ctx* c, int64_t k, uint32_t mode, int64_t ntask_max, int na, double* mag,
                   double* err, int32_t* ns, uint32_t* flags) {
   int rc;
   const bool mixed = (mode & TWK_MODE_MIXED) != 0, learned = (mode & TWK_MODE_MLP) != 0;
   if ((rc = mark(c, k, 1))) return rc;
-  if (learned && (rc = learned_stage(c, ntask_max))) return rc;
+  if (learned && (rc = learned_stage(c, ntask_max, na))) return rc;
   if ((rc = mark(c, k, 2))) return rc;
-  if (mode & TWK_MODE_ROUNDS) rc = rounds_stage(c, mixed, learned, mag, err, ns, flags);
+  if (mode & (TWK_MODE_ROUNDS | TWK_MODE_CONVENTIONAL))
+    rc = rounds_stage(c, mixed, learned, (mode & TWK_MODE_CONVENTIONAL) != 0, mag, err, ns, flags);
   else rc = launch_fs(c, mixed, learned, mag, err, ns, flags);
   if (rc) return rc;
   return mark(c, k, 3);
 }
 
 uint64_t entry_key(int id, uint32_t mode) {
-  return (uint64_t)id | ((mode & TWK_MODE_ROUNDS) ? ROUNDS_KEY : 0ull);
+  return (uint64_t)id | ((mode & (TWK_MODE_ROUNDS | TWK_MODE_CONVENTIONAL)) ? ROUNDS_KEY : 0ull);
 }
+
+// Every source by contour (the point-source test skipped)?
+int all_fs_of(uint32_t mode) { return (mode & (TWK_MODE_ALL_FS | TWK_MODE_CONVENTIONAL)) ? 1 : 0; }
 
 }  // namespace
 
@@ -1319,7 +1374,7 @@ int twk_finite_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, 
   const bool learned = (mode & TWK_MODE_MLP) != 0;
   if ((rc = ensure_fs(c, chunk))) return rc;
   if (learned && (rc = ensure_learn(c, chunk))) return rc;
-  const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
+  const int all_fs = all_fs_of(mode);
   float* tfeat = learned ? learn_bufs(c).feat : nullptr;
   CallKey key;
   key.u(entry_key(1, mode)).d(s).d(q).u((uint64_t)n).p(zx).p(zy).d(rho).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
@@ -1335,7 +1390,7 @@ int twk_finite_mag(twk_ctx* c, double s, double q, int64_t n, const double* zx, 
                          zy + i0, rho, tol, all_fs, c->tasks, c->cnt, mag + i0, err + i0, ns + i0,
                          flags + i0, tfeat);
       HIP_TRY(c, hipGetLastError());
-      if ((r = contour_stage(c, i0 / chunk, mode, m, mag + i0, err + i0, ns + i0, flags + i0)))
+      if ((r = contour_stage(c, i0 / chunk, mode, m, 1, mag + i0, err + i0, ns + i0, flags + i0)))
         return r;
     }
     return mark_call(c, 1);
@@ -1355,7 +1410,7 @@ int twk_finite_mag_each(twk_ctx* c, int64_t n, const double* s, const double* q,
   const bool learned = (mode & TWK_MODE_MLP) != 0;
   if ((rc = ensure_fs(c, chunk))) return rc;
   if (learned && (rc = ensure_learn(c, chunk))) return rc;
-  const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
+  const int all_fs = all_fs_of(mode);
   float* tfeat = learned ? learn_bufs(c).feat : nullptr;
   CallKey key;
   key.u(entry_key(4, mode)).u((uint64_t)n).p(s).p(q).p(zx).p(zy).p(rho).d(tol).u(mode).p(mag).p(err).p(ns).p(flags);
@@ -1371,7 +1426,7 @@ int twk_finite_mag_each(twk_ctx* c, int64_t n, const double* s, const double* q,
                          m, zx + i0, zy + i0, rho + i0, tol, all_fs, c->tasks, c->cnt, mag + i0,
                          err + i0, ns + i0, flags + i0, tfeat);
       HIP_TRY(c, hipGetLastError());
-      if ((r = contour_stage(c, i0 / chunk, mode, m, mag + i0, err + i0, ns + i0, flags + i0)))
+      if ((r = contour_stage(c, i0 / chunk, mode, m, 1, mag + i0, err + i0, ns + i0, flags + i0)))
         return r;
     }
     return mark_call(c, 1);
@@ -1413,7 +1468,7 @@ int twk_finite_mag_noalloc(twk_ctx* c, double s, double q, int64_t n, const doub
   Task* tasks = (Task*)(c->noalloc + NOALLOC_TASK_OFF);
   char* sl = c->noalloc + NOALLOC_SLICE_OFF;
   const bool mixed = (mode & TWK_MODE_MIXED) != 0;
-  const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
+  const int all_fs = all_fs_of(mode);
   // the counters start at zero by a kernel (no memset node if captured)
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, cnt, 0);
   HIP_TRY(c, hipGetLastError());
@@ -1446,7 +1501,7 @@ int twk_mag_map(twk_ctx* c, double s, double q, double rho, double xc, double yc
   const bool learned = (mode & TWK_MODE_MLP) != 0;
   if ((rc = ensure_fs(c, rows * nx))) return rc;
   if (learned && (rc = ensure_learn(c, rows * nx))) return rc;
-  const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
+  const int all_fs = all_fs_of(mode);
   float* tfeat = learned ? learn_bufs(c).feat : nullptr;
   CallKey key;
   key.u(entry_key(2, mode)).d(s).d(q).d(rho).d(xc).d(yc).d(width).d(height).u((uint64_t)nx).u((uint64_t)ny).d(tol)
@@ -1463,7 +1518,7 @@ int twk_mag_map(twk_ctx* c, double s, double q, double rho, double xc, double yc
                          yc, width, height, nx, ny, y0, nr, tol, all_fs, c->tasks, c->cnt, mag, err,
                          ns, flags, tfeat);
       HIP_TRY(c, hipGetLastError());
-      if ((r = contour_stage(c, y0 / rows, mode, nr * nx, mag, err, ns, flags)))
+      if ((r = contour_stage(c, y0 / rows, mode, nr * nx, 1, mag, err, ns, flags)))
         return r;
     }
     return mark_call(c, 1);
@@ -1493,7 +1548,7 @@ int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q,
   if (learned && (rc = ensure_learn(c, chunk_n * na))) return rc;
   if (ld && (rc = ensure_ld(c, chunk_n, na))) return rc;
   const AnnBufs ab = ld ? ann_bufs(c, chunk_n * na) : AnnBufs{nullptr, nullptr, nullptr, nullptr};
-  const int all_fs = (mode & TWK_MODE_ALL_FS) ? 1 : 0;
+  const int all_fs = all_fs_of(mode);
   float* tfeat = learned ? learn_bufs(c).feat : nullptr;
   CallKey key;
   key.u(entry_key(3, mode)).u((uint64_t)nsets).p(s).p(q).p(u0).p(alpha).p(rho).p(gamma).u((uint64_t)nepochs).p(tau)
@@ -1513,9 +1568,9 @@ int twk_lightcurves(twk_ctx* c, int64_t nsets, const double* s, const double* q,
                          na, c->tasks, c->cnt, c->fs_epoch, mag + o, err + o, ns + o, flags + o,
                          tfeat);
       HIP_TRY(c, hipGetLastError());
-      if (ld) r = contour_stage(c, k0 / chunk_sets, mode, nk * nepochs * na, ab.mag, ab.err, ab.ns,
-                                ab.flags);
-      else r = contour_stage(c, k0 / chunk_sets, mode, nk * nepochs, mag + o, err + o, ns + o,
+      if (ld) r = contour_stage(c, k0 / chunk_sets, mode, nk * nepochs * na, na, ab.mag, ab.err,
+                                ab.ns, ab.flags);
+      else r = contour_stage(c, k0 / chunk_sets, mode, nk * nepochs, 1, mag + o, err + o, ns + o,
                              flags + o);
       if (r) return r;
       if (ld) {

@@ -161,6 +161,26 @@ __device__ __forceinline__ void coefficients(const Lens& L, c64 y, c64 c[6]) {
   c[0] = (s * s * m2 * m2) * y;
 }
 
+// Comparator only: the conventional coefficients of Sec. 2.2, Eq.
+// lens-poly-orig (the printed symbol `a` of c3 reads -s, the position of
+// lens 1 in this frame).  c3 and c2 add terms of order 1 and of order q
+// that cancel against each other for small q, which costs the digits the
+// refined form keeps (Fig. 1).  Used by the comparator mode and by
+// twk_coefficients; never by the method's path.
+__device__ __forceinline__ void coefficients_conventional(const Lens& L, c64 y, c64 c[6]) {
+  const double s = L.s, m1 = L.m1, m2 = L.m2, s2 = s * s, s3 = s2 * s;
+  const c64 yb = cconj(y);
+  const c64 u = yb * (y - 2.0 * s);  // conj(y) (y - 2 s)
+  c[5] = -(yb * (yb + s));
+  c[4] = yb * (u - 1.0) + s * (u - m1);
+  c[3] = 2.0 * (yb * y) - s3 * yb + s2 * (yb * (2.0 * y - yb) - m1) +
+         s * (y + 2.0 * (yb * ((yb * y) - m2)));
+  c[2] = y * (s3 * yb + 1.0) + s * (2.0 * (1.0 + m2) * (y * yb) + m1) +
+         s2 * ((m1 - m2) * yb + y * (yb * yb + (1.0 + m2)));
+  c[1] = (m2 * s) * (s * (y * (2.0 * yb + s) + m1) + 2.0 * y);
+  c[0] = (s2 * m2 * m2) * y;
+}
+
 // ---------------------------------------------------------------- roots
 // All five roots by the Aberth-Ehrlich simultaneous iteration (each root is
 // corrected by Newton's ratio deflated against the others), updating in
@@ -483,6 +503,64 @@ __device__ inline void finish_images(const Lens& L, c64 y, c64 r[5], Images& im)
   double J[5];
   polish_lens(L, y, r, R, J);
   classify(L, y, r, R, J, im);
+}
+
+// Comparator only: the classification of older codes.  A root is a real
+// image when its lens-equation residual is below a fixed absolute
+// threshold (LEGACY_THR, in Einstein radii), no lens-equation polish, and
+// parity is sign(J).  Five real images when the five residuals are all
+// below the threshold, otherwise the three smallest; a parity sum other
+// than -1 is flagged anomalous.
+constexpr double LEGACY_THR = 1e-6;
+__device__ inline void finish_images_legacy(const Lens& L, c64 y, const c64 r[5], Images& im) {
+  double aR2[5], J[5];
+  int nbelow = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const LensPoint p = lens_point(L, y, r[k]);
+    aR2[k] = cnorm(p.R);
+    J[k] = p.J;
+    nbelow += aR2[k] < LEGACY_THR * LEGACY_THR ? 1 : 0;
+  }
+  // the two largest residuals are the ghosts unless all five are below
+  int a = 0;
+#pragma unroll
+  for (int k = 1; k < 5; ++k)
+    if (aR2[k] > aR2[a]) a = k;
+  int b = a == 0 ? 1 : 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    if (k != a && aR2[k] > aR2[b]) b = k;
+  const bool ghosts = nbelow < 5;
+  int key[5], npos = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    im.J[k] = J[k];
+    im.z[k] = r[k];
+    const bool g = ghosts && (k == a || k == b);
+    key[k] = g ? 2 : (J[k] > 0.0 ? 0 : 1);
+    npos += key[k] == 0 ? 1 : 0;
+  }
+#pragma unroll
+  for (int pass = 0; pass < 4; ++pass) {
+#pragma unroll
+    for (int i = 0; i < 4 - pass; ++i) {
+      const bool sw = key[i] > key[i + 1];
+      const c64 z0 = im.z[i], z1 = im.z[i + 1];
+      const double j0 = im.J[i], j1 = im.J[i + 1];
+      const int k0 = key[i], k1 = key[i + 1];
+      im.z[i] = sw ? z1 : z0;
+      im.z[i + 1] = sw ? z0 : z1;
+      im.J[i] = sw ? j1 : j0;
+      im.J[i + 1] = sw ? j0 : j1;
+      key[i] = sw ? k1 : k0;
+      key[i + 1] = sw ? k0 : k1;
+    }
+  }
+  im.n = ghosts ? 3 : 5;
+  im.par = (1u << npos) - 1u;
+  im.margin = 0.0;
+  im.flags = (2 * npos - im.n != -1) ? F_ANOMALY : 0u;
 }
 
 __device__ __forceinline__ double point_mag(const Images& im) {

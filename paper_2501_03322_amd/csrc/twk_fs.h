@@ -188,14 +188,17 @@ constexpr double PAIR_FLOOR = 1e-7;
 // sample's roots advanced along their derivative; or the centre roots) and
 // write its record to `slot`.  Returns the root sweeps spent (low 16 bits
 // FP64, high 16 bits FP32) and the sample flags in *fl.
-template <bool MIXED, class R>
+// CONV: the comparator (conventional coefficients, the legacy absolute-
+// threshold classification).
+template <bool MIXED, class R, bool CONV = false>
 __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double theta, c64 r[5],
                                        const R& m, int slot, uint32_t* fl) {
   double sn, cs;
   limb_sincos(theta, &sn, &cs);
   const c64 y = yc + rho * cz(cs, sn);
   c64 c[6];
-  coefficients(L, y, c);
+  if constexpr (CONV) coefficients_conventional(L, y, c);
+  else coefficients(L, y, c);
   int it, s32 = 0, s64;
   if (MIXED) s32 = aberth32(c, r, 12);
   it = aberth64(c, r, 40);
@@ -205,7 +208,8 @@ __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double
     s64 += aberth64(c, r, 200);
   }
   Images im;
-  finish_images(L, y, r, im);
+  if constexpr (CONV) finish_images_legacy(L, y, r, im);
+  else finish_images(L, y, r, im);
   const c64 zp1 = cz(-rho * sn, rho * cs);  // zeta' = i rho e^{i theta}
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -238,8 +242,8 @@ __device__ __forceinline__ void warm_start(const R& m, int slot, double dtheta, 
 // Sample records keep their real images ordered by parity: positive ones
 // first (one of three, two of five), then negative ones, then the ghost
 // pair.  Linking (Sec. 2.3) pairs same-parity images of adjacent samples by
-// the assignment of least total distance ("the way to minimize the sum of
-// all distances is selected"); when the counts differ, the left-over + and
+// the assignment whose summed image-to-image distance is smallest, tried
+// over every permutation; when the counts differ, the left-over + and
 // - images at the sample with five images are the pair created (or
 // destroyed) on the critical curve.
 
@@ -993,7 +997,7 @@ enum { FS_DONE = 0, FS_OUTGROWN = 1, FS_PAUSED = 2 };
 // Rounds of the contour integration on the sorted arrays S, at most
 // max_rounds of them (negative: no limit).  ivl: the wave's LDS array of
 // NNEW interval indices of the round's new samples.
-template <bool MIXED, class Sorted, class R>
+template <bool MIXED, class Sorted, class R, bool CONV = false>
 __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc, double tol,
                                          const R& m, lint* ivl, const Sorted& S, int lane,
                                          int n0, FsState& st, int max_rounds = -1) {
@@ -1110,7 +1114,7 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
         warm_start(m, left ? S.sl[iv] : S.sl[ivb], left ? thn - ta : thn - tb, r);
       }
       uint32_t sf;
-      const uint32_t sw = solve_store<MIXED>(lens, yc, rho, thn, r, m, N + rank, &sf);
+      const uint32_t sw = solve_store<MIXED, R, CONV>(lens, yc, rho, thn, r, m, N + rank, &sf);
       sw64 += sw & 0xffffu;
       sw32 += sw >> 16;
       fl |= sf & (F_ANOMALY | F_NEARDEGEN);
@@ -1290,7 +1294,7 @@ struct RoundState {
 // down the first 64 samples of the uniform grid of n0).  Returns true when
 // the source is finished, with its output in *o; otherwise its state is
 // saved in *rs for the next launch.
-template <bool MIXED>
+template <bool MIXED, bool CONV = false>
 __device__ bool fs_round_step(const Task& T, double tol_stated, const WaveMem<MIXED>& gm,
                               lint* ivl, int lane, int n0, RoundState* rs, bool fresh, FsOut* o) {
   const double tol = tol_stated * TOL_SAFETY;
@@ -1306,7 +1310,8 @@ __device__ bool fs_round_step(const Task& T, double tol_stated, const WaveMem<MI
     baseint = r.nint;
   }
   const SortedG<MIXED> S{gm.sth, gm.sE, gm.ssl, METHOD_CAP};
-  const int how = fs_rounds<MIXED>(T, lens, yc, tol, gm.G, ivl, S, lane, n0, st, 1);
+  const int how = fs_rounds<MIXED, SortedG<MIXED>, RecG<MIXED>, CONV>(T, lens, yc, tol, gm.G, ivl, S,
+                                                                     lane, n0, st, 1);
   FsOut out = fs_output(T, st, true);
   out.sweeps32 += base32;
   out.sweeps64 += base64;

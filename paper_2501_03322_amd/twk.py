@@ -20,6 +20,8 @@ MODE_MIXED = 1 << 0
 MODE_MLP = 1 << 2
 MODE_ALL_FS = 1 << 3
 MODE_ROUNDS = 1 << 4
+MODE_CONVENTIONAL = 1 << 5
+COEF_REFINED, COEF_CONVENTIONAL = 0, 1
 
 FLAG_POINT = 1 << 0
 FLAG_CAP = 1 << 1
@@ -29,7 +31,7 @@ FLAG_NONFINITE = 1 << 4
 FLAG_NEARDEGEN = 1 << 5
 
 EXPORTS = ("twk_create", "twk_destroy", "twk_sync", "twk_last_hip_error", "twk_strerror",
-           "twk_point_mag", "twk_finite_mag", "twk_finite_mag_each", "twk_finite_mag_noalloc",
+           "twk_point_mag", "twk_coefficients", "twk_finite_mag", "twk_finite_mag_each", "twk_finite_mag_noalloc",
            "twk_lightcurves",
            "twk_last_stats",
            "twk_enable_timing", "twk_kernel_times", "twk_mag_map", "twk_features",
@@ -84,6 +86,7 @@ def load():
     L.twk_strerror.argtypes = [C.c_int]
     L.twk_strerror.restype = C.c_char_p
     L.twk_point_mag.argtypes = [_vp, C.c_double, C.c_double, C.c_int64, _vp, _vp, _vp, _vp, _vp]
+    L.twk_coefficients.argtypes = [_vp, C.c_double, C.c_double, C.c_int64, _vp, _vp, C.c_int32, _vp]
     L.twk_finite_mag.argtypes = [_vp, C.c_double, C.c_double, C.c_int64, _vp, _vp, C.c_double,
                                  C.c_double, C.c_uint32, _vp, _vp, _vp, _vp]
     L.twk_finite_mag_noalloc.argtypes = L.twk_finite_mag.argtypes
@@ -196,6 +199,17 @@ class Context:
         self._check(self.lib.twk_point_mag(self.h, s, q, n, _ptr(zx), _ptr(zy), _ptr(mag),
                                            _ptr(nimg), _ptr(fl)), "twk_point_mag")
         return mag, nimg, fl
+
+    def coefficients(self, s, q, zx, zy, form=COEF_REFINED):
+        """Quintic coefficients c0..c5 of each source position ([n, 6] complex
+        tensor on the device), refined or conventional form."""
+        zx = _dev(zx, self.device)
+        zy = _dev(zy, self.device)
+        n = zx.numel()
+        out = torch.empty((n, 12), dtype=torch.float64, device=self.device)
+        self._check(self.lib.twk_coefficients(self.h, s, q, n, _ptr(zx), _ptr(zy), form, _ptr(out)),
+                    "twk_coefficients")
+        return torch.view_as_complex(out.view(n, 6, 2))
 
     def finite_mag(self, s, q, zx, zy, rho, tol, mode=MODE_FP64, out=None):
         zx = _dev(zx, self.device)
