@@ -210,14 +210,19 @@ __device__ __forceinline__ void cold_start(const c64 c[6], c64 r[5]) {
 
 // Stopping rule shared by both precisions.  A sweep's largest relative
 // correction d bounds the error before the sweep; Aberth converges cubically
-// for simple roots, so after a sweep with d < 1e-6 the error is ~1e-18 unless
-// two roots are close (then convergence is linear).  Stop when d < 1e-6 and
-// no two roots lie within 1e-3 (relative) of each other, or when d < 1e-14.
-// Returns the number of sweeps used (maxit + 1 when not converged).
+// for simple roots, the error after the sweep being about 4 d^3 / sigma^2
+// for a relative separation sigma of the nearest two roots (linear
+// convergence once the error exceeds sigma).  Stop when d < 1e-14; or when
+// d < 1e-6 and no two roots lie within 1e-3 (relative) of each other; or when
+// d < 1e-5 and none lie within 0.05 (error after the sweep below 2e-12 of the
+// root; the lens-equation polish that follows takes real images to full
+// precision).  Returns the number of sweeps used (maxit + 1 when not
+// converged).
 __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
   for (int it = 0; it < maxit; ++it) {
     double worst = 0.0;
     bool close = false;  // some root within 1e-3 (relative) of another
+    bool near = false;   // some root within 0.05 (relative) of another
     // Gauss-Seidel order: root 0 is corrected against roots 1..4, then the
     // roots rotate by one place; after five steps the order is restored.
     // Only static register indices appear.
@@ -236,7 +241,9 @@ __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
         const double ir = rcp64(n2);
         rep = rep + cz(dd.x * ir, -dd.y * ir);
       }
-      close = close || n2min <= 1e-6 * fmax(cnorm(x), 1e-300);
+      const double x2 = fmax(cnorm(x), 1e-300);
+      close = close || n2min <= 1e-6 * x2;
+      near = near || n2min <= 2.5e-3 * x2;
       // Newton's ratio deflated against the other roots, in one division
       c64 w = p * cinv(cfma(-p, rep, d));
       double nw = cnorm(w);
@@ -255,16 +262,20 @@ __device__ inline int aberth64(const c64 c[6], c64 r[5], int maxit) {
       r[3] = r[4];
       r[4] = xn;
     }
-    if (worst < 1e-28 || (worst < 1e-12 && !close)) return it + 1;
+    if (worst < 1e-28 || (worst < 1e-12 && !close) || (worst < 1e-10 && !near)) return it + 1;
   }
   return maxit + 1;
 }
 
 // Mixed precision: the bulk sweeps in FP32 (polynomial scaled by 1/c5 so
 // that FP32 keeps its range) from a start given in FP64; the caller then
-// polishes with FP64 sweeps.  FP32 stops at a relative correction of 1e-3:
-// by cubic convergence the root is then accurate to about FP32's rounding
-// level, and the first FP64 sweep takes it to full precision.  A lane that has not
+// polishes with FP64 sweeps.  FP32 stops at a relative correction below
+// 0.03: by cubic convergence the roots are then within about 1e-5 of the
+// root (FP32's rounding level when the correction was much smaller), which
+// one FP64 sweep takes to full precision for separated roots (the FP64 stop
+// rule decides).  Stopping there rather than at 1e-3 saves the second FP32
+// sweep of limb points started far from their roots (the first round of a
+// source starts from the roots at its centre).  A lane that has not
 // got there within the sweep cap (near-double roots converge linearly and
 // FP32 rounding stalls them) hands over to the FP64 sweeps, which cost the
 // same on a VALU without packed FP32 and can finish the job; the cap keeps
@@ -309,7 +320,7 @@ __device__ inline int aberth32(const c64 c64c[6], c64 r64[5], int maxit) {
       r[3] = r[4];
       r[4] = xn;
     }
-    if (worst < 1e-6f) {
+    if (worst < 1e-3f) {
       ++it;
       break;
     }

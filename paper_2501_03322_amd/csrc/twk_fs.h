@@ -226,17 +226,37 @@ __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double
   return (uint32_t)s64 | ((uint32_t)s32 << 16);
 }
 
-// Warm start for a new sample dtheta away from the stored sample `slot`:
-// real images advanced by z' dtheta, ghosts copied.
+// Warm start for a new sample at theta between the stored samples sa (at
+// ta) and sb (at tb): the real images of the nearer one advanced by their
+// z'; the ghost pair, when both neighbours have three images, interpolated
+// linearly between the neighbours' ghost pairs (paired by least total
+// distance), else copied from the nearer one.
 template <class R>
-__device__ __forceinline__ void warm_start(const R& m, int slot, double dtheta, c64 r[5]) {
-  const int n = meta_at(m, slot) & 7u;
+__device__ __forceinline__ void warm_start(const R& m, int sa, int sb, double ta, double tb,
+                                           double theta, c64 r[5]) {
+  const bool left = theta - ta <= tb - theta;
+  const int sn = left ? sa : sb;
+  const double dt = left ? theta - ta : theta - tb;
+  const int n = meta_at(m, sn) & 7u;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    r[k] = ld_root(m, k, slot);
-    if (k < n) r[k] = r[k] + dtheta * ld_dz(m, k, slot);
+    r[k] = ld_root(m, k, sn);
+    if (k < n) r[k] = r[k] + dt * ld_dz(m, k, sn);
+  }
+  if (n == 3 && (meta_at(m, left ? sb : sa) & 7u) == 3u) {
+    const c64 a3 = ld_root(m, 3, sa), a4 = ld_root(m, 4, sa);
+    c64 b3 = ld_root(m, 3, sb), b4 = ld_root(m, 4, sb);
+    if (cnorm(a3 - b4) + cnorm(a4 - b3) < cnorm(a3 - b3) + cnorm(a4 - b4)) {
+      const c64 x = b3;
+      b3 = b4;
+      b4 = x;
+    }
+    const double f = (theta - ta) / (tb - ta);
+    r[3] = a3 + f * (b3 - a3);
+    r[4] = a4 + f * (b4 - a4);
   }
 }
+
 
 // ---------------------------------------------------------------- linking
 // Sample records keep their real images ordered by parity: positive ones
@@ -1008,6 +1028,13 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
   uint32_t fl = st.fl, sw32 = st.sw32, sw64 = st.sw64, nint = st.nint;
   bool suspects = st.suspects;
   bool outgrown = false, paused = false;
+  if (N == 0) {
+    // the first round starts from the roots at the source centre, parked in
+    // the record slot each lane's first sample will take (slot = lane), so
+    // that the round loop reads starts from records only
+#pragma unroll
+    for (int k = 0; k < 5; ++k) st_root(m, k, lane, T.roots[k]);
+  }
   // One round per iteration.  The first n0 samples form the uniform grid
   // theta = 2 pi i / n0, laid down 64 at a time: round r adds the phase
   // offset r / (n0 / 64) of the base grid theta_j = 2 pi j / 64 (whose
@@ -1105,13 +1132,12 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
       c64 r[5];
       if (N == 0) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) r[k] = T.roots[k];
+        for (int k = 0; k < 5; ++k) r[k] = ld_root(m, k, lane);
       } else {
         const double ta = S.th[iv];
         const int ivb = iv + 1 < N ? iv + 1 : 0;
         const double tb = iv + 1 < N ? S.th[ivb] : S.th[ivb] + TWO_PI;
-        const bool left = thn - ta <= tb - thn;
-        warm_start(m, left ? S.sl[iv] : S.sl[ivb], left ? thn - ta : thn - tb, r);
+        warm_start(m, (int)S.sl[iv], (int)S.sl[ivb], ta, tb, thn, r);
       }
       uint32_t sf;
       const uint32_t sw = solve_store<MIXED, R, CONV>(lens, yc, rho, thn, r, m, N + rank, &sf);
