@@ -27,7 +27,8 @@ FLAG_NEARDEGEN = 1 << 5
 class Cfg(C.Structure):
     _fields_ = [("tol", C.c_double), ("n0", C.c_int32), ("nnew", C.c_int32),
                 ("cap", C.c_int32), ("grow", C.c_int32), ("slope", C.c_int32),
-                ("kgap", C.c_double), ("cross_flip", C.c_int32)]
+                ("kgap", C.c_double), ("cross_flip", C.c_int32),
+                ("cross_tol", C.c_double)]
 
 
 _lib = None

@@ -878,6 +878,7 @@ void twk_ref_cfg_default(twk_ref_cfg *cfg, double tol) {
   cfg->slope = 1;
   cfg->kgap = 100.0;
   cfg->cross_flip = 0;
+  cfg->cross_tol = 1.0;
 }
 
 static int contour(const lens_t *L, cplx yc, double rho, const twk_ref_cfg *cfg,
@@ -925,7 +926,15 @@ static int contour(const lens_t *L, cplx yc, double rho, const twk_ref_cfg *cfg,
     }
     A = sa.sum + sa.comp;
     E = se;
-    if (E <= tol * fabs(A)) break;
+    /* a contour with both three- and five-image samples crosses a caustic:
+     * there the tolerance is scaled by cfg->cross_tol */
+    int seen3 = 0, seen5 = 0;
+    for (int i = 0; i < N; ++i) {
+      seen3 |= sm[i].im.n == 3;
+      seen5 |= sm[i].im.n == 5;
+    }
+    const double tol_r = (seen3 && seen5) ? cfg->cross_tol * tol : tol;
+    if (E <= tol_r * fabs(A)) break;
     int nnew = cfg->nnew;
     if (cfg->grow > 0 && N / cfg->grow > nnew) nnew = N / cfg->grow;
     if (N + nnew > cap) nnew = cap - N;
@@ -934,7 +943,7 @@ static int contour(const lens_t *L, cplx yc, double rho, const twk_ref_cfg *cfg,
      * narrower than THETA_FLOOR gets no new sample (READING: there the pair
      * merging on the critical curve is closer than its roots can be
      * resolved in binary64, and its pieces are rounding noise) */
-    double avg = tol * fabs(A) / N;
+    double avg = tol_r * fabs(A) / N;
     wcum[0] = 0.0;
     for (int i = 0; i < N; ++i) {
       double w = Wi[i] > THETA_FLOOR ? Ei[i] - avg : 0.0;
@@ -993,7 +1002,7 @@ int twk_ref_finite_mag(double s, double q, int64_t n, const double *zx,
   else twk_ref_cfg_default(&cfg, tol);
   cfg.tol = tol;
   if (cfg.n0 < 4 || cfg.nnew < 1 || cfg.cap < cfg.n0 || cfg.cross_flip < 0 ||
-      cfg.cross_flip > 3)
+      cfg.cross_flip > 3 || !(cfg.cross_tol > 0.0 && cfg.cross_tol <= 1.0))
     return TWK_REF_EINVAL;
   lens_t L = lens_make(s, q);
   for (int64_t i = 0; i < n; ++i) {

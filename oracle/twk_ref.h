@@ -96,6 +96,10 @@ typedef struct {
   int32_t cross_flip; /* diagnostic, default 0 (the reading used): bit 0
                          negates the cross-caustic correction of created
                          pairs, bit 1 that of destroyed pairs              */
+  double cross_tol;   /* factor (0, 1] on tol for a contour whose samples
+                         include both three- and five-image points (its
+                         limb crosses a caustic), in the stop test and the
+                         tolerance subtraction; default 1 (tol as stated)  */
 } twk_ref_cfg;
 
 /* Defaults as the paper describes its own sampler: tol as given, 64 initial

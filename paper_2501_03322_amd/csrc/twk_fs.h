@@ -174,6 +174,9 @@ enum : uint32_t { IF_CROSS = 1u, IF_ANOMALY = 2u, IF_COUNT = 4u };
 // demoted (16) | demoted + image (17-19) | demoted - image (20-22) |
 // suspect (23).
 enum : uint32_t { M_DEMOTED = 1u << 16, M_SUSPECT = 1u << 23 };
+// Image count of a solved sample, reported by solve_store beside its flags
+// (not stored in the meta word).
+enum : uint32_t { M_SEEN3 = 1u << 24, M_SEEN5 = 1u << 25 };
 
 // Slope detector (Sec. 2.4.2).  A five-image sample whose ghost-pair
 // margin is above SUSPECT (yet below the residual detector's gap) may hold
@@ -222,7 +225,7 @@ __device__ inline uint32_t solve_store(const Lens& L, c64 yc, double rho, double
   }
   const bool suspect = im.n == 5 && im.par == 3u && im.margin > SUSPECT;
   meta_at(m, slot) = (uint32_t)im.n | (im.par << 3) | (im.flags << 8) | (suspect ? M_SUSPECT : 0u);
-  *fl = im.flags | (suspect ? M_SUSPECT : 0u);
+  *fl = im.flags | (suspect ? M_SUSPECT : 0u) | (im.n == 5 ? M_SEEN5 : M_SEEN3);
   return (uint32_t)s64 | ((uint32_t)s32 << 16);
 }
 
@@ -972,11 +975,13 @@ __device__ __attribute__((noinline)) bool slope_pass(const R& m, const Sorted& S
   return changed > 0;
 }
 
-// Relative tolerance actually targeted by the stop test: half the stated one.
-// The error estimate of Sec. 2.5 can fall short of the true error by up to
-// about a factor 2 across caustics (measured against the tight oracle on
-// near-caustic sources), so the stop test aims at tol/2 for the returned
-// magnification to meet tol.
+// Relative tolerance targeted by the stop test of a contour that crosses a
+// caustic (some samples with three images, some with five): half the stated
+// one.  Across a crossing the error estimate of Sec. 2.5 can fall short of
+// the true error by up to about a factor 2 (the cross-caustic interval),
+// measured against the tight oracle.  A contour that crosses no caustic
+// stops at the stated tolerance: there the estimate exceeds the true error
+// by a large factor (more than 4 even just outside a caustic).
 constexpr double TOL_SAFETY = 0.5;
 
 // Running state of one source's contour integration: wave-uniform totals
@@ -986,6 +991,7 @@ struct FsState {
   double Ahi, Alo, A, E;
   uint32_t fl, sw32, sw64, nint;
   bool suspects;  // some sample may hold a misjudged ghost pair
+  uint32_t seen;  // bit 0: a three-image sample seen; bit 1: a five-image one
 };
 
 typedef TWK_LDS_AS int lint;
@@ -1027,6 +1033,7 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
   double Ahi = st.Ahi, Alo = st.Alo, A = st.A, E = st.E;
   uint32_t fl = st.fl, sw32 = st.sw32, sw64 = st.sw64, nint = st.nint;
   bool suspects = st.suspects;
+  uint32_t seen = st.seen;
   bool outgrown = false, paused = false;
   if (N == 0) {
     // the first round starts from the roots at the source centre, parked in
@@ -1044,6 +1051,7 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
   // each, which keeps the kernel small.
   for (;;) {
     bool valid;
+    uint32_t sf = 0u;  // flags and image count of this lane's new sample
     int iv = -1, rank, mcount;
     double thn;
     if (N < n0) {
@@ -1061,7 +1069,8 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
       // error total and total tolerance-subtracted weight (intervals
       // narrower than THETA_FLOOR weigh nothing)
       A = Ahi + Alo;
-      const double avg = tol * fabs(A) / N;
+      const double tol_r = seen == 3u ? TOL_SAFETY * tol : tol;
+      const double avg = tol_r * fabs(A) / N;
       double es = 0.0, ws = 0.0;
       for (int p = lane; p < N; p += WAVE) {
         const double e = S.E[p];
@@ -1069,7 +1078,7 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
         ws += interval_weight(S, p, N, e, avg);
       }
       E = wave_sum(es);
-      if (E <= tol * fabs(A)) break;
+      if (E <= tol_r * fabs(A)) break;
       // outgrowing the LDS copy: the caller continues in global memory
       if (N + NNEW > S.cap && S.cap < METHOD_CAP) {
         outgrown = true;
@@ -1139,7 +1148,6 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
         const double tb = iv + 1 < N ? S.th[ivb] : S.th[ivb] + TWO_PI;
         warm_start(m, (int)S.sl[iv], (int)S.sl[ivb], ta, tb, thn, r);
       }
-      uint32_t sf;
       const uint32_t sw = solve_store<MIXED, R, CONV>(lens, yc, rho, thn, r, m, N + rank, &sf);
       sw64 += sw & 0xffffu;
       sw32 += sw >> 16;
@@ -1147,6 +1155,7 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
       if (sf & M_SUSPECT) suspects = true;
     }
     suspects = __ballot(suspects) != 0;
+    seen |= (__ballot((sf & M_SEEN3) != 0u) ? 1u : 0u) | (__ballot((sf & M_SEEN5) != 0u) ? 2u : 0u);
     lane_sync<Sorted>();
     // merge: old position p moves up by #(new samples in intervals < p);
     // strips from the top so that no unread entry is overwritten
@@ -1232,7 +1241,7 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
       break;
     }
   }
-  st = FsState{N, Ahi, Alo, A, E, fl, sw32, sw64, nint, suspects};
+  st = FsState{N, Ahi, Alo, A, E, fl, sw32, sw64, nint, suspects, seen};
   return outgrown ? FS_OUTGROWN : (paused ? FS_PAUSED : FS_DONE);
 }
 
@@ -1272,10 +1281,10 @@ template <int LCAP, bool MIXED>
 __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem<MIXED>& gm,
                            FsLds<LCAP, MIXED>& L,
                            int lane, int n0) {
-  const double tol = tol_stated * TOL_SAFETY;
+  const double tol = tol_stated;
   const Lens lens = make_lens(T.s, T.q);
   const c64 yc = cz(T.zx - lens.z2, T.zy);
-  FsState st{0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, false};
+  FsState st{0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, false, 0u};
   const SortedL<MIXED> S{(ldouble*)L.th, (lcorr_t<MIXED>*)L.E, (luint16*)L.sl, LCAP};
   const RecL<MIXED> R{(ldouble*)L.root, (lcorr_t<MIXED>*)L.dz, (lcorr_t<MIXED>*)L.w, (ldouble*)L.dA,
                (luint32*)L.meta, LCAP};
@@ -1313,6 +1322,7 @@ struct RoundState {
   int N;
   uint32_t fl;              // OR of the lanes' flags so far
   int suspects;
+  uint32_t seen;            // image counts seen so far (FsState::seen)
   int done;
 };
 
@@ -1323,14 +1333,14 @@ struct RoundState {
 template <bool MIXED, bool CONV = false>
 __device__ bool fs_round_step(const Task& T, double tol_stated, const WaveMem<MIXED>& gm,
                               lint* ivl, int lane, int n0, RoundState* rs, bool fresh, FsOut* o) {
-  const double tol = tol_stated * TOL_SAFETY;
+  const double tol = tol_stated;
   const Lens lens = make_lens(T.s, T.q);
   const c64 yc = cz(T.zx - lens.z2, T.zy);
-  FsState st{0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, false};
+  FsState st{0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, false, 0u};
   double base32 = 0.0, base64 = 0.0, baseint = 0.0;
   if (!fresh) {
     const RoundState r = *rs;
-    st = FsState{r.N, r.Ahi, r.Alo, r.A, r.E, r.fl, 0u, 0u, 0u, r.suspects != 0};
+    st = FsState{r.N, r.Ahi, r.Alo, r.A, r.E, r.fl, 0u, 0u, 0u, r.suspects != 0, r.seen};
     base32 = r.sw32;
     base64 = r.sw64;
     baseint = r.nint;
@@ -1354,6 +1364,7 @@ __device__ bool fs_round_step(const Task& T, double tol_stated, const WaveMem<MI
     r.N = st.N;
     r.fl = out.flags;
     r.suspects = st.suspects ? 1 : 0;
+    r.seen = st.seen;
     r.done = how != FS_PAUSED;
     *rs = r;
   }
