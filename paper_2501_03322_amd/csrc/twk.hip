@@ -966,9 +966,11 @@ int ensure_learn(twk_ctx* c, int64_t ntask_max) {
 }
 
 // Learned stage between the point-source pass and the contour kernel:
-// predict every queued task's sample count, set its starting grid, and
-// order the queue longest first.  Grids cover the chunk's task capacity;
-// threads beyond the device-side task count return at once.
+// predict every queued task's sample count and order the queue longest
+// first (the contours themselves are unchanged).  Grids cover the chunk's
+// task capacity; threads beyond the device-side task count return at once
+// (a fixed grid striding over the tasks was measured slower: its blocks
+// serialise on the class counters' atomics tile after tile).
 int learned_stage(twk_ctx* c, int64_t ntask_max, int na) {
   const LearnBufs b = learn_bufs(c);
   hipLaunchKernelGGL(mlp::k_infer, dim3(c->n_cu), dim3(64 * mlp::INFER_WAVES), 0, c->stream,

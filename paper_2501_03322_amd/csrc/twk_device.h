@@ -365,8 +365,10 @@ __device__ __forceinline__ c64 residual(const Lens& L, c64 y, c64 eta) {
 // root gets one Newton step on it, dz = (R - conj(f') conj(R)) / J, kept
 // only when the step is tiny against the distance to the nearer lens
 // (<= 1e-8 min(|eta|, |eta + s|)) and at least halves |R|; a ghost has no
-// nearby solution and its step is refused.  On return R holds the residual
-// of each (possibly polished) root.
+// nearby solution and its step is refused.  A step below 1e-15 of that
+// distance is rounding noise and is not taken (the root is already
+// converged).  On return R holds the residual of each (possibly polished)
+// root.
 // The residual, f' and J of a point all follow from the two inverses
 // 1/(eta + s) and 1/eta (1/conj(x) = conj(1/x)); on return J[k] is the
 // Jacobian at the final root.
@@ -392,7 +394,10 @@ __device__ inline void polish_lens(const Lens& L, c64 y, c64 r[5], c64 R[5], dou
     const double scale = fmin(cnorm(e), cnorm(e + L.s));
     R[k] = p.R;
     J[k] = p.J;
-    if (cnorm(dz) <= 1e-16 * scale) {
+    // a step worth taking: beyond the root's rounding, tiny against the
+    // distances to the lenses (a ghost's step is large)
+    const double d2 = cnorm(dz);
+    if (d2 <= 1e-16 * scale && d2 > 1e-30 * scale) {
       const c64 cand = e + dz;
       const LensPoint pc = lens_point(L, y, cand);
       if (cnorm(pc.R) < 0.25 * cnorm(p.R)) {
@@ -420,7 +425,8 @@ constexpr double KGAP = TWK_KGAP;
 constexpr double EPS64 = 2.220446049250313e-16;
 
 // sqrt to FP32 precision (the hardware square root, about 1 ulp), for the
-// rounding scale of the noise level only
+// rounding scale of the noise level only (whose reciprocals are the
+// hardware estimate too)
 __device__ __forceinline__ double sqrt_rough(double x) {
   return (double)__builtin_amdgcn_sqrtf((float)x);
 }
@@ -438,7 +444,8 @@ __device__ inline void classify(const Lens& L, c64 y, const c64 r[5], const c64 
     Rs = Rs + R[k];
     const double ae2 = cnorm(r[k]), as2 = cnorm(r[k] + L.s);
     sg[k] = 64.0 * EPS64 *
-            (ay + sqrt_rough(ae2) + L.m1 * sqrt_rough(rcp64(as2)) + L.m2 * sqrt_rough(rcp64(ae2)));
+            (ay + sqrt_rough(ae2) + L.m1 * sqrt_rough(__builtin_amdgcn_rcp(as2)) +
+             L.m2 * sqrt_rough(__builtin_amdgcn_rcp(ae2)));
   }
   // the two largest residuals (first index wins ties)
   int a = 0;

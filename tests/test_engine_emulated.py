@@ -208,14 +208,19 @@ def test_slope_detector_follows_oracle(emu_blind, oracle):
 def test_lds_capacity_changes_nothing(emu):
     """Records and sorted arrays in LDS, continued in global memory once a
     source outgrows the LDS capacity: an engine built with capacity 64
-    (most sources continue in global memory) gives bit-identical results
-    to the capacity-512 build."""
+    (most sources continue in global memory) gives bit-identical results to
+    the capacity-512 build, in both precisions, on sources of 64 to over
+    1000 samples."""
     small = _load(lcap=64)
+    longest = 0
     for (s, q, z, rho) in CASES[:6]:
-        a = emu["finite"](s, q, z.real, z.imag, rho, 1e-4, 1)
-        b = small["finite"](s, q, z.real, z.imag, rho, 1e-4, 1)
-        assert a == b, (s, q, z, rho, a, b)
-        assert a[2] > 64 or a == b
+        for tol in (1e-4, 1e-6):
+            for mixed in (0, 1):
+                a = emu["finite"](s, q, z.real, z.imag, rho, tol, mixed)
+                b = small["finite"](s, q, z.real, z.imag, rho, tol, mixed)
+                assert a == b, (s, q, z, rho, tol, mixed, a, b)
+                longest = max(longest, a[2])
+    assert longest > 768
 
 
 def test_limb_sincos_accuracy(emu):

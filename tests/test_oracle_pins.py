@@ -12,12 +12,13 @@ GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_e
 RNG = np.random.default_rng(12345)
 
 
-def _random_configs(n, logq=(-6, -1), logs=(-0.5, 0.5), box=1.6):
+def _random_configs(n, logq=(-6, -1), logs=(-0.5, 0.5), box=1.6, rng=None):
+    rng = RNG if rng is None else rng
     out = []
     for _ in range(n):
-        s = 10 ** RNG.uniform(*logs)
-        q = 10 ** RNG.uniform(*logq)
-        zeta = RNG.uniform(-box, box) + 1j * RNG.uniform(-box, box)
+        s = 10 ** rng.uniform(*logs)
+        q = 10 ** rng.uniform(*logq)
+        zeta = rng.uniform(-box, box) + 1j * rng.uniform(-box, box)
         out.append((s, q, zeta))
     return out
 
@@ -120,7 +121,12 @@ def test_image_counts_parity_and_newton_census(oracle):
     exactly the solutions of the lens equation, found here independently by
     Newton's method on the lens equation itself from many starts."""
     seen = {3: 0, 5: 0}
-    cfgs = _random_configs(40, logq=(-3, -0.3), box=0.6) + _random_configs(20, logq=(-4, -1), box=1.2)
+    # a generator of its own (the module's shared one depends on which tests
+    # ran before in the same process), seeded so that the draw holds both
+    # image counts (55 sources with three images, 5 with five)
+    rng = np.random.default_rng(22)
+    cfgs = _random_configs(40, logq=(-3, -0.3), box=0.6, rng=rng) + \
+        _random_configs(20, logq=(-4, -1), box=1.2, rng=rng)
     for (s, q, zeta) in cfgs:
         im = oracle.images(s, q, zeta)
         n = im["n"]
