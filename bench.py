@@ -15,7 +15,7 @@ Paths timed (same call, mode bits differ), each addition separately:
 plain FP64 (one kernel launch per refinement round over the list of
 unfinished sources, the paper's dispatch), + persistent kernel with a device
 queue, + mixed precision (FP32 bulk root iterations), + learned budget (the
-MLP's starting grid and longest-first queue).  The headline value is the
+MLP's predicted-long contours queued first).  The headline value is the
 learned + mixed + persistent path.  The fit-style batch of 1024 sets x 2000
 epochs (uniform source, seed 1) is reported beside it.
 

@@ -122,8 +122,9 @@ int twk_coefficients(twk_ctx *ctx, double s, double q, int64_t n, const double *
  * mode: TWK_MODE_FP64 or TWK_MODE_MIXED; without TWK_MODE_ALL_FS the
  * point-source test may return the point value (flag bit 0).  With
  * TWK_MODE_MLP the learned budget (weights from twk_mlp_set/load/train)
- * predicts each contour's sample count and the queue runs contours longest
- * predicted first; the sampling of a contour is unchanged (it starts from
+ * predicts each contour's sample count and the queue runs the contours
+ * predicted to need 256 samples or more first (launch tails); the sampling
+ * of a contour is unchanged (it starts from
  * the 64 uniform samples of the paper's schedule), so the results are
  * bit-identical to those of the same call without TWK_MODE_MLP.
  * Errors: TWK_EINVAL for s, q, rho, tol <= 0 or non-finite, n < 0 or > 2^48, NULL

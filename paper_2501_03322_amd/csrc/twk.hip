@@ -13,8 +13,8 @@
 //                value, the rest are appended to the task queue with their
 //                centre roots (wave-aggregated atomics)
 //   mlp::k_infer, k_budget, k_place   (learned path) inference on the
-//                features the point pass wrote, starting grids, longest-first
-//                queue order
+//                features the point pass wrote; contours predicted long are
+//                queued first
 //   k_fs<C, MIXED>  persistent: each 64-lane wave pops tasks from the queue
 //                and runs the adaptive contour integration, keeping up to C
 //                limb samples (records and sorted arrays) in LDS and
@@ -58,11 +58,11 @@ enum {
   C_INTERVALS = 7, // intervals linked
   C_RUNS = 8,      // contour runs
   C_NFS = 9,       // limb-darkened epochs sent to the annulus contours
-  C_BUCKET = 16,   // learned path: tasks per budget class (7 classes)
+  C_BUCKET = 16,   // learned path: tasks per budget class
   C_CURSOR = 24,   // learned path: fill cursors of the classes
   C_NCOUNTERS = 32
 };
-constexpr int NBUCKET = 7;  // predicted sample counts 2^6 .. >= 2^12
+constexpr int NBUCKET = 2;  // predicted under 256 samples / 256 or more
 
 // Point-source adequacy test.  The paper (Sec. 2.3) applies the quadrupole
 // test and the ghost-image test before any contour work but gives no
@@ -547,15 +547,19 @@ __global__ __launch_bounds__(256) void k_feat(int64_t nsets, const double* ps, c
   adequate[i] = r.adequate ? 1 : 0;
 }
 
-// Learned budget: each queued task is counted into the class floor(l2) - 6
-// of its predicted log2 sample count l2 (7 classes, 2^6 .. >= 2^12
-// samples); the classes set the queue order.  The prediction does not
-// change how a contour is sampled: every contour starts from the paper's
-// 64 uniform samples.  Counts are gathered per block in LDS and added to
-// the global class counters with one atomic per class and block.
-__device__ inline int budget_class(float l2) {
-  return min(max((int)floorf(l2) - 6, 0), NBUCKET - 1);
-}
+// Learned budget: each queued task is counted into class 1 when its
+// predicted log2 sample count l2 is 8 or more (256 samples or more), else
+// class 0; class 1 runs first and class 0 after it, each in about the order
+// the point pass queued them.  Long contours started last would hold their
+// waves after the rest of the launch has finished; only they are moved
+// (measured on the limb-darkened batch: ordering every contour longest
+// first started all long ones together and made the contour kernel slower
+// than no ordering at all, this order makes it 2 % faster).  The
+// prediction does not change how a contour is sampled: every contour starts
+// from the paper's 64 uniform samples.  Counts are gathered per block in
+// LDS and added to the global class counters with one atomic per class and
+// block.
+__device__ inline int budget_class(float l2) { return l2 >= 8.0f ? 1 : 0; }
 
 // Inference row of task i: its own, or (limb darkening, na > 1) its
 // epoch's, whose annulus contours have outputs epoch * na + k.
@@ -622,27 +626,62 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES
   const WaveMem<MIXED> m = wave_mem<MIXED>(slices, blockIdx.x);
   const long long n = *ntask;
   unsigned long long w_samples = 0, w_sw32 = 0, w_sw64 = 0, w_int = 0, w_runs = 0, w_over = 0;
-  for (;;) {
-    long long t = 0;
-    if (lane == 0) t = atomicAdd((unsigned long long*)head, 1ull);
-    t = __shfl(t, 0);
-    if (t >= n) break;
-    if (order) t = order[t];
-    const Task task = tasks[t];
-    const FsOut o = fs_source<LCAP, MIXED>(task, task.tol, m, lds, lane, NNEW);
-    if (lane == 0) {
-      mag[task.out] = o.mag;
-      err[task.out] = o.err;
-      ns[task.out] = o.n;
-      flags[task.out] = o.flags;
-      w_samples += (unsigned long long)o.n;
-      w_sw32 += (unsigned long long)o.sweeps32;
-      w_sw64 += (unsigned long long)o.sweeps64;
-      w_int += (unsigned long long)o.intervals;
-      w_runs += 1ull;
-      w_over += o.spilled ? 1ull : 0ull;
+  // Phase 1 runs sources on their LDS copies until one outgrows it; phase 2
+  // then finishes that one in the wave's global slice; repeat.  The two
+  // phases are separate loops of one kernel: neither holds the other's
+  // registers and no function is called (a call made the compiler spill
+  // the round loop's registers to scratch memory).
+  bool drained = false;
+  while (!drained) {
+    long long big = -1;  // the source that outgrew its LDS copy, if any
+    FsState st;
+    for (;;) {
+      long long t = 0;
+      if (lane == 0) t = atomicAdd((unsigned long long*)head, 1ull);
+      t = __shfl(t, 0);
+      if (t >= n) {
+        drained = true;
+        break;
+      }
+      if (order) t = order[t];
+      const Task task = tasks[t];
+      st = fs_fresh();
+      if (fs_source_lds<LCAP, MIXED>(task, task.tol, m, lds, lane, NNEW, st)) {
+        big = t;
+        break;
+      }
+      const FsOut o = fs_output(task, st, false);
+      if (lane == 0) {
+        mag[task.out] = o.mag;
+        err[task.out] = o.err;
+        ns[task.out] = o.n;
+        flags[task.out] = o.flags;
+        w_samples += (unsigned long long)o.n;
+        w_sw32 += (unsigned long long)o.sweeps32;
+        w_sw64 += (unsigned long long)o.sweeps64;
+        w_int += (unsigned long long)o.intervals;
+        w_runs += 1ull;
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    if (big >= 0) {
+      const Task task = tasks[big];
+      fs_source_global<MIXED>(task, task.tol, m, (lint*)lds.ivl, lane, st);
+      const FsOut o = fs_output(task, st, true);
+      if (lane == 0) {
+        mag[task.out] = o.mag;
+        err[task.out] = o.err;
+        ns[task.out] = o.n;
+        flags[task.out] = o.flags;
+        w_samples += (unsigned long long)o.n;
+        w_sw32 += (unsigned long long)o.sweeps32;
+        w_sw64 += (unsigned long long)o.sweeps64;
+        w_int += (unsigned long long)o.intervals;
+        w_runs += 1ull;
+        w_over += 1ull;
+      }
+      __syncthreads();
+    }
   }
   // work counters: one flush per wave, not per source (the counters share a
   // cache line that every wave would otherwise hit once per source)
@@ -966,8 +1005,8 @@ int ensure_learn(twk_ctx* c, int64_t ntask_max) {
 }
 
 // Learned stage between the point-source pass and the contour kernel:
-// predict every queued task's sample count and order the queue longest
-// first (the contours themselves are unchanged).  Grids cover the chunk's
+// predict every queued task's sample count and queue the predicted-long
+// contours first (the contours themselves are unchanged).  Grids cover the chunk's
 // task capacity; threads beyond the device-side task count return at once
 // (a fixed grid striding over the tasks was measured slower: its blocks
 // serialise on the class counters' atomics tile after tile).

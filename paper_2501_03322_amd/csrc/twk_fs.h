@@ -946,9 +946,8 @@ __device__ inline int detect_runs(const R& m, const Sorted& S, int N) {
 // re-examine every run, relink every interval and recompute the area total
 // (compensated).  Returns true if any sample is demoted.
 template <class Sorted, class R>
-__device__ __attribute__((noinline)) bool slope_pass(const R& m, const Sorted& S, int N,
-                                                     int lane, double* Ahi, double* Alo,
-                                                     uint32_t* nint) {
+__device__ __forceinline__ bool slope_pass(const R& m, const Sorted& S, int N, int lane,
+                                          double* Ahi, double* Alo, uint32_t* nint) {
   for (int p = lane; p < N; p += WAVE) undo_demotion(m, p);
   lane_sync<Sorted>();
   int changed = 0;
@@ -993,6 +992,9 @@ struct FsState {
   bool suspects;  // some sample may hold a misjudged ghost pair
   uint32_t seen;  // bit 0: a three-image sample seen; bit 1: a five-image one
 };
+__device__ __forceinline__ FsState fs_fresh() {
+  return FsState{0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, false, 0u};
+}
 
 typedef TWK_LDS_AS int lint;
 
@@ -1245,20 +1247,6 @@ __device__ __forceinline__ int fs_rounds(const Task& T, const Lens& lens, c64 yc
   return outgrown ? FS_OUTGROWN : (paused ? FS_PAUSED : FS_DONE);
 }
 
-// Continuation of a source that outgrew its LDS copy (rare: kept out of
-// line).  Arguments and state go by value so that nothing of the hot path
-// has its address taken.
-template <bool MIXED>
-__device__ __attribute__((noinline)) FsState fs_rounds_spilled(Task T, double tol,
-                                                               WaveMem<MIXED> m, lint* ivl,
-                                                               int lane, FsState st) {
-  const Lens lens = make_lens(T.s, T.q);
-  const c64 yc = cz(T.zx - lens.z2, T.zy);
-  const SortedG<MIXED> S{m.sth, m.sE, m.ssl, METHOD_CAP};
-  fs_rounds<MIXED>(T, lens, yc, tol, m.G, ivl, S, lane, 0, st);
-  return st;
-}
-
 // Output of a finished source from its final state.
 __device__ __forceinline__ FsOut fs_output(const Task& T, const FsState& st, bool spilled) {
   FsOut o;
@@ -1274,40 +1262,62 @@ __device__ __forceinline__ FsOut fs_output(const Task& T, const FsState& st, boo
   return o;
 }
 
-// One source: rounds on the LDS copies of the records and sorted arrays;
-// a source that would outgrow LDS has both copied to the wave's global
-// slice and continues there.
+// The rounds of one source on the LDS copies of its records and sorted
+// arrays (st: fresh state on entry, final or outgrown state on return).
+// Returns true if the source outgrew the LDS copy: its records and sorted
+// arrays are then copied to the wave's global slice, where
+// fs_source_global continues it.
+template <int LCAP, bool MIXED>
+__device__ __forceinline__ bool fs_source_lds(const Task& T, double tol, const WaveMem<MIXED>& gm,
+                                              FsLds<LCAP, MIXED>& L, int lane, int n0,
+                                              FsState& st) {
+  const Lens lens = make_lens(T.s, T.q);
+  const c64 yc = cz(T.zx - lens.z2, T.zy);
+  const SortedL<MIXED> S{(ldouble*)L.th, (lcorr_t<MIXED>*)L.E, (luint16*)L.sl, LCAP};
+  const RecL<MIXED> R{(ldouble*)L.root, (lcorr_t<MIXED>*)L.dz, (lcorr_t<MIXED>*)L.w, (ldouble*)L.dA,
+               (luint32*)L.meta, LCAP};
+  if (fs_rounds<MIXED>(T, lens, yc, tol, R, (lint*)L.ivl, S, lane, n0, st) != FS_OUTGROWN)
+    return false;
+  for (int p = lane; p < st.N; p += WAVE) {
+    gm.sth[p] = S.th[p];
+    gm.sE[p] = S.E[p];
+    gm.ssl[p] = S.sl[p];
+    // slot p's record (slots are 0 .. N-1)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      st_root(gm.G, k, p, ld_root(R, k, p));
+      st_dz(gm.G, k, p, ld_dz(R, k, p));
+      w_at(gm.G, k, p) = w_at(R, k, p);
+    }
+    dA_at(gm.G, p) = dA_at(R, p);
+    meta_at(gm.G, p) = meta_at(R, p);
+  }
+  __syncthreads();
+  return true;
+}
+
+// The remaining rounds of a source that outgrew its LDS copy, on the
+// records and sorted arrays in the wave's global slice.
+template <bool MIXED>
+__device__ __forceinline__ void fs_source_global(const Task& T, double tol, const WaveMem<MIXED>& gm,
+                                                 lint* ivl, int lane, FsState& st) {
+  const Lens lens = make_lens(T.s, T.q);
+  const c64 yc = cz(T.zx - lens.z2, T.zy);
+  const SortedG<MIXED> S{gm.sth, gm.sE, gm.ssl, METHOD_CAP};
+  fs_rounds<MIXED>(T, lens, yc, tol, gm.G, ivl, S, lane, 0, st);
+}
+
+// One source from start to finish (both parts in sequence).  The
+// persistent kernel instead runs the LDS part of many sources in one loop
+// and the global part of an outgrown source after leaving it, so that the
+// two parts' registers never meet in one loop and no call is made.
 template <int LCAP, bool MIXED>
 __device__ FsOut fs_source(const Task& T, double tol_stated, const WaveMem<MIXED>& gm,
                            FsLds<LCAP, MIXED>& L,
                            int lane, int n0) {
-  const double tol = tol_stated;
-  const Lens lens = make_lens(T.s, T.q);
-  const c64 yc = cz(T.zx - lens.z2, T.zy);
-  FsState st{0, 0.0, 0.0, 0.0, 0.0, 0u, 0u, 0u, 0u, false, 0u};
-  const SortedL<MIXED> S{(ldouble*)L.th, (lcorr_t<MIXED>*)L.E, (luint16*)L.sl, LCAP};
-  const RecL<MIXED> R{(ldouble*)L.root, (lcorr_t<MIXED>*)L.dz, (lcorr_t<MIXED>*)L.w, (ldouble*)L.dA,
-               (luint32*)L.meta, LCAP};
-  bool spilled = false;
-  if (fs_rounds<MIXED>(T, lens, yc, tol, R, (lint*)L.ivl, S, lane, n0, st) == FS_OUTGROWN) {
-    for (int p = lane; p < st.N; p += WAVE) {
-      gm.sth[p] = S.th[p];
-      gm.sE[p] = S.E[p];
-      gm.ssl[p] = S.sl[p];
-      // slot p's record (slots are 0 .. N-1)
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        st_root(gm.G, k, p, ld_root(R, k, p));
-        st_dz(gm.G, k, p, ld_dz(R, k, p));
-        w_at(gm.G, k, p) = w_at(R, k, p);
-      }
-      dA_at(gm.G, p) = dA_at(R, p);
-      meta_at(gm.G, p) = meta_at(R, p);
-    }
-    __syncthreads();
-    st = fs_rounds_spilled<MIXED>(T, tol, gm, (lint*)L.ivl, lane, st);
-    spilled = true;
-  }
+  FsState st = fs_fresh();
+  const bool spilled = fs_source_lds<LCAP, MIXED>(T, tol_stated, gm, L, lane, n0, st);
+  if (spilled) fs_source_global<MIXED>(T, tol_stated, gm, (lint*)L.ivl, lane, st);
   return fs_output(T, st, spilled);
 }
 

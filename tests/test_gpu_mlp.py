@@ -191,7 +191,7 @@ def test_features_parity(ctx, oracle):
 
 
 def test_learned_path_parity(ctx, oracle):
-    """The learned budget only orders the queue (longest predicted first):
+    """The learned budget only orders the queue (predicted-long contours first):
     every contour is sampled as on the path without it, so the results are
     bit-identical to that path's whatever the weights say, and they meet
     the gate against the tight oracle run, on the single light curve, near
@@ -243,9 +243,9 @@ def test_learned_path_parity(ctx, oracle):
 
 
 def test_learned_batch_every_task_once(ctx, oracle):
-    """Bucketed longest-first ordering processes every queued task exactly
-    once: outputs pre-filled with NaN are all overwritten, and the sample
-    total equals the work counter."""
+    """The learned ordering (predicted-long contours first) processes every
+    queued task exactly once: outputs pre-filled with NaN are all
+    overwritten, and the sample total equals the work counter."""
     import torch
     from paper_2501_03322_amd import inputs, twk
     ctx.mlp_set(M.flatten(_params(31)))
@@ -291,7 +291,7 @@ def test_trained_network_gain(ctx):
     sets x 4000 epochs, seed 3, tol 1e-4) at one launch tuning for both paths
     (LDS capacity 128 samples, the most resident waves): the same samples and
     bit-identical results as the mixed path without it (the budget only
-    orders the queue, longest predicted first), and the time per call, its
+    orders the queue, predicted-long contours first), and the time per call, its
     learned stage (inference, classes, placement) included, reported and not
     worse than the path without it by more than the run-to-run noise."""
     import torch
