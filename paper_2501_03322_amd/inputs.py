@@ -84,6 +84,20 @@ def large_ld_curves(nsets=16384, nepochs=8000, seed=4, n_annuli=10):
     return LightCurveSet(s, q, u0, alpha, rho, np.linspace(-1.5, 1.5, nepochs), gamma, n_annuli)
 
 
+def wide_training_curves(nsets=1000, nepochs=2000, seed=5):
+    """Training batch over the high-cadence batch's parameter ranges: s, q,
+    alpha, u0, rho drawn in that order with log10 q ~ U[-6,-1], log10 rho ~
+    U[-4,-2.5] and s, alpha, u0 as in the batch; uniform source (the learned
+    features of a limb-darkened epoch are those of its outer disk)."""
+    rng = np.random.default_rng(seed)
+    s = 10.0 ** rng.uniform(-0.5, 0.5, nsets)
+    q = 10.0 ** rng.uniform(-6.0, -1.0, nsets)
+    alpha = rng.uniform(0.0, 2.0 * np.pi, nsets)
+    u0 = rng.uniform(-0.1, 0.1, nsets)
+    rho = 10.0 ** rng.uniform(-4.0, -2.5, nsets)
+    return LightCurveSet(s, q, u0, alpha, rho, np.linspace(-1.5, 1.5, nepochs))
+
+
 # Magnification map: s=0.9, q=1e-4, rho=1e-3 on a 2048 x 2048 grid over a
 # 0.2 x 0.2 box centred on the central caustic.  The centre is the midpoint
 # of the central caustic's x-extent in the centre-of-mass frame, computed

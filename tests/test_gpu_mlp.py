@@ -266,7 +266,7 @@ def test_learned_batch_every_task_once(ctx, oracle):
 
 
 def test_trained_weights_file(ctx, oracle):
-    """The committed weights (trained on the seed-2 training set) load and
+    """The committed weights (trained on the seed-2 and seed-5 training sets) load and
     give sample-count predictions that correlate with the plain path's."""
     import torch
     from paper_2501_03322_amd import inputs, twk
