@@ -100,24 +100,67 @@ def test_tuning_does_not_change_results(lc, cap):
     from paper_2501_03322_amd import twk
     c, args = lc
     ctx = twk.Context(0)
-    ref = [t.clone() for t in _run(ctx, args, twk.MODE_MIXED)]
-    t0 = ctx.get_tuning()
-    for frac in (0.25, 1.0):
-        ctx.set_tuning(lds_cap=cap, waves_per_cu=1)
-        mx = 1
-        # largest accepted grid for this capacity
-        for w in range(2, 33):
-            try:
-                ctx.set_tuning(lds_cap=cap, waves_per_cu=w)
-                mx = w
-            except twk.TwkError:
-                break
-        w = max(1, int(mx * frac))
-        ctx.set_tuning(lds_cap=cap, waves_per_cu=w)
-        _log(f"cap {cap}: waves per CU {w} of {mx}")
-        got = _run(ctx, args, twk.MODE_MIXED)
-        for a, b in zip(got, ref):
-            assert torch.equal(a, b), (cap, w)
+    for mode in (twk.MODE_MIXED, twk.MODE_FP64):
+        ctx.set_tuning(lds_cap=128, waves_per_cu=1)
+        ref = [t.clone() for t in _run(ctx, args, mode)]
+        for frac in (0.25, 1.0):
+            ctx.set_tuning(lds_cap=cap, waves_per_cu=1)
+            mx = 1
+            # largest accepted grid for this capacity
+            for w in range(2, 33):
+                try:
+                    ctx.set_tuning(lds_cap=cap, waves_per_cu=w)
+                    mx = w
+                except twk.TwkError:
+                    break
+            w = max(1, int(mx * frac))
+            ctx.set_tuning(lds_cap=cap, waves_per_cu=w)
+            _log(f"mode {mode}, cap {cap}: waves per CU {w} of {mx}")
+            got = _run(ctx, args, mode)
+            for a, b in zip(got, ref):
+                assert torch.equal(a, b), (mode, cap, w)
+    ctx.close()
+
+
+def test_long_contours_across_capacities(oracle):
+    """Sources near caustics at a tight tolerance (hundreds to thousands of
+    limb samples: nearly every contour outgrows the LDS copy and is finished
+    in global memory by the persistent kernel's second phase): identical
+    results at LDS capacities 64, 128 and 256, in both precisions, and
+    within 1e-4 of the oracle on a sample of them."""
+    import torch
+    from paper_2501_03322_amd import twk
+    import pins
+    rng = np.random.default_rng(9)
+    s, q, rho = 1.0, 1e-3, 1e-3
+    ca = pins.caustic(s, q, 2048)
+    z = ca[rng.integers(0, ca.size, 3000)] + rho * rng.uniform(0, 1.5, 3000) * np.exp(
+        2j * np.pi * rng.uniform(0, 1, 3000))
+    dev = torch.device("cuda", 0)
+    zx = torch.as_tensor(z.real, device=dev)
+    zy = torch.as_tensor(z.imag, device=dev)
+    ctx = twk.Context(0)
+    for mode in (twk.MODE_MIXED, twk.MODE_FP64):
+        ref = None
+        for cap in (64, 128, 256):
+            ctx.set_tuning(lds_cap=cap, waves_per_cu=1)
+            out = ctx.finite_mag(s, q, zx, zy, rho, 1e-6, mode | twk.MODE_ALL_FS)
+            ctx.sync()
+            st = ctx.stats()
+            _log(f"mode {mode}, cap {cap}: {st['fs_tasks']} contours, {st['spilled']} finished in "
+                 f"global memory, {st['samples']} samples")
+            if cap == 64:
+                assert st["spilled"] > 0.9 * st["fs_tasks"]
+            if ref is None:
+                ref = [t.clone() for t in out]
+            else:
+                for a, b in zip(out, ref):
+                    assert torch.equal(a, b), (mode, cap)
+        pick = rng.choice(z.size, 12, replace=False)
+        mag = ref[0].cpu().numpy()[pick]
+        rm = oracle.finite_mag(s, q, z.real[pick], z.imag[pick], rho, oracle.TIGHT_TOL,
+                               oracle.tight_cfg())[0]
+        assert np.abs(mag / rm - 1).max() <= 1e-4, (mode, np.abs(mag / rm - 1).max())
     ctx.close()
 
 
