@@ -120,13 +120,16 @@ int twk_coefficients(twk_ctx *ctx, double s, double q, int64_t n, const double *
  * Outputs (device, length n): mag = area/(pi rho^2); err = error estimate
  * in the same units; n_samples = limb samples used; flags.
  * mode: TWK_MODE_FP64 or TWK_MODE_MIXED; without TWK_MODE_ALL_FS the
- * point-source test may return the point value (flag bit 0).  With
- * TWK_MODE_MLP the learned budget (weights from twk_mlp_set/load/train)
- * predicts each contour's sample count and the queue runs the contours
- * predicted to need 256 samples or more first (launch tails); the sampling
- * of a contour is unchanged (it starts from
- * the 64 uniform samples of the paper's schedule), so the results are
- * bit-identical to those of the same call without TWK_MODE_MLP.
+ * point-source test may return the point value (flag bit 0).  The
+ * persistent contour kernel takes the queued contours in a dispersed order
+ * (a golden-ratio stride over the queue, a limb-darkened epoch's annuli
+ * together) rather than in source order.  With TWK_MODE_MLP the learned
+ * budget (weights from twk_mlp_set/load/train) predicts each contour's
+ * sample count and the queue runs the contours predicted to need 256
+ * samples or more first (launch tails), each class dispersed; the sampling
+ * of a contour is unchanged (it starts from the 64 uniform samples of the
+ * paper's schedule), so the results are bit-identical to those of the same
+ * call without TWK_MODE_MLP.
  * Errors: TWK_EINVAL for s, q, rho, tol <= 0 or non-finite, n < 0 or > 2^48, NULL
  * pointers or unknown mode bits; TWK_ENOMLP for TWK_MODE_MLP without
  * weights; TWK_ENOMEM / TWK_EDEVICE. */
@@ -157,8 +160,9 @@ int twk_finite_mag_each(twk_ctx *ctx, int64_t n, const double *s, const double *
  * twk_finite_mag without any allocation.  Same arguments, results and
  * errors as twk_finite_mag, bit-identical results, for modes TWK_MODE_FP64
  * or TWK_MODE_MIXED, optionally with TWK_MODE_ALL_FS.  Its scratch (work
- * counters, the task queue and the global slices of the persistent waves)
- * is a fixed device array of 129 MB compiled into the library, of which
+ * counters, the queue order, the task queue and the global slices of the
+ * persistent waves)
+ * is a fixed device array of 130 MB compiled into the library, of which
  * each device holds one copy until the process ends; its address on a
  * device is looked up when the first context is created there.  Limits:
  * n <= 65536 sources per call (TWK_EINVAL above), at most 128 persistent

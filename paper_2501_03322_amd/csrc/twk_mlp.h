@@ -116,14 +116,22 @@ __device__ inline void hidden(__bf16 (*act)[ACT_LD], const bf16x8* __restrict__ 
 // weights sit in LDS for the whole block, activations never leave LDS.
 // feat: [n x 8] float32 (raw features); out: [n x 2] float32; the row count
 // is n, or *n_dev when given (a device-side count of queued tasks).
+// n_long (optional): the rows whose first output is at least long_l2 are
+// counted, each as `weight` tasks, into *n_long (one atomic per block), and
+// per 32-row tile (rows, unweighted) into tile_long[tile].
 __global__ __launch_bounds__(64 * INFER_WAVES) void k_infer(const float* __restrict__ P,
                                                              const bf16x8* __restrict__ frag,
                                                              int64_t n, const long long* __restrict__ n_dev,
                                                              const float* __restrict__ feat,
-                                                             float* __restrict__ out) {
+                                                             float* __restrict__ out,
+                                                             long long* __restrict__ n_long,
+                                                             float long_l2, int weight,
+                                                             int32_t* __restrict__ tile_long) {
   __shared__ bf16x8 w[NFRAG * 64];
   __shared__ __bf16 act[INFER_WAVES][32][ACT_LD];
   __shared__ float pb[3 * HID + NO + 2 * NF];
+  __shared__ unsigned block_long;
+  if (threadIdx.x == 0) block_long = 0u;
   for (int i = threadIdx.x; i < NFRAG * 64; i += blockDim.x) w[i] = frag[i];
   for (int i = threadIdx.x; i < HID; i += blockDim.x) {
     pb[i] = P[OFF_B0 + i];
@@ -138,6 +146,7 @@ __global__ __launch_bounds__(64 * INFER_WAVES) void k_infer(const float* __restr
   const float* mean = &pb[3 * HID + NO];
   const float* sd = mean + NF;
   const int64_t ntile = (n + 31) / 32;
+  unsigned nl = 0u;
   for (int64_t t = (int64_t)blockIdx.x * INFER_WAVES + wave; t < ntile;
        t += (int64_t)gridDim.x * INFER_WAVES) {
     const int64_t r0 = t * 32;
@@ -167,13 +176,29 @@ __global__ __launch_bounds__(64 * INFER_WAVES) void k_infer(const float* __restr
       o = mma(x, w[(FRAG_L3 + ks) * 64 + lane], o);
     }
     const int col = lane & 31;
+    unsigned tl = 0u;
     if (col < NO) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t row = r0 + d_row(lane, r);
-        if (row < n) out[row * NO + col] = o[r] + pb[3 * HID + col];
+        if (row < n) {
+          const float v = o[r] + pb[3 * HID + col];
+          out[row * NO + col] = v;
+          tl += (col == 0 && v >= long_l2) ? 1u : 0u;
+        }
       }
     }
+    nl += tl;
+    if (tile_long) {
+      tl += __shfl_down(tl, 32);
+      if (lane == 0) tile_long[t] = (int32_t)tl;
+    }
+  }
+  if (n_long) {
+    if (nl) atomicAdd(&block_long, nl);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_long)
+      atomicAdd((unsigned long long*)n_long, (unsigned long long)block_long * (unsigned)weight);
   }
 }
 

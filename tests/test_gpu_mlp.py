@@ -265,6 +265,42 @@ def test_learned_batch_every_task_once(ctx, oracle):
     assert st["samples"] == int(ns.sum())
 
 
+def test_learned_limb_darkened_every_task_once(ctx):
+    """Limb darkening on the learned path: each inference row is an epoch and
+    places its ten annulus contours together.  On 1000 sets x 8000 epochs
+    (two chunks of the task queue), with the predictions biased to lie
+    around the long-class threshold (log2 = 8), the outputs pre-filled with NaN are all
+    overwritten, the work counters equal those of the mixed path without
+    the budget, and every output is bit-identical to that path's."""
+    import torch
+    from paper_2501_03322_amd import inputs, twk
+    p = _params(41)
+    p["b3"][0] = 8.0
+    ctx.mlp_set(M.flatten(p))
+    c = inputs.large_ld_curves().subset(np.arange(1000))
+    dev = torch.device("cuda", 0)
+    args = [torch.as_tensor(a, device=dev) for a in (c.s, c.q, c.u0, c.alpha, c.rho, c.tau)]
+    g = torch.as_tensor(c.gamma, device=dev)
+    n = c.nsets * c.nepochs
+    out = ctx.alloc_out(n)
+    out[0].fill_(float("nan"))
+    out[2].fill_(-1)
+    _log("learned limb-darkened batch 1000 x 8000 x 10")
+    ctx.lightcurves(*args, 1e-4, twk.MODE_MLP | twk.MODE_MIXED, gamma=g, n_annuli=10, out=out)
+    ctx.sync()
+    st_l = ctx.stats()
+    got = [t.clone() for t in out]
+    ref = ctx.lightcurves(*args, 1e-4, twk.MODE_MIXED, gamma=g, n_annuli=10)
+    ctx.sync()
+    st_p = ctx.stats()
+    _log(f"  stats learned {st_l}, plain {st_p}")
+    assert torch.isfinite(got[0]).all() and bool((got[2] >= 0).all())
+    assert all(torch.equal(a, b) for a, b in zip(got, ref))
+    fl = got[3].cpu().numpy()
+    assert st_l["fs_tasks"] == 10 * int(np.sum((fl & 1) == 0)) == st_p["fs_tasks"]
+    assert st_l["samples"] == int(got[2].sum()) == st_p["samples"]
+
+
 def test_trained_weights_file(ctx, oracle):
     """The committed weights (trained on the seed-2 and seed-5 training sets) load and
     give sample-count predictions that correlate with the plain path's."""
