@@ -187,7 +187,7 @@ int twk_finite_mag_noalloc(twk_ctx *ctx, double s, double q, int64_t n, const do
  * Outputs (device, length nsets*nepochs, set-major): mag, err, n_samples
  * (summed over annuli), flags.  Point-source-adequate epochs are answered
  * by the point value; all others by contour integration in one persistent
- * launch per chunk of parameter sets (a chunk holds at most 2^26 contour
+ * launch per chunk of parameter sets (a chunk holds at most 2^28 contour
  * tasks) fed by a device work queue.  Queued on the context's stream without
  * waiting for it (except when the context's buffers must grow).
  * Errors: TWK_EINVAL for nsets or nepochs < 0, nepochs above 2^30,
@@ -217,7 +217,7 @@ int twk_mag_map(twk_ctx *ctx, double s, double q, double rho, double xc, double 
  * returned results, out[3] = persistent waves launched, out[4] = FP32 root
  * sweeps, out[5] = FP64 root sweeps (one sweep updates all five roots of one
  * limb point), out[6] = intervals linked, out[7] = contour-kernel launches
- * of the call (one per chunk; a call is split into chunks of at most 2^26
+ * of the call (one per chunk; a call is split into chunks of at most 2^28
  * contour tasks).  Synchronises the context's stream. */
 int twk_last_stats(twk_ctx *ctx, int64_t *out8);
 

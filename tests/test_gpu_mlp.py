@@ -267,7 +267,7 @@ def test_learned_batch_every_task_once(ctx, oracle):
 
 def test_learned_limb_darkened_every_task_once(ctx):
     """Limb darkening on the learned path: each inference row is an epoch and
-    places its ten annulus contours together.  On 1000 sets x 8000 epochs
+    places its ten annulus contours together.  On 4000 sets x 8000 epochs
     (two chunks of the task queue), with the predictions biased to lie
     around the long-class threshold (log2 = 8), the outputs pre-filled with NaN are all
     overwritten, the work counters equal those of the mixed path without
@@ -277,7 +277,7 @@ def test_learned_limb_darkened_every_task_once(ctx):
     p = _params(41)
     p["b3"][0] = 8.0
     ctx.mlp_set(M.flatten(p))
-    c = inputs.large_ld_curves().subset(np.arange(1000))
+    c = inputs.large_ld_curves().subset(np.arange(4000))
     dev = torch.device("cuda", 0)
     args = [torch.as_tensor(a, device=dev) for a in (c.s, c.q, c.u0, c.alpha, c.rho, c.tau)]
     g = torch.as_tensor(c.gamma, device=dev)
@@ -285,7 +285,7 @@ def test_learned_limb_darkened_every_task_once(ctx):
     out = ctx.alloc_out(n)
     out[0].fill_(float("nan"))
     out[2].fill_(-1)
-    _log("learned limb-darkened batch 1000 x 8000 x 10")
+    _log("learned limb-darkened batch 4000 x 8000 x 10")
     ctx.lightcurves(*args, 1e-4, twk.MODE_MLP | twk.MODE_MIXED, gamma=g, n_annuli=10, out=out)
     ctx.sync()
     st_l = ctx.stats()
