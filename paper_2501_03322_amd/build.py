@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtwk.so")
 SRC = [os.path.join(HERE, "csrc", "twk.hip")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("twk_device.h", "twk_fs.h", "twk_mlp.h", "twk_gelu.h")] + \
+HEADERS = [os.path.join(HERE, "csrc", f)
+           for f in ("twk_device.h", "twk_fs.h", "twk_mlp.h", "twk_gelu.h", "twk_queue.h")] + \
     [os.path.join(ROOT, "include", "twk.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -39,6 +39,7 @@
 #include "twk_device.h"
 #include "twk_fs.h"
 #include "twk_mlp.h"
+#include "twk_queue.h"
 
 using namespace twk;
 
@@ -581,36 +582,7 @@ static_assert(NBUCKET == 2, "two budget classes: the inference kernel counts cla
 // waves resident at any time hold a representative mix of contours.
 // Measured on the limb-darkened batch: the contour kernel 6 % faster than
 // in source order (annuli dispersed one by one: 5 %).
-// golden_stride: g and its inverse mod N (g = 1 for N <= 2).
-__device__ inline long long gcd64(long long a, long long b) {
-  while (b) {
-    const long long t = a % b;
-    a = b;
-    b = t;
-  }
-  return a;
-}
-
-__device__ inline void golden_stride(long long N, long long* g, long long* ginv) {
-  *g = 1;
-  *ginv = 1;
-  if (N <= 2) return;
-  long long s = (long long)((double)N * 0.6180339887498949);
-  for (int k = 0; k < 4096 && gcd64(s, N) != 1; ++k) s = s + 1 < N ? s + 1 : 1;
-  if (gcd64(s, N) != 1) return;
-  // inverse by the extended Euclidean algorithm: x s = 1 (mod N)
-  long long r0 = N, r1 = s, x0 = 0, x1 = 1;
-  while (r1) {
-    const long long qt = r0 / r1, r2 = r0 - qt * r1, x2 = x0 - qt * x1;
-    r0 = r1;
-    r1 = r2;
-    x0 = x1;
-    x1 = x2;
-  }
-  *g = s;
-  *ginv = x0 < 0 ? x0 + N : x0;
-}
-
+// The stride, its inverse and the position map are in twk_queue.h.
 #ifndef TWK_DISPERSE_GROUPED
 #define TWK_DISPERSE_GROUPED 1
 #endif
@@ -641,11 +613,8 @@ __global__ __launch_bounds__(256) void k_disperse(const long long* cnt, int32_t*
   const unsigned long long g = (unsigned long long)cnt[C_DSTRIDE];
   const long long grp = cnt[C_DGROUP], ng = n / grp;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-       p += (long long)gridDim.x * blockDim.x) {
-    const long long gp = p / grp;
-    order[p] = (int32_t)((long long)(((unsigned long long)gp * g) % (unsigned long long)ng) * grp +
-                         (p - gp * grp));
-  }
+       p += (long long)gridDim.x * blockDim.x)
+    order[p] = (int32_t)dispersed_task(p, g, grp, ng);
 }
 
 // Placement, one thread per inference row r: a task (na == 1) or a

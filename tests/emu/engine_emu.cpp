@@ -8,6 +8,7 @@
 
 #include "../../paper_2501_03322_amd/csrc/twk_fs.h"
 #include "../../paper_2501_03322_amd/csrc/twk_gelu.h"
+#include "../../paper_2501_03322_amd/csrc/twk_queue.h"
 
 using namespace twk;
 
@@ -84,6 +85,13 @@ void run_wave(const Task& T, double tol, bool mixed, int n0, FsOut* out) {
 }  // namespace
 
 extern "C" {
+
+// The contour queue's dispersal arithmetic (twk_queue.h), as the kernels
+// use it.
+void emu_golden_stride(long long n, long long* g, long long* ginv) { golden_stride(n, g, ginv); }
+long long emu_dispersed_task(long long p, unsigned long long g, long long grp, long long ng) {
+  return dispersed_task(p, g, grp, ng);
+}
 
 // Centre roots by the device cold-start solve, then the contour engine
 // starting from a uniform grid of n0 samples (a multiple of 64, at most the
