@@ -710,17 +710,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TWK_FS_WAVES
   // registers and no function is called (a call made the compiler spill
   // the round loop's registers to scratch memory).
   bool drained = false;
+  // A wave takes its next queue position while the current source runs
+  // (the atomic's latency then overlaps the work; measured 0.8 % on the
+  // limb-darkened batch).  Every position a wave takes below n is run by
+  // it, and a wave leaves when the position it takes is n or beyond.
+  long long t_next = 0;
+  if (lane == 0) t_next = atomicAdd((unsigned long long*)head, 1ull);
   while (!drained) {
     long long big = -1;  // the source that outgrew its LDS copy, if any
     FsState st;
     for (;;) {
-      long long t = 0;
-      if (lane == 0) t = atomicAdd((unsigned long long*)head, 1ull);
-      t = __shfl(t, 0);
+      long long t = __shfl(t_next, 0);
       if (t >= n) {
         drained = true;
         break;
       }
+      if (lane == 0) t_next = atomicAdd((unsigned long long*)head, 1ull);
       if (order) t = order[t];
       const Task task = tasks[t];
       st = fs_fresh();
