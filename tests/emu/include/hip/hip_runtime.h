@@ -132,6 +132,9 @@ inline void run_wave(void (*fn)(int, void*), void* ctx) {
 inline void __syncthreads() { hip_emu::yield(); }
 // The emulated lanes are fibers: a wave barrier is a rendezvous too.
 inline void __builtin_amdgcn_wave_barrier() { hip_emu::yield(); }
+// Memory fences order nothing here: the fibers of a wave share one address
+// space and run one at a time.
+#define __builtin_amdgcn_fence(order, scope) ((void)0)
 
 template <class T>
 inline T __hip_emu_exchange(T v, int src) {
