@@ -68,7 +68,7 @@ enum {
   C_DINV = 26,     // learned path: inverse strides of classes 0 and 1 (26, 27)
   C_NCOUNTERS = 32
 };
-constexpr int NBUCKET = 2;  // predicted under 256 samples / 256 or more
+constexpr int NBUCKET = 2;  // predicted under 512 samples / 512 or more
 
 // Point-source adequacy test.  The paper (Sec. 2.3) applies the quadrupole
 // test and the ghost-image test before any contour work but gives no
@@ -558,17 +558,19 @@ __global__ __launch_bounds__(256) void k_feat(int64_t nsets, const double* ps, c
 }
 
 // Learned budget: a queued task is in class 1 when its predicted log2
-// sample count l2 is LONG_L2 or more (256 samples or more), else in class
+// sample count l2 is LONG_L2 or more (512 samples or more), else in class
 // 0; class 1 runs first and class 0 after it, each class in the dispersed
 // order below.  Long contours started last would hold their waves after
-// the rest of the launch has finished; only they are moved (measured on the
-// limb-darkened batch: ordering every contour longest first made the
-// contour kernel slower than no ordering at all; this order makes it 0.7 %
-// faster than the dispersed order alone).  The prediction does not change
+// the rest of the launch has finished; only they are moved.  Measured on
+// the limb-darkened batch: ordering every contour longest first made the
+// contour kernel slower than no ordering at all; at eight waves per CU a
+// threshold of 256 samples made it 0.7 % slower than the dispersed order
+// alone (too many expensive contours starting together), 512 and 1024
+// match it (at seven waves 256 was 0.7 % faster).  The prediction does not change
 // how a contour is sampled: every contour starts from the paper's 64
 // uniform samples.  The inference kernel counts the class-1 tasks into
 // cnt[C_BUCKET + 1]; class 0 starts right after them.
-constexpr float LONG_L2 = 8.0f;
+constexpr float LONG_L2 = 9.0f;
 static_assert(NBUCKET == 2, "two budget classes: the inference kernel counts class 1");
 
 // Queue dispersal.  The point pass queues contours in source order, so the

@@ -10,8 +10,8 @@ contour: log2 of the limb samples it used, and whether the point value
 misses the tolerance (|mu_ps / mu_FS - 1| > tol).  Training: minibatch
 Adam on the device (twk_mlp_train).  Evaluation on 128 sets of the seed-3
 batch and 128 sets of a seed-6 batch over the high-cadence ranges,
-including how often the queue's long class (256 samples or more) is
-predicted right.  Writes weights/mlp_budget.bin and a JSON record beside
+including how often the contours that need 256 samples or more are
+predicted so.  Writes weights/mlp_budget.bin and a JSON record beside
 it.
 
     python -m paper_2501_03322_amd.train_mlp [--epochs 8] [--out PATH]
