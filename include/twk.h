@@ -125,8 +125,8 @@ int twk_coefficients(twk_ctx *ctx, double s, double q, int64_t n, const double *
  * (a golden-ratio stride over the queue, a limb-darkened epoch's annuli
  * together) rather than in source order.  With TWK_MODE_MLP the learned
  * budget (weights from twk_mlp_set/load/train) predicts each contour's
- * sample count and the queue runs the contours predicted to need 512
- * samples or more first (launch tails), each class dispersed; the sampling
+ * sample count and the contours predicted to need 256 samples or more
+ * are spread over the first half of the queue (launch tails); the sampling
  * of a contour is unchanged (it starts from the 64 uniform samples of the
  * paper's schedule), so the results are bit-identical to those of the same
  * call without TWK_MODE_MLP.

@@ -68,7 +68,7 @@ enum {
   C_DINV = 26,     // learned path: inverse strides of classes 0 and 1 (26, 27)
   C_NCOUNTERS = 32
 };
-constexpr int NBUCKET = 2;  // predicted under 512 samples / 512 or more
+constexpr int NBUCKET = 2;  // predicted under 256 samples / 256 or more
 
 // Point-source adequacy test.  The paper (Sec. 2.3) applies the quadrupole
 // test and the ghost-image test before any contour work but gives no
@@ -558,19 +558,19 @@ __global__ __launch_bounds__(256) void k_feat(int64_t nsets, const double* ps, c
 }
 
 // Learned budget: a queued task is in class 1 when its predicted log2
-// sample count l2 is LONG_L2 or more (512 samples or more), else in class
-// 0; class 1 runs first and class 0 after it, each class in the dispersed
-// order below.  Long contours started last would hold their waves after
-// the rest of the launch has finished; only they are moved.  Measured on
-// the limb-darkened batch: ordering every contour longest first made the
-// contour kernel slower than no ordering at all; at eight waves per CU a
-// threshold of 256 samples made it 0.7 % slower than the dispersed order
-// alone (too many expensive contours starting together), 512 and 1024
-// match it (at seven waves 256 was 0.7 % faster).  The prediction does not change
-// how a contour is sampled: every contour starts from the paper's 64
-// uniform samples.  The inference kernel counts the class-1 tasks into
-// cnt[C_BUCKET + 1]; class 0 starts right after them.
-constexpr float LONG_L2 = 9.0f;
+// sample count l2 is LONG_L2 or more (256 samples or more), else in class
+// 0.  Each class is dispersed (below) and the class-1 rows are spread
+// evenly over the first half of the queue, the class-0 rows filling the
+// rest (twk_queue.h): a long contour started late would hold its wave after
+// the rest of the launch has finished, and long contours started all at
+// once slow each other down.  Measured at eight waves per CU: on the
+// limb-darkened batch (five launches) as fast as the dispersed order alone
+// and 0.8 % faster than queuing class 1 first; on the uniform batch of
+// 1024 x 2000 epochs (one launch) 8 % faster than the dispersed order
+// alone.  The prediction does not change how a contour is sampled: every
+// contour starts from the paper's 64 uniform samples.  The inference
+// kernel counts the class-1 tasks into cnt[C_BUCKET + 1].
+constexpr float LONG_L2 = 8.0f;
 static_assert(NBUCKET == 2, "two budget classes: the inference kernel counts class 1");
 
 // Queue dispersal.  The point pass queues contours in source order, so the
@@ -585,15 +585,12 @@ static_assert(NBUCKET == 2, "two budget classes: the inference kernel counts cla
 // Measured on the limb-darkened batch: the contour kernel 6 % faster than
 // in source order (annuli dispersed one by one: 5 %).
 // The stride, its inverse and the position map are in twk_queue.h.
-#ifndef TWK_DISPERSE_GROUPED
-#define TWK_DISPERSE_GROUPED 1
-#endif
 // Dispersal strides of a chunk, one thread.  Without the learned order: one
 // stride over the queue's groups (k_disperse); with it: the inverse strides
 // of the two classes' rows for the placement.
 __global__ void k_stride(long long* cnt, int na, int learned) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int grp = TWK_DISPERSE_GROUPED ? na : 1;
+  const int grp = na;  // an epoch's annuli stay together
   long long g, gi;
   if (learned) {
     const long long rows = cnt[na > 1 ? C_NFS : C_NTASK], n1 = cnt[C_BUCKET + 1] / na;
@@ -622,10 +619,10 @@ __global__ __launch_bounds__(256) void k_disperse(const long long* cnt, int32_t*
 // Placement, one thread per inference row r: a task (na == 1) or a
 // limb-darkened epoch, whose na annulus tasks are slot[r] .. slot[r] + na - 1.
 // The class ranks are exact prefix counts (per-tile counts from the
-// inference kernel, segment sums from k_seg): the long row of rank a goes
-// to unit a * ginv1 mod N1 of class 1, any other row of rank b to unit
-// b * ginv0 mod N0 of class 0 (after all of class 1), so that queue
-// position p holds rank p * g mod N: class 1 first, each class dispersed.
+// inference kernel, segment sums from k_seg): the long row of rank a takes
+// the dispersed rank a * ginv1 mod N1 in class 1, any other row of rank b
+// the dispersed rank b * ginv0 mod N0 in class 0, and the two classes are
+// merged with class 1 spread over the first half of the queue.
 constexpr int PLACE_SEG = 256;  // 32-row tiles per segment of the prefix
 
 // Sum of v over a block of 256 threads (every thread gets it).
@@ -675,18 +672,12 @@ __global__ __launch_bounds__(256) void k_place(const long long* cnt, const float
     const long long c1 = cnt[C_BUCKET + 1];               // class-1 tasks
     const long long rank = lng ? a : r - a;                // row rank in its class
     const long long units = lng ? c1 : n * na - c1;        // tasks of the class
-    const long long base = lng ? 0 : c1;
     const unsigned long long gi = (unsigned long long)cnt[C_DINV + (lng ? 1 : 0)];
     const int32_t first = na > 1 ? slot[r] : (int32_t)r;
-    if (TWK_DISPERSE_GROUPED) {
-      const long long pos = base + (long long)(((unsigned long long)rank * gi) % (unsigned long long)(units / na)) * na;
-      for (int k = 0; k < na; ++k) order[pos + k] = first + k;
-    } else {
-      for (int k = 0; k < na; ++k) {
-        const unsigned long long u = (unsigned long long)(rank * na + k);
-        order[base + (long long)((u * gi) % (unsigned long long)units)] = first + k;
-      }
-    }
+    const long long n1 = c1 / na, n0 = n - n1;  // rows of the two classes
+    const long long q = (long long)(((unsigned long long)rank * gi) % (unsigned long long)(units / na));
+    const long long pos = (lng ? merged_place_long(q, n0, n1) : merged_place_other(q, n0, n1)) * na;
+    for (int k = 0; k < na; ++k) order[pos + k] = first + k;
   }
 }
 

@@ -92,6 +92,9 @@ void emu_golden_stride(long long n, long long* g, long long* ginv) { golden_stri
 long long emu_dispersed_task(long long p, unsigned long long g, long long grp, long long ng) {
   return dispersed_task(p, g, grp, ng);
 }
+long long emu_merged_place(int long_row, long long q, long long n0, long long n1) {
+  return long_row ? merged_place_long(q, n0, n1) : merged_place_other(q, n0, n1);
+}
 
 // Centre roots by the device cold-start solve, then the contour engine
 // starting from a uniform grid of n0 samples (a multiple of 64, at most the

@@ -97,3 +97,35 @@ def test_windows_sample_the_queue_evenly(q):
                 idx = np.sort((np.arange(start, start + w, dtype=np.int64) * g) % n)
                 gaps = np.diff(np.concatenate([idx, [idx[0] + n]]))
                 assert gaps.max() <= 3.0 * n / w, (n, w, start, gaps.max())
+
+
+@pytest.fixture(scope="module")
+def merged():
+    from emu import build_emu
+    lib = C.CDLL(build_emu.build())
+    ll = C.c_longlong
+    lib.emu_merged_place.argtypes = [C.c_int, ll, ll, ll]
+    lib.emu_merged_place.restype = ll
+    return lambda long_row, q, n0, n1: lib.emu_merged_place(1 if long_row else 0, q, n0, n1)
+
+
+@pytest.mark.parametrize("n0,n1", [(0, 5), (5, 0), (1, 1), (10, 3), (1000, 37), (7, 100),
+                                   (123457, 999), (50, 50), (3, 1000), (2 ** 20, 3001)])
+def test_merged_places_spread_the_long_class(merged, n0, n1):
+    """The learned order's merge of the two classes: the places form a
+    permutation of 0 .. n0+n1-1, each class keeps its dispersed order, and
+    the long rows lie evenly in the first half (the k-th long row after
+    about k n0 / (2 n1) other rows), checked against the keys' definition
+    with exact fractions."""
+    from fractions import Fraction
+    pl = np.array([merged(True, q, n0, n1) for q in range(n1)], dtype=np.int64)
+    po = np.array([merged(False, b, n0, n1) for b in range(n0)], dtype=np.int64)
+    assert np.array_equal(np.sort(np.concatenate([pl, po])), np.arange(n0 + n1))
+    assert np.all(np.diff(pl) > 0) and np.all(np.diff(po) > 0)
+    if n0 < 3000:  # brute force over the other class's keys
+        for q in range(0, n1, max(1, n1 // 50)):
+            key = Fraction(2 * q + 1, 4 * n1)
+            before = sum(1 for b in range(n0) if Fraction(2 * b + 1, 2 * n0) < key)
+            assert pl[q] == q + before, (q, pl[q], before)
+    if n1 and n0 > n1:
+        assert pl.max() <= n1 + n0 // 2 + 1
